@@ -1,0 +1,142 @@
+/*
+ * wt.h -- C ABI of libwt, the MI355X (gfx950) wavelet-transparency resolve.
+ *
+ * Method: M. Aizenshtein, N. Smal, M. McGuire, "Wavelet Transparency" (2021).
+ *   Build pass     (section 2.1 step 2; closed forms of section 2.3.1): every transparent fragment adds its
+ *                  Haar coefficients of absorbance a = -ln(1 - alpha) over normalised depth into a fixed-size
+ *                  per-pixel array, in any order.
+ *   Evaluate pass  (section 2.1 step 3; compositing sum of section 2.2; interpolation of section 2.3.2):
+ *                  visibility v = exp(-A~(x)) is reconstructed at each fragment's depth and the
+ *                  visibility-weighted colour alpha * rgb * v is accumulated, together with sum(a).
+ *   Resolve        (section 2.1 step 4): out = accumulated colour + background * exp(-sum(a)).
+ *
+ * Conventions shared by every entry point
+ *   - All pointers to per-frame data are DEVICE pointers (HIP device memory of the current device) unless a
+ *     parameter says "host". The library never allocates persistent memory and never frees caller memory;
+ *     scratch comes from a caller-provided device workspace sized by wt_workspace_bytes().
+ *   - Every call is asynchronous on the given HIP stream (0 = the null stream) and returns once the work is
+ *     enqueued. The return code reports host-side validation and launch failures only.
+ *   - Errors: WT_ERR_INVALID (null pointer, bad enum, zero size), WT_ERR_RANGE (size limits: rank > 10,
+ *     pixel count or fragment count >= 2^32, workspace too small), WT_ERR_HIP (a HIP runtime error; the HIP
+ *     error string is in wt_last_error()). Nothing is enqueued when validation fails.
+ *   - Device-side bad fragments are dropped, not faulted: a pixel id >= width*height, a NaN depth or a NaN
+ *     alpha. Their number is read back with wt_dropped_count(). Depth is clamped to [0, 1]; alpha to
+ *     [0, 1 - 2^-24].
+ *   - The library is stateless and re-entrant; calls that share a workspace must be ordered on one stream.
+ *
+ * Data layout (row-major, little endian)
+ *   fragments  structure of arrays, F = count entries:
+ *                pixel[F] uint32 = y * width + x;  depth[F] float;  alpha[F * channels] float
+ *                (channel-minor);  rgb[F * 3] float, straight (not premultiplied) colour.
+ *   coeffs     [P][channels][M] of the storage type (M = 2^(rank+1)); element m = 0 holds the scaling
+ *              coefficient chi_00, element m = 2^n + k holds 2^(n/2) X_{n,k} (level n = 0..rank).
+ *   accum      float [P][4] for channels = 1: (sum alpha r v, sum alpha g v, sum alpha b v, sum a);
+ *              float [P][8] for channels = 3: (sum alpha_r r v_r, .._g, .._b, 0, sum a_r, sum a_g, sum a_b, 0).
+ *   out        float [P][3] linear RGB, no clamp.
+ */
+#ifndef WT_H
+#define WT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  WT_OK = 0,
+  WT_ERR_INVALID = -1,
+  WT_ERR_RANGE = -2,
+  WT_ERR_NOMEM = -3,
+  WT_ERR_HIP = -4,
+  WT_ERR_UNSUPPORTED = -5
+} wt_status;
+
+/* Storage type of the coefficient array. Accumulation is always FP32 on chip; FP16 and BF16 round once,
+ * to nearest even, when a coefficient tile is stored, and widen exactly when it is loaded. */
+typedef enum { WT_F32 = 0, WT_F16 = 1, WT_BF16 = 2 } wt_dtype;
+
+typedef struct {
+  uint32_t width;       /* pixels per row, >= 1 */
+  uint32_t height;      /* rows, >= 1; width * height < 2^32 */
+  uint32_t rank;        /* N in 0..10: levels n = 0..N, M = 2^(N+1) coefficients per channel */
+  uint32_t channels;    /* 1 (one visibility for r, g, b) or 3 (per-channel transmittance) */
+  uint32_t coeff_dtype; /* wt_dtype */
+} wt_frame_desc;
+
+typedef struct {
+  uint64_t count;       /* F < 2^32 */
+  const uint32_t* pixel;
+  const float* depth;
+  const float* alpha;
+  const float* rgb;
+} wt_fragments;
+
+/* Bytes of device workspace needed for frames of this description with up to max_fragments fragments.
+ * Returns 0 for an invalid description. */
+size_t wt_workspace_bytes(const wt_frame_desc* desc, uint64_t max_fragments);
+
+/* Ingest and screen-tile binning (a device-side regrouping of the stream so that each pixel's fragments
+ * are processed on one compute unit; it stands in for the screen locality of a raster pipeline). Copies the
+ * stream into the workspace grouped by screen tile, dropping and counting bad fragments. The binned copy
+ * stays valid until the workspace is reused and serves any number of wt_*_binned calls with the same desc
+ * and ws_bytes. */
+wt_status wt_bin(const wt_frame_desc* desc, const wt_fragments* frags, void* ws, size_t ws_bytes,
+                 hipStream_t stream);
+
+/* Build pass over a binned stream (section 2.3.1): coeffs += the coefficients of every binned fragment.
+ * coeffs must hold P * channels * M elements of desc->coeff_dtype; the caller zeroes it before the first
+ * contribution of a frame. */
+wt_status wt_build_binned(const wt_frame_desc* desc, void* coeffs, const void* ws, size_t ws_bytes,
+                          hipStream_t stream);
+
+/* Evaluate pass over a binned stream (sections 2.2, 2.3.2): accum += the visibility-weighted colour and
+ * absorbance of every binned fragment, reconstructed from complete coefficients. */
+wt_status wt_evaluate_binned(const wt_frame_desc* desc, const void* coeffs, float* accum, const void* ws,
+                             size_t ws_bytes, hipStream_t stream);
+
+/* wt_bin followed by wt_build_binned. Calls accumulate, so a long stream can be built in chunks. */
+wt_status wt_build(const wt_frame_desc* desc, const wt_fragments* frags, void* coeffs, void* ws, size_t ws_bytes,
+                   hipStream_t stream);
+
+/* wt_bin followed by wt_evaluate_binned. */
+wt_status wt_evaluate(const wt_frame_desc* desc, const wt_fragments* frags, const void* coeffs, float* accum,
+                      void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Composite (section 2.1 step 4): out[p] = accum colour + bg * exp(-sum a); bg_rgb is a HOST array of 3. */
+wt_status wt_resolve(const wt_frame_desc* desc, const float* accum, const float* bg_rgb, float* out,
+                     hipStream_t stream);
+
+/* The whole path for one frame in one pass over the binned stream: bin, build, evaluate and resolve, with
+ * the per-pixel state held on chip. Writes out[P][3] (overwritten) and, if coeffs is not NULL, the frame's
+ * coefficients (overwritten). The evaluation sees the coefficients at storage precision, exactly as a
+ * build/evaluate pair through a stored coefficient array would. bg_rgb is a HOST array of 3. */
+wt_status wt_render(const wt_frame_desc* desc, const wt_fragments* frags, const float* bg_rgb, void* coeffs,
+                    float* out, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Gradient of a scalar loss through wt_render with respect to alpha and colour. grad_out is dL/dout
+ * [P][3]; coeffs are the frame's complete coefficients and accum its accumulation (as written by wt_build
+ * and wt_evaluate, or recomputed). Writes grad_alpha[F * channels] and grad_rgb[F * 3] (overwritten, in
+ * stream order). Depth is not differentiated (A~ has kinks on the subdivision grid). The clamp of alpha has
+ * zero slope outside (0, 1 - 2^-24); dropped fragments get zero gradients. bg_rgb is a HOST array of 3. */
+wt_status wt_backward(const wt_frame_desc* desc, const wt_fragments* frags, const void* coeffs, const float* accum,
+                      const float* bg_rgb, const float* grad_out, float* grad_alpha, float* grad_rgb, void* ws,
+                      size_t ws_bytes, hipStream_t stream);
+
+/* Number of fragments dropped by the last binning in this workspace. Synchronises the given stream. */
+wt_status wt_dropped_count(const void* ws, size_t ws_bytes, uint64_t* count, hipStream_t stream);
+
+/* Thread-local message describing the last non-OK status returned on this thread ("" if none). */
+const char* wt_last_error(void);
+
+/* ABI version of this header: increments on any incompatible change. */
+int wt_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WT_H */

@@ -49,7 +49,7 @@ def _load():
     vp = C.c_void_p
     lib.orc_resolve.restype = C.c_int
     lib.orc_resolve.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64, vp, vp, vp, vp, vp, vp,
-                                vp, vp, vp, vp, vp, vp, vp, C.c_int]
+                                C.c_int, vp, vp, vp, vp, vp, vp, vp, C.c_int]
     lib.orc_abuffer.restype = C.c_int
     lib.orc_abuffer.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64, vp, vp, vp, vp, vp, vp, C.c_int, vp, vp,
                                 vp, C.c_int]
@@ -70,6 +70,8 @@ def _load():
     lib.orc_absorbance.argtypes = [C.c_double]
     lib.orc_alpha_used.restype = C.c_double
     lib.orc_alpha_used.argtypes = [C.c_double]
+    lib.orc_round_storage.restype = C.c_double
+    lib.orc_round_storage.argtypes = [C.c_double, C.c_int]
     lib.orc_num_threads.restype = C.c_int
     lib.orc_num_threads.argtypes = []
     _lib = lib
@@ -95,9 +97,13 @@ def num_threads() -> int:
     return int(_load().orc_num_threads())
 
 
+STORAGE = {"exact": 0, "f32": 0, "f16": 1, "bf16": 2}
+
+
 def resolve(width, height, rank, pixel, depth, alpha, rgb, bg=(0.0, 0.0, 0.0), channels=1, mask=None,
-            want=("coeffs", "cells", "accum", "suma", "out", "vis"), threads=0):
-    """FP64 wavelet resolve of one frame. Returns a dict with the requested arrays:
+            want=("coeffs", "cells", "accum", "suma", "out", "vis"), threads=0, storage="exact"):
+    """FP64 wavelet resolve of one frame. ``storage`` ("exact", "f16", "bf16") rounds the coefficients to that
+    format before they are used. Returns a dict with the requested arrays:
 
     ``coeffs``/``cells`` [P, C, M]; ``accum`` [P, 3]; ``suma`` [P, C]; ``out`` [P, 3]; ``vis`` [F, C]; and
     ``dropped`` (int). ``mask`` (bool [P]) restricts the computed pixels; the rest read as zeros (NaN in vis).
@@ -117,8 +123,8 @@ def resolve(width, height, rank, pixel, depth, alpha, rgb, bg=(0.0, 0.0, 0.0), c
     bgv = np.ascontiguousarray(bg, dtype=np.float64)
     dropped = C.c_uint64(0)
     rc = lib.orc_resolve(width, height, rank, channels, F, _ptr(pixel), _ptr(depth), _ptr(alpha), _ptr(rgb), _ptr(bgv),
-                         _ptr(m), _ptr(res["coeffs"]), _ptr(res["cells"]), _ptr(res["accum"]), _ptr(res["suma"]),
-                         _ptr(res["out"]), _ptr(res["vis"]), C.byref(dropped), int(threads))
+                         _ptr(m), STORAGE[storage], _ptr(res["coeffs"]), _ptr(res["cells"]), _ptr(res["accum"]),
+                         _ptr(res["suma"]), _ptr(res["out"]), _ptr(res["vis"]), C.byref(dropped), int(threads))
     if rc != 0:
         raise RuntimeError("orc_resolve failed with %d" % rc)
     out = {k: v for k, v in res.items() if v is not None}
@@ -200,6 +206,10 @@ def psi(n, k, z):
 
 def absorbance(alpha):
     return float(_load().orc_absorbance(float(alpha)))
+
+
+def round_storage(v, storage):
+    return float(_load().orc_round_storage(float(v), STORAGE[storage]))
 
 
 def alpha_used(alpha):

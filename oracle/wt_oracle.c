@@ -96,6 +96,29 @@ double orc_psi(int n, int k, double z) {
   return 0.0;
 }
 
+/* Round to a binary format with `mbits` fraction bits and minimum normal exponent `emin`, to nearest with
+ * ties to even (IEEE 754 roundTiesToEven). mbits = 10, emin = -14, emax = 15: binary16 (FP16);
+ * mbits = 7, emin = -126, emax = 127: bfloat16. Values beyond the largest finite number become infinite. */
+static double round_format(double v, int mbits, int emin, int emax) {
+  if (v == 0.0 || isnan(v) || isinf(v)) return v;
+  int e;
+  frexp(fabs(v), &e); /* |v| = f 2^e, f in [0.5, 1): exponent of the leading bit is e - 1 */
+  int lead = e - 1;
+  if (lead < emin) lead = emin; /* subnormal range: fixed spacing */
+  double ulp = ldexp(1.0, lead - mbits);
+  double r = nearbyint(v / ulp) * ulp; /* default rounding mode: to nearest, ties to even */
+  double maxfin = ldexp(2.0 - ldexp(1.0, -mbits), emax);
+  if (fabs(r) > maxfin) return v > 0 ? INFINITY : -INFINITY;
+  return r;
+}
+
+/* Coefficient storage precision: 0 = exact (FP64 here), 1 = FP16, 2 = BF16. */
+double orc_round_storage(double v, int storage) {
+  if (storage == 1) return round_format(v, 10, -14, 15);
+  if (storage == 2) return round_format(v, 7, -126, 127);
+  return v;
+}
+
 /* ------------------------------------------------------------------------------------------------ */
 /* One pixel, one channel: coefficients, cell averages, reconstruction                              */
 /* ------------------------------------------------------------------------------------------------ */
@@ -244,13 +267,15 @@ static uint64_t max_run(const uint64_t* start, uint64_t P) {
  *   suma   [P][C]     sum_i a_{i,c}                                      (may be NULL)
  *   out    [P][3]     S_q + bg_q exp(-suma_{c(q)})                        (may be NULL)
  *   vis    [F][C]     v_{i,c} = exp(-A~_c(x_i)); NaN for dropped fragments (may be NULL)
- * with c(q) = q when C = 3 and 0 when C = 1. mask (uint8 [P], may be NULL) restricts the pixels computed;
+ * with c(q) = q when C = 3 and 0 when C = 1. storage != 0 rounds every coefficient to FP16 (1) or BF16 (2)
+ * before the cell averages are formed (the method with coefficients kept at that precision).
+ * mask (uint8 [P], may be NULL) restricts the pixels computed;
  * outputs of unmasked pixels are left untouched. threads <= 0 keeps the OpenMP default.
  */
 int orc_resolve(uint32_t width, uint32_t height, uint32_t rank, uint32_t channels, uint64_t count,
                 const uint32_t* pixel, const float* depth, const float* alpha, const float* rgb, const double* bg,
-                const uint8_t* mask, double* coeffs, double* cells, double* accum, double* suma, double* out,
-                double* vis, uint64_t* dropped, int threads) {
+                const uint8_t* mask, int storage, double* coeffs, double* cells, double* accum, double* suma,
+                double* out, double* vis, uint64_t* dropped, int threads) {
   if (rank > 12 || (channels != 1 && channels != 3) || (count && (!pixel || !depth || !alpha || !rgb)) || !bg)
     return ORC_EINVAL;
   orc_stream s = {width, height, rank, channels, count, pixel, depth, alpha, rgb};
@@ -299,6 +324,7 @@ int orc_resolve(uint32_t width, uint32_t height, uint32_t rank, uint32_t channel
             as[r] = orc_absorbance(alpha[(uint64_t)i * C + c]);
           }
           orc_coeffs_one((int)rank, (int)k, xs, as, cf);
+          for (int m = 0; m < M; ++m) cf[m] = orc_round_storage(cf[m], storage);
           orc_cells_one((int)rank, cf, ce);
           if (coeffs) memcpy(coeffs + ((uint64_t)p * C + c) * M, cf, sizeof(double) * M);
           if (cells) memcpy(cells + ((uint64_t)p * C + c) * M, ce, sizeof(double) * M);

@@ -1,0 +1,10 @@
+"""MI355X-native wavelet-transparency resolve (Wavelet Transparency, Aizenshtein, Smal, McGuire 2021).
+
+The compute lives in ``libwt.so`` (HIP kernels for gfx950 behind the C ABI of ``include/wt.h``); this package
+marshals torch tensors into it. Importing it does not load the library; the first call does, and fails loudly
+if the library has not been built.
+"""
+from ._lib import WTError, load as load_library  # noqa: F401
+from .wt import (FrameSpec, Fragments, Workspace, backward, bin, build, build_binned, dropped_count,  # noqa: F401
+                 evaluate, evaluate_binned, render, resolve, workspace_bytes)
+from .autograd import WaveletComposite, composite  # noqa: F401

@@ -1,0 +1,197 @@
+// C ABI of libwt: argument validation, workspace layout and the order of kernel launches. Every call only
+// enqueues work on the caller's stream; nothing here allocates device memory.
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <string>
+
+#include "wt_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+wt_status fail(wt_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+wt_status hip_fail(hipError_t e, const char* where) {
+  return fail(WT_ERR_HIP, "%s: HIP error %d (%s)", where, (int)e, hipGetErrorString(e));
+}
+
+wt_status check_desc(const wt_frame_desc* d) {
+  if (!d) return fail(WT_ERR_INVALID, "desc is NULL");
+  if (d->width == 0 || d->height == 0) return fail(WT_ERR_INVALID, "frame size %ux%u is empty", d->width, d->height);
+  if ((uint64_t)d->width * d->height >= (1ull << 32))
+    return fail(WT_ERR_RANGE, "frame %ux%u has 2^32 or more pixels", d->width, d->height);
+  if (d->rank > 10) return fail(WT_ERR_RANGE, "rank %u exceeds 10", d->rank);
+  if (d->channels != 1 && d->channels != 3) return fail(WT_ERR_INVALID, "channels must be 1 or 3, got %u", d->channels);
+  if (d->coeff_dtype > WT_BF16) return fail(WT_ERR_INVALID, "unknown coefficient dtype %u", d->coeff_dtype);
+  return WT_OK;
+}
+
+wt_status check_frags(const wt_fragments* f) {
+  if (!f) return fail(WT_ERR_INVALID, "frags is NULL");
+  if (f->count >= (1ull << 32)) return fail(WT_ERR_RANGE, "fragment count %llu is 2^32 or more",
+                                            (unsigned long long)f->count);
+  if (f->count && (!f->pixel || !f->depth || !f->alpha || !f->rgb))
+    return fail(WT_ERR_INVALID, "a fragment array pointer is NULL");
+  return WT_OK;
+}
+
+wt_status check_ws(const wt::Geom& g, const void* ws, size_t ws_bytes, uint64_t need_cap, wt::Layout* l) {
+  if (!ws) return fail(WT_ERR_INVALID, "workspace is NULL");
+  const uint64_t cap = wt::capacity_for(g, ws_bytes);
+  if (cap < need_cap || ws_bytes < wt::make_layout(g, 0).total)
+    return fail(WT_ERR_RANGE, "workspace of %zu bytes holds %llu fragments, %llu needed (wt_workspace_bytes)", ws_bytes,
+                (unsigned long long)cap, (unsigned long long)need_cap);
+  *l = wt::make_layout(g, cap);
+  return WT_OK;
+}
+
+wt_status check_lds(const wt::Geom& g) {
+  if (wt::lds_tile_bytes(g, true) > wt::kLdsBytes)
+    return fail(WT_ERR_UNSUPPORTED, "tile of %u pixels needs %zu bytes of LDS", g.tile_px, wt::lds_tile_bytes(g, true));
+  return WT_OK;
+}
+
+#define WT_TRY(expr)                 \
+  do {                               \
+    wt_status st_ = (expr);          \
+    if (st_ != WT_OK) return st_;    \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+int wt_abi_version(void) { return 1; }
+
+const char* wt_last_error(void) { return g_last_error.c_str(); }
+
+size_t wt_workspace_bytes(const wt_frame_desc* desc, uint64_t max_fragments) {
+  if (check_desc(desc) != WT_OK || max_fragments >= (1ull << 32)) return 0;
+  // the gradient uses smaller tiles (more tile-table entries), so size for whichever layout is larger
+  const size_t fwd = wt::make_layout(wt::make_geom(*desc), max_fragments).total;
+  const size_t bwd = wt::make_layout(wt::make_geom(*desc, true), max_fragments).total;
+  return fwd > bwd ? fwd : bwd;
+}
+
+wt_status wt_bin(const wt_frame_desc* desc, const wt_fragments* frags, void* ws, size_t ws_bytes, hipStream_t stream) {
+  WT_TRY(check_desc(desc));
+  WT_TRY(check_frags(frags));
+  const wt::Geom g = wt::make_geom(*desc);
+  WT_TRY(check_lds(g));
+  wt::Layout l;
+  WT_TRY(check_ws(g, ws, ws_bytes, frags->count, &l));
+  hipError_t e = wt::launch_bin(g, *frags, ws, l, false, stream);
+  if (e != hipSuccess) return hip_fail(e, "wt_bin");
+  return WT_OK;
+}
+
+wt_status wt_build_binned(const wt_frame_desc* desc, void* coeffs, const void* ws, size_t ws_bytes,
+                          hipStream_t stream) {
+  WT_TRY(check_desc(desc));
+  if (!coeffs) return fail(WT_ERR_INVALID, "coeffs is NULL");
+  const wt::Geom g = wt::make_geom(*desc);
+  WT_TRY(check_lds(g));
+  wt::Layout l;
+  WT_TRY(check_ws(g, ws, ws_bytes, 0, &l));
+  hipError_t e = wt::launch_build(g, wt::binned_view(g, l, ws), coeffs, stream);
+  if (e != hipSuccess) return hip_fail(e, "wt_build");
+  return WT_OK;
+}
+
+wt_status wt_evaluate_binned(const wt_frame_desc* desc, const void* coeffs, float* accum, const void* ws,
+                             size_t ws_bytes, hipStream_t stream) {
+  WT_TRY(check_desc(desc));
+  if (!coeffs || !accum) return fail(WT_ERR_INVALID, "coeffs or accum is NULL");
+  const wt::Geom g = wt::make_geom(*desc);
+  WT_TRY(check_lds(g));
+  wt::Layout l;
+  WT_TRY(check_ws(g, ws, ws_bytes, 0, &l));
+  hipError_t e = wt::launch_evaluate(g, wt::binned_view(g, l, ws), coeffs, accum, stream);
+  if (e != hipSuccess) return hip_fail(e, "wt_evaluate");
+  return WT_OK;
+}
+
+wt_status wt_build(const wt_frame_desc* desc, const wt_fragments* frags, void* coeffs, void* ws, size_t ws_bytes,
+                   hipStream_t stream) {
+  if (!coeffs) return fail(WT_ERR_INVALID, "coeffs is NULL");
+  WT_TRY(wt_bin(desc, frags, ws, ws_bytes, stream));
+  return wt_build_binned(desc, coeffs, ws, ws_bytes, stream);
+}
+
+wt_status wt_evaluate(const wt_frame_desc* desc, const wt_fragments* frags, const void* coeffs, float* accum,
+                      void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!coeffs || !accum) return fail(WT_ERR_INVALID, "coeffs or accum is NULL");
+  WT_TRY(wt_bin(desc, frags, ws, ws_bytes, stream));
+  return wt_evaluate_binned(desc, coeffs, accum, ws, ws_bytes, stream);
+}
+
+wt_status wt_resolve(const wt_frame_desc* desc, const float* accum, const float* bg_rgb, float* out,
+                     hipStream_t stream) {
+  WT_TRY(check_desc(desc));
+  if (!accum || !bg_rgb || !out) return fail(WT_ERR_INVALID, "accum, bg_rgb or out is NULL");
+  const wt::Geom g = wt::make_geom(*desc);
+  hipError_t e = wt::launch_resolve(g, accum, bg_rgb, out, stream);
+  if (e != hipSuccess) return hip_fail(e, "wt_resolve");
+  return WT_OK;
+}
+
+wt_status wt_render(const wt_frame_desc* desc, const wt_fragments* frags, const float* bg_rgb, void* coeffs,
+                    float* out, void* ws, size_t ws_bytes, hipStream_t stream) {
+  WT_TRY(check_desc(desc));
+  WT_TRY(check_frags(frags));
+  if (!bg_rgb || !out) return fail(WT_ERR_INVALID, "bg_rgb or out is NULL");
+  const wt::Geom g = wt::make_geom(*desc);
+  WT_TRY(check_lds(g));
+  wt::Layout l;
+  WT_TRY(check_ws(g, ws, ws_bytes, frags->count, &l));
+  hipError_t e = wt::launch_bin(g, *frags, ws, l, false, stream);
+  if (e != hipSuccess) return hip_fail(e, "wt_render (bin)");
+  e = wt::launch_render(g, wt::binned_view(g, l, ws), bg_rgb, coeffs, out, stream);
+  if (e != hipSuccess) return hip_fail(e, "wt_render");
+  return WT_OK;
+}
+
+wt_status wt_backward(const wt_frame_desc* desc, const wt_fragments* frags, const void* coeffs, const float* accum,
+                      const float* bg_rgb, const float* grad_out, float* grad_alpha, float* grad_rgb, void* ws,
+                      size_t ws_bytes, hipStream_t stream) {
+  WT_TRY(check_desc(desc));
+  WT_TRY(check_frags(frags));
+  if (!coeffs || !accum || !bg_rgb || !grad_out || (frags->count && (!grad_alpha || !grad_rgb)))
+    return fail(WT_ERR_INVALID, "a backward array pointer is NULL");
+  const wt::Geom g = wt::make_geom(*desc, true);
+  if (wt::lds_backward_bytes(g) > wt::kLdsBytes)
+    return fail(WT_ERR_UNSUPPORTED, "gradient tile of %u pixels needs %zu bytes of LDS", g.tile_px,
+                wt::lds_backward_bytes(g));
+  wt::Layout l;
+  WT_TRY(check_ws(g, ws, ws_bytes, frags->count, &l));
+  hipError_t e = wt::launch_bin(g, *frags, ws, l, true, stream);
+  if (e != hipSuccess) return hip_fail(e, "wt_backward (bin)");
+  e = wt::launch_backward(g, wt::binned_view(g, l, ws), coeffs, accum, bg_rgb, grad_out, grad_alpha, grad_rgb,
+                          frags->count, stream);
+  if (e == hipErrorNotSupported) return fail(WT_ERR_UNSUPPORTED, "wt_backward: not available for this frame");
+  if (e != hipSuccess) return hip_fail(e, "wt_backward");
+  return WT_OK;
+}
+
+wt_status wt_dropped_count(const void* ws, size_t ws_bytes, uint64_t* count, hipStream_t stream) {
+  if (!ws || !count) return fail(WT_ERR_INVALID, "ws or count is NULL");
+  if (ws_bytes < 256) return fail(WT_ERR_RANGE, "workspace of %zu bytes has no header", ws_bytes);
+  unsigned long long v = 0;
+  hipError_t e = hipMemcpyAsync(&v, ws, sizeof v, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(e, "wt_dropped_count");
+  *count = v;
+  return WT_OK;
+}
+
+}  // extern "C"

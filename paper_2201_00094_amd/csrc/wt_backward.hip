@@ -1,0 +1,253 @@
+// Gradient of the resolve with respect to alpha and colour, one workgroup per screen tile.
+//
+// Forward, per pixel and visibility channel c (colour channels q with c(q) = c):
+//   out_q = sum_i alpha_i c_{i,q} v_i + bg_q exp(-sum_i a_i),  v_i = exp(-A~(x_i)),  a_i = -ln(1 - alpha_i),
+//   A~(z) = (1 - t) Abar_{j-1} + t Abar_j  (u = M z, j = min(floor(u), M-1), t = u - j).
+// With g = dL/dout:
+//   dL/dc_{i,q}  = g_q alpha_i v_i
+//   dL/dA~(x_i)  = -s_i,  s_i = alpha_i v_i sum_q g_q c_{i,q}
+//   cell adjoint  Abar'_m = sum_i -s_i dA~(x_i)/dAbar_m   (two cells per fragment: (1 - t), t)
+//   dL/da_i      = sum_m Abar'_m dAbar_m/da_i - exp(-sum a) sum_q g_q bg_q
+//   dL/dalpha_i  = v_i sum_q g_q c_{i,q} + dL/da_i / (1 - alpha_i)
+// The map a_i -> Abar_m is the build (section 2.3.1) followed by the Haar synthesis; composed, it is the
+// average of the fragment's step over cell m, dAbar_m/da_i = clamp((m + 1) - M x_i, 0, 1). Its adjoint is
+// therefore a suffix sum of the cell adjoints: with S_m = sum_{m' >= m} Abar'_{m'} and j = floor(M x_i),
+//   sum_m Abar'_m dAbar_m/da_i = (j + 1 - M x_i) Abar'_j + S_{j+1},
+// which needs O(M) work per pixel and O(1) per fragment for any rank.
+#include <algorithm>
+
+#include "wt_common.h"
+
+namespace wt {
+
+constexpr int kBwdThreads = 512;
+
+__device__ __forceinline__ float clamp01_b(float x) { return fminf(fmaxf(x, 0.f), 1.f); }
+
+__device__ __forceinline__ float cell_value(const float* cf, const Geom& g, uint32_t j, bool cells) {
+  if (cells) return cf[j];
+  float A = cf[0];
+  for (uint32_t n = 0; n <= g.rank; ++n) {
+    const uint32_t k = j >> (g.L - n);
+    const float d = cf[(1u << n) + k];
+    A += ((j >> (g.L - 1 - n)) & 1u) ? -d : d;
+  }
+  return A;
+}
+
+template <int M>
+__device__ __forceinline__ void synth_fixed_b(float* cf) {
+  float v[M];
+  v[0] = cf[0];
+#pragma unroll
+  for (int s = 1; s < M; s <<= 1) {
+#pragma unroll
+    for (int k = s - 1; k >= 0; --k) {
+      const float d = cf[s + k];
+      const float a = v[k];
+      v[2 * k] = a + d;
+      v[2 * k + 1] = a - d;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < M; ++j) cf[j] = v[j];
+}
+
+__device__ __forceinline__ void synth_b(float* cf, uint32_t M) {
+  switch (M) {
+    case 2: synth_fixed_b<2>(cf); break;
+    case 4: synth_fixed_b<4>(cf); break;
+    case 8: synth_fixed_b<8>(cf); break;
+    case 16: synth_fixed_b<16>(cf); break;
+    default: synth_fixed_b<32>(cf); break;
+  }
+}
+
+__global__ void k_zero_f32(float* __restrict__ p, uint64_t n) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = 0.f;
+}
+
+template <int C, typename TS, bool CELLS>
+__global__ __launch_bounds__(kBwdThreads) void k_backward(Binned b, Geom g, const TS* __restrict__ coeffs,
+                                                          const float* __restrict__ accum, float bg0, float bg1,
+                                                          float bg2, const float* __restrict__ grad_out,
+                                                          float* __restrict__ grad_alpha,
+                                                          float* __restrict__ grad_rgb) {
+  extern __shared__ float smem[];
+  const uint32_t per = C * g.M, nel = g.tile_px * per;
+  float* lc = smem;             // cell values [tile_px][C][M]
+  float* ladj = lc + nel;       // cell adjoints, then their suffix sums
+  float* lg = ladj + nel;       // dL/dout [tile_px][3]
+  float* lT = lg + g.tile_px * 3;  // background transmittance [tile_px][C]
+  const uint32_t t = blockIdx.x;
+  const uint32_t x0 = (t % g.tilesX) * g.TW, y0 = (t / g.tilesX) * g.TH;
+  for (uint32_t e = threadIdx.x; e < nel; e += blockDim.x) {
+    const uint32_t lp = e / per, rem = e - lp * per;
+    const uint32_t px = x0 + (lp & (g.TW - 1)), py = y0 + lp / g.TW;
+    const bool in = px < g.W && py < g.H;
+    lc[e] = in ? widen<TS>(coeffs[((uint64_t)py * g.W + px) * per + rem]) : 0.f;
+    ladj[e] = 0.f;
+  }
+  for (uint32_t e = threadIdx.x; e < g.tile_px * 3; e += blockDim.x) {
+    const uint32_t lp = e / 3, q = e - lp * 3;
+    const uint32_t px = x0 + (lp & (g.TW - 1)), py = y0 + lp / g.TW;
+    lg[e] = (px < g.W && py < g.H) ? grad_out[((uint64_t)py * g.W + px) * 3 + q] : 0.f;
+  }
+  for (uint32_t e = threadIdx.x; e < g.tile_px * C; e += blockDim.x) {
+    const uint32_t lp = e / C, c = e - lp * C;
+    const uint32_t px = x0 + (lp & (g.TW - 1)), py = y0 + lp / g.TW;
+    float T = 0.f;
+    if (px < g.W && py < g.H) {
+      const uint64_t p = (uint64_t)py * g.W + px;
+      T = __expf(-accum[p * g.AW + (C == 1 ? 3 : 4 + c)]);
+    }
+    lT[e] = T;
+  }
+  __syncthreads();
+  if (CELLS)
+    for (uint32_t q = threadIdx.x; q < g.tile_px * C; q += blockDim.x) synth_b(lc + q * g.M, g.M);
+  __syncthreads();
+  const uint32_t beg = b.offsets[t * g.NX], end = b.offsets[(t + 1) * g.NX];
+  // pass 1: cell adjoints
+  for (uint32_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    const uint32_t lp = b.lpx[i];
+    float x = b.x[i];
+    float al[C];
+    bool bad = isnan(x);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      al[c] = b.alpha[c * b.cap + i];
+      bad |= isnan(al[c]);
+    }
+    if (bad) continue;
+    float rgb[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) rgb[q] = b.rgb[q * b.cap + i];
+    x = clamp01_b(x);
+    const float u = x * (float)g.M;
+    const uint32_t j = min((uint32_t)u, g.M - 1);
+    const float tt = u - (float)j;
+    const float* gp = lg + lp * 3;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const float* cf = lc + (lp * C + c) * g.M;
+      const float hi = cell_value(cf, g, j, CELLS);
+      const float lo = j ? cell_value(cf, g, j - 1, CELLS) : 0.f;
+      const float v = __expf(-fmaf(tt, hi, (1.f - tt) * lo));
+      const float alc = alpha_clamped(al[c]);
+      const float gc = (C == 1) ? (gp[0] * rgb[0] + gp[1] * rgb[1] + gp[2] * rgb[2]) : gp[c] * rgb[c];
+      const float s = alc * v * gc;
+      float* adj = ladj + (lp * C + c) * g.M;
+      if (j) atomicAdd(adj + j - 1, -s * (1.f - tt));
+      atomicAdd(adj + j, -s * tt);
+    }
+  }
+  __syncthreads();
+  // suffix sums of the cell adjoints
+  for (uint32_t q = threadIdx.x; q < g.tile_px * C; q += blockDim.x) {
+    float* adj = ladj + q * g.M;
+    float run = 0.f;
+    for (int m = (int)g.M - 1; m >= 0; --m) {
+      run += adj[m];
+      adj[m] = run;
+    }
+  }
+  __syncthreads();
+  // pass 2: per-fragment gradients, written at the fragment's stream position
+  const float bg[3] = {bg0, bg1, bg2};
+  for (uint32_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    const uint32_t lp = b.lpx[i];
+    float x = b.x[i];
+    float al[C];
+    bool bad = isnan(x);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      al[c] = b.alpha[c * b.cap + i];
+      bad |= isnan(al[c]);
+    }
+    if (bad) continue;
+    const uint64_t src = b.idx[i];
+    float rgb[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) rgb[q] = b.rgb[q * b.cap + i];
+    x = clamp01_b(x);
+    const float u = x * (float)g.M;
+    const uint32_t j = min((uint32_t)u, g.M - 1);
+    const float tt = u - (float)j;
+    const float* gp = lg + lp * 3;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const float* cf = lc + (lp * C + c) * g.M;
+      const float hi = cell_value(cf, g, j, CELLS);
+      const float lo = j ? cell_value(cf, g, j - 1, CELLS) : 0.f;
+      const float v = __expf(-fmaf(tt, hi, (1.f - tt) * lo));
+      const float alc = alpha_clamped(al[c]);
+      const float* S = ladj + (lp * C + c) * g.M;
+      const float Sj = S[j];
+      const float Sj1 = (j + 1 < g.M) ? S[j + 1] : 0.f;
+      const float through_cells = ((float)(j + 1) - u) * (Sj - Sj1) + Sj1;
+      const float gbg = (C == 1) ? (gp[0] * bg[0] + gp[1] * bg[1] + gp[2] * bg[2]) : gp[c] * bg[c];
+      const float dLda = through_cells - gbg * lT[lp * C + c];
+      const float gc = (C == 1) ? (gp[0] * rgb[0] + gp[1] * rgb[1] + gp[2] * rgb[2]) : gp[c] * rgb[c];
+      const bool inside = al[c] > 0.f && al[c] < kAlphaMax;
+      grad_alpha[src * C + c] = inside ? v * gc + dLda / (1.f - alc) : 0.f;
+      if (C == 1) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) grad_rgb[src * 3 + q] = gp[q] * alc * v;
+      } else {
+        grad_rgb[src * 3 + c] = gp[c] * alc * v;
+      }
+    }
+  }
+}
+
+size_t lds_backward_bytes(const Geom& g) {
+  return (size_t)g.tile_px * (2 * g.C * g.M + 3 + g.C) * sizeof(float);
+}
+
+hipError_t launch_backward(const Geom& g, const Binned& b, const void* coeffs, const float* accum, const float* bg,
+                           const float* grad_out, float* grad_alpha, float* grad_rgb, uint64_t count,
+                           hipStream_t s) {
+  if (count) {
+    const unsigned za = (unsigned)std::min<uint64_t>((count * g.C + 255) / 256, 8192);
+    const unsigned zr = (unsigned)std::min<uint64_t>((count * 3 + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_zero_f32, dim3(za), dim3(256), 0, s, grad_alpha, count * g.C);
+    hipLaunchKernelGGL(k_zero_f32, dim3(zr), dim3(256), 0, s, grad_rgb, count * 3);
+  }
+  const size_t lds = lds_backward_bytes(g);
+  if (lds > kLdsBytes) return hipErrorNotSupported;
+  hipError_t err = hipSuccess;
+#define WT_BWD_LAUNCH(CC, TT, CELLS)                                                                              \
+  do {                                                                                                           \
+    auto k = k_backward<CC, TT, CELLS>;                                                                          \
+    if (lds > 65536) err = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+    if (err == hipSuccess)                                                                                       \
+      hipLaunchKernelGGL(k, dim3(g.ntiles), dim3(kBwdThreads), lds, s, b, g, (const TT*)coeffs, accum, bg[0],     \
+                         bg[1], bg[2], grad_out, grad_alpha, grad_rgb);                                          \
+  } while (0)
+#define WT_BWD_CELLS(CC, TT)               \
+  do {                                     \
+    if (g.M <= 32)                         \
+      WT_BWD_LAUNCH(CC, TT, true);         \
+    else                                   \
+      WT_BWD_LAUNCH(CC, TT, false);        \
+  } while (0)
+#define WT_BWD_TYPE(CC)                                   \
+  do {                                                    \
+    if (g.dtype == WT_F32) WT_BWD_CELLS(CC, float);       \
+    else if (g.dtype == WT_F16) WT_BWD_CELLS(CC, __half); \
+    else WT_BWD_CELLS(CC, bf16_t);                        \
+  } while (0)
+  if (g.C == 1)
+    WT_BWD_TYPE(1);
+  else
+    WT_BWD_TYPE(3);
+#undef WT_BWD_TYPE
+#undef WT_BWD_CELLS
+#undef WT_BWD_LAUNCH
+  if (err != hipSuccess) return err;
+  return hipGetLastError();
+}
+
+}  // namespace wt

@@ -1,0 +1,79 @@
+// Internal declarations shared by the libwt translation units: frame geometry, workspace layout and the
+// kernel launchers. Nothing here is part of the public ABI (include/wt.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "wt.h"
+
+namespace wt {
+
+// Workgroups of a grid are dealt to the eight XCDs of an MI355X round-robin (workgroup b runs on XCD b % 8),
+// and each XCD has its own L2. The binning keeps one write frontier per (tile, XCD class) so that the
+// partial cache lines of a frontier are filled inside a single L2 before they are written back.
+constexpr uint32_t kClasses = 8;
+constexpr uint32_t kChunk = 8192;          // fragments per scatter workgroup
+constexpr uint32_t kMaxLdsBins = 16384;    // tiles a per-workgroup LDS histogram can hold (64 KB)
+constexpr uint32_t kLdsBytes = 160 * 1024; // LDS of one CDNA4 compute unit
+constexpr uint32_t kCoeffLdsBudget = 128 * 1024;
+constexpr float kAlphaMax = 0.99999994f;   // 1 - 2^-24
+
+// Frame geometry as the kernels see it.
+struct Geom {
+  uint32_t W, H, P;      // frame
+  uint32_t C, rank, M, L;// channels, rank, coefficients per channel (2^L), L = rank + 1
+  uint32_t TW, TH;       // tile extent in pixels (powers of two)
+  uint32_t tilesX, tilesY, ntiles, tile_px;
+  uint32_t NX;           // write-frontier classes (kClasses, or 1 when the tile count is large)
+  uint32_t lds_bins;     // 1: per-workgroup LDS histograms; 0: global atomics per fragment
+  uint32_t AW;           // accum floats per pixel: 4 (C = 1) or 8 (C = 3)
+  uint32_t dtype;        // wt_dtype of the coefficient storage
+};
+
+// Device workspace: a header, the tile tables and the binned fragment arrays (structure of arrays).
+struct Layout {
+  size_t header;   // uint64 dropped counter + spare
+  size_t counts;   // uint32 [NX][ntiles]
+  size_t offsets;  // uint32 [ntiles * NX + 1], tile-major: segment (t, x) = [off[t*NX+x], off[t*NX+x+1])
+  size_t cursors;  // uint32 [NX][ntiles]
+  size_t lpx;      // uint32 [cap] tile-local pixel index
+  size_t x;        // float [cap]
+  size_t alpha;    // float [C][cap]
+  size_t rgb;      // float [3][cap]
+  size_t idx;      // uint32 [cap] stream index of the binned fragment
+  size_t total;    // bytes
+  uint64_t cap;    // fragment capacity
+};
+
+// Pointers into a workspace, as passed to kernels.
+struct Binned {
+  const uint32_t* offsets;
+  const uint32_t* lpx;
+  const float* x;
+  const float* alpha;  // channel c at alpha + c * cap
+  const float* rgb;    // channel q at rgb + q * cap
+  const uint32_t* idx;
+  uint64_t cap;
+};
+
+// backward = true picks tiles half the size: the gradient kernel holds cell values and their adjoints.
+Geom make_geom(const wt_frame_desc& d, bool backward = false);
+Layout make_layout(const Geom& g, uint64_t cap);
+uint64_t capacity_for(const Geom& g, size_t ws_bytes);
+size_t lds_tile_bytes(const Geom& g, bool with_accum);
+size_t lds_backward_bytes(const Geom& g);
+Binned binned_view(const Geom& g, const Layout& l, const void* ws);
+
+// Launchers (return hipError_t of the launch).
+hipError_t launch_bin(const Geom& g, const wt_fragments& f, void* ws, const Layout& l, bool record_index,
+                      hipStream_t s);
+hipError_t launch_build(const Geom& g, const Binned& b, void* coeffs, hipStream_t s);
+hipError_t launch_evaluate(const Geom& g, const Binned& b, const void* coeffs, float* accum, hipStream_t s);
+hipError_t launch_resolve(const Geom& g, const float* accum, const float* bg, float* out, hipStream_t s);
+hipError_t launch_render(const Geom& g, const Binned& b, const float* bg, void* coeffs, float* out, hipStream_t s);
+hipError_t launch_backward(const Geom& g, const Binned& b, const void* coeffs, const float* accum, const float* bg,
+                           const float* grad_out, float* grad_alpha, float* grad_rgb, uint64_t count,
+                           hipStream_t s);
+
+}  // namespace wt

@@ -1,0 +1,203 @@
+"""PyTorch-facing wrappers of libwt. PyTorch supplies device memory and the current HIP stream; every step of the
+path runs in the library's HIP kernels.
+
+Fragments are device tensors: ``pixel`` int32/uint32 [F] (y * width + x), ``depth`` float32 [F], ``alpha``
+float32 [F] or [F, 3], ``rgb`` float32 [F, 3].
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+
+DTYPES = {"f32": _lib.WT_F32, "f16": _lib.WT_F16, "bf16": _lib.WT_BF16}
+TORCH_DTYPES = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}
+
+
+@dataclass
+class FrameSpec:
+    width: int
+    height: int
+    rank: int
+    channels: int = 1
+    dtype: str = "f32"
+
+    @property
+    def pixels(self) -> int:
+        return self.width * self.height
+
+    @property
+    def M(self) -> int:
+        return 1 << (self.rank + 1)
+
+    @property
+    def accum_width(self) -> int:
+        return 8 if self.channels == 3 else 4
+
+    def c_desc(self) -> _lib.FrameDesc:
+        if self.dtype not in DTYPES:
+            raise ValueError("unknown coefficient storage %r" % self.dtype)
+        return _lib.desc(self.width, self.height, self.rank, self.channels, DTYPES[self.dtype])
+
+    def coeff_shape(self):
+        return (self.pixels, self.channels, self.M)
+
+    def new_coeffs(self, device="cuda"):
+        return torch.zeros(self.coeff_shape(), dtype=TORCH_DTYPES[self.dtype], device=device)
+
+    def new_accum(self, device="cuda"):
+        return torch.zeros((self.pixels, self.accum_width), dtype=torch.float32, device=device)
+
+
+@dataclass
+class Fragments:
+    pixel: torch.Tensor
+    depth: torch.Tensor
+    alpha: torch.Tensor
+    rgb: torch.Tensor
+
+    @property
+    def count(self) -> int:
+        return int(self.pixel.shape[0])
+
+    @staticmethod
+    def from_numpy(pixel, depth, alpha, rgb, device="cuda") -> "Fragments":
+        import numpy as np
+        return Fragments(torch.from_numpy(np.ascontiguousarray(pixel).view(np.int32)).to(device),
+                         torch.from_numpy(np.ascontiguousarray(depth, dtype=np.float32)).to(device),
+                         torch.from_numpy(np.ascontiguousarray(alpha, dtype=np.float32)).to(device),
+                         torch.from_numpy(np.ascontiguousarray(rgb, dtype=np.float32)).to(device))
+
+    def c_struct(self, channels: int) -> _lib.Fragments:
+        F = self.count
+        _check(self.pixel, (torch.int32, getattr(torch, "uint32", torch.int32)), (F,), "pixel")
+        _check(self.depth, (torch.float32,), (F,), "depth")
+        _check(self.alpha, (torch.float32,), (F,) if channels == 1 else (F, 3), "alpha")
+        _check(self.rgb, (torch.float32,), (F, 3), "rgb")
+        return _lib.Fragments(F, self.pixel.data_ptr(), self.depth.data_ptr(), self.alpha.data_ptr(),
+                              self.rgb.data_ptr())
+
+
+def _check(t: torch.Tensor, dtypes, shape, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a device tensor" % name)
+    if t.dtype not in dtypes:
+        raise TypeError("%s has dtype %s" % (name, t.dtype))
+    if tuple(t.shape) != tuple(shape) and not (t.numel() == 0 and shape[0] == 0):
+        raise ValueError("%s has shape %s, expected %s" % (name, tuple(t.shape), tuple(shape)))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def workspace_bytes(spec: FrameSpec, max_fragments: int) -> int:
+    n = _lib.load().wt_workspace_bytes(C.byref(spec.c_desc()), int(max_fragments))
+    if n == 0:
+        raise ValueError("invalid frame description %r" % (spec,))
+    return int(n)
+
+
+class Workspace:
+    """Device scratch for one frame description and fragment budget (a torch uint8 tensor)."""
+
+    def __init__(self, spec: FrameSpec, max_fragments: int, device="cuda"):
+        self.spec = spec
+        self.nbytes = workspace_bytes(spec, max_fragments)
+        self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
+
+    @property
+    def ptr(self):
+        return C.c_void_p(self.buf.data_ptr())
+
+
+def bin(spec: FrameSpec, frags: Fragments, ws: Workspace, stream=None):
+    lib = _lib.load()
+    _lib.check(lib.wt_bin(C.byref(spec.c_desc()), C.byref(frags.c_struct(spec.channels)), ws.ptr, ws.nbytes,
+                          _stream(stream)), "wt_bin")
+
+
+def build_binned(spec: FrameSpec, coeffs: torch.Tensor, ws: Workspace, stream=None):
+    _check(coeffs, (TORCH_DTYPES[spec.dtype],), spec.coeff_shape(), "coeffs")
+    _lib.check(_lib.load().wt_build_binned(C.byref(spec.c_desc()), _ptr(coeffs), ws.ptr, ws.nbytes, _stream(stream)),
+               "wt_build_binned")
+
+
+def evaluate_binned(spec: FrameSpec, coeffs: torch.Tensor, accum: torch.Tensor, ws: Workspace, stream=None):
+    _check(coeffs, (TORCH_DTYPES[spec.dtype],), spec.coeff_shape(), "coeffs")
+    _check(accum, (torch.float32,), (spec.pixels, spec.accum_width), "accum")
+    _lib.check(_lib.load().wt_evaluate_binned(C.byref(spec.c_desc()), _ptr(coeffs), _ptr(accum), ws.ptr, ws.nbytes,
+                                              _stream(stream)), "wt_evaluate_binned")
+
+
+def build(spec: FrameSpec, frags: Fragments, coeffs: torch.Tensor, ws: Workspace, stream=None):
+    """coeffs += coefficients of ``frags`` (build pass)."""
+    _check(coeffs, (TORCH_DTYPES[spec.dtype],), spec.coeff_shape(), "coeffs")
+    _lib.check(_lib.load().wt_build(C.byref(spec.c_desc()), C.byref(frags.c_struct(spec.channels)), _ptr(coeffs),
+                                    ws.ptr, ws.nbytes, _stream(stream)), "wt_build")
+
+
+def evaluate(spec: FrameSpec, frags: Fragments, coeffs: torch.Tensor, accum: torch.Tensor, ws: Workspace,
+             stream=None):
+    """accum += visibility-weighted colour and absorbance of ``frags`` (evaluate pass)."""
+    _check(coeffs, (TORCH_DTYPES[spec.dtype],), spec.coeff_shape(), "coeffs")
+    _check(accum, (torch.float32,), (spec.pixels, spec.accum_width), "accum")
+    _lib.check(_lib.load().wt_evaluate(C.byref(spec.c_desc()), C.byref(frags.c_struct(spec.channels)), _ptr(coeffs),
+                                       _ptr(accum), ws.ptr, ws.nbytes, _stream(stream)), "wt_evaluate")
+
+
+def resolve(spec: FrameSpec, accum: torch.Tensor, bg, out: torch.Tensor = None, stream=None) -> torch.Tensor:
+    _check(accum, (torch.float32,), (spec.pixels, spec.accum_width), "accum")
+    if out is None:
+        out = torch.empty((spec.pixels, 3), dtype=torch.float32, device=accum.device)
+    _check(out, (torch.float32,), (spec.pixels, 3), "out")
+    _lib.check(_lib.load().wt_resolve(C.byref(spec.c_desc()), _ptr(accum), _lib.bg3(bg), _ptr(out), _stream(stream)),
+               "wt_resolve")
+    return out
+
+
+def render(spec: FrameSpec, frags: Fragments, bg, ws: Workspace, out: torch.Tensor = None,
+           coeffs: torch.Tensor = None, stream=None) -> torch.Tensor:
+    """Whole path for one frame (bin, build, evaluate, resolve); writes ``out`` and, if given, ``coeffs``."""
+    dev = frags.pixel.device
+    if out is None:
+        out = torch.empty((spec.pixels, 3), dtype=torch.float32, device=dev)
+    _check(out, (torch.float32,), (spec.pixels, 3), "out")
+    if coeffs is not None:
+        _check(coeffs, (TORCH_DTYPES[spec.dtype],), spec.coeff_shape(), "coeffs")
+    _lib.check(_lib.load().wt_render(C.byref(spec.c_desc()), C.byref(frags.c_struct(spec.channels)), _lib.bg3(bg),
+                                     _ptr(coeffs), _ptr(out), ws.ptr, ws.nbytes, _stream(stream)), "wt_render")
+    return out
+
+
+def backward(spec: FrameSpec, frags: Fragments, coeffs: torch.Tensor, accum: torch.Tensor, bg, grad_out: torch.Tensor,
+             ws: Workspace, grad_alpha: torch.Tensor = None, grad_rgb: torch.Tensor = None, stream=None):
+    dev = frags.pixel.device
+    F = frags.count
+    if grad_alpha is None:
+        grad_alpha = torch.empty((F,) if spec.channels == 1 else (F, 3), dtype=torch.float32, device=dev)
+    if grad_rgb is None:
+        grad_rgb = torch.empty((F, 3), dtype=torch.float32, device=dev)
+    _check(coeffs, (TORCH_DTYPES[spec.dtype],), spec.coeff_shape(), "coeffs")
+    _check(accum, (torch.float32,), (spec.pixels, spec.accum_width), "accum")
+    _check(grad_out, (torch.float32,), (spec.pixels, 3), "grad_out")
+    _lib.check(_lib.load().wt_backward(C.byref(spec.c_desc()), C.byref(frags.c_struct(spec.channels)), _ptr(coeffs),
+                                       _ptr(accum), _lib.bg3(bg), _ptr(grad_out), _ptr(grad_alpha), _ptr(grad_rgb),
+                                       ws.ptr, ws.nbytes, _stream(stream)), "wt_backward")
+    return grad_alpha, grad_rgb
+
+
+def dropped_count(ws: Workspace, stream=None) -> int:
+    n = C.c_uint64(0)
+    _lib.check(_lib.load().wt_dropped_count(ws.ptr, ws.nbytes, C.byref(n), _stream(stream)), "wt_dropped_count")
+    return int(n.value)

@@ -1,0 +1,94 @@
+"""Shared helpers for the GPU parity tests: move a synthetic frame to the device, run the library, compare with
+the oracle under the parity contract."""
+import sys
+
+import numpy as np
+
+
+def say(*args):
+    print(*args, flush=True)
+    sys.stdout.flush()
+
+
+def device_frags(f, device="cuda"):
+    import paper_2201_00094_amd as wt
+    return wt.Fragments.from_numpy(f.pixel, f.depth, f.alpha, f.rgb, device=device)
+
+
+def spec_of(f, dtype="f32", rank=None):
+    import paper_2201_00094_amd as wt
+    return wt.FrameSpec(f.width, f.height, f.rank if rank is None else rank, f.channels, dtype)
+
+
+def gpu_render(f, dtype="f32", rank=None, want_coeffs=True):
+    import torch
+    import paper_2201_00094_amd as wt
+    spec = spec_of(f, dtype, rank)
+    fr = device_frags(f)
+    ws = wt.Workspace(spec, f.count)
+    coeffs = spec.new_coeffs() if want_coeffs else None
+    out = wt.render(spec, fr, f.bg, ws, coeffs=coeffs)
+    torch.cuda.synchronize()
+    res = {"out": out.cpu().double().numpy(), "dropped": wt.dropped_count(ws)}
+    if want_coeffs:
+        res["coeffs"] = coeffs.float().cpu().double().numpy()
+    return res
+
+
+def gpu_passes(f, dtype="f32", rank=None, chunks=1):
+    """Separate build / evaluate / resolve calls, each taking the raw stream (optionally in chunks)."""
+    import torch
+    import paper_2201_00094_amd as wt
+    spec = spec_of(f, dtype, rank)
+    coeffs = spec.new_coeffs()
+    accum = spec.new_accum()
+    bounds = np.linspace(0, f.count, chunks + 1).astype(np.int64)
+    ws = wt.Workspace(spec, max(1, int(np.diff(bounds).max())))
+    parts = [device_frags(f.subset(np.arange(bounds[i], bounds[i + 1]))) for i in range(chunks)]
+    for p in parts:
+        wt.build(spec, p, coeffs, ws)
+    for p in parts:
+        wt.evaluate(spec, p, coeffs, accum, ws)
+    out = wt.resolve(spec, accum, f.bg)
+    torch.cuda.synchronize()
+    return {"coeffs": coeffs.float().cpu().double().numpy(), "accum": accum.cpu().double().numpy(),
+            "out": out.cpu().double().numpy()}
+
+
+def oracle_frame(orc, f, rank=None, storage="exact", mask=None, want=("coeffs", "accum", "suma", "out")):
+    return orc.resolve(f.width, f.height, f.rank if rank is None else rank, f.pixel, f.depth, f.alpha, f.rgb,
+                       bg=f.bg, channels=f.channels, mask=mask, want=want, storage=storage)
+
+
+def assert_coeffs(g, o, rel=1e-5, sel=None, what="coeffs"):
+    """Every element within rel * |oracle|; exact zeros stay zero."""
+    g = g.reshape(o.shape)
+    if sel is not None:
+        g, o = g[sel], o[sel]
+    zero = o == 0
+    assert (g[zero] == 0).all(), "%s: %d oracle zeros are non-zero on the GPU" % (what, int((g[zero] != 0).sum()))
+    err = np.abs(g - o)
+    bad = err > rel * np.abs(o)
+    if bad.any():
+        i = np.unravel_index(np.argmax(err / np.maximum(np.abs(o), 1e-300)), o.shape)
+        raise AssertionError("%s: %d elements beyond %.1e relative; worst at %s: gpu %r oracle %r" %
+                             (what, int(bad.sum()), rel, i, g[i], o[i]))
+
+
+def assert_close_abs(g, o, atol, sel=None, what="out"):
+    g = g.reshape(o.shape)
+    if sel is not None:
+        g, o = g[sel], o[sel]
+    err = np.abs(g - o)
+    if not (err <= atol).all():
+        i = np.unravel_index(np.argmax(err), o.shape)
+        raise AssertionError("%s: max abs error %.3e > %.1e at %s: gpu %r oracle %r" % (what, err.max(), atol, i, g[i],
+                                                                                       o[i]))
+    return float(err.max()) if err.size else 0.0
+
+
+def accum_to_oracle_layout(acc, channels):
+    """GPU accum [P][4] or [P][8] -> (S [P][3], suma [P][C])."""
+    if channels == 1:
+        return acc[:, :3], acc[:, 3:4]
+    return acc[:, :3], acc[:, 4:7]

@@ -1,0 +1,97 @@
+"""Host-side checks of the C ABI (no GPU): every symbol of include/wt.h is exported, and argument validation
+fails before anything is enqueued."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2201_00094_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "wt.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(wt_[a-z_0-9]+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def test_header_declares_the_path():
+    names = header_functions()
+    for n in ("wt_build", "wt_evaluate", "wt_resolve", "wt_render", "wt_backward", "wt_bin", "wt_workspace_bytes",
+              "wt_last_error", "wt_dropped_count"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in header_functions():
+        assert hasattr(lib, name), name
+        assert name in _lib.SIGNATURES, name
+
+
+def test_abi_version(lib):
+    assert lib.wt_abi_version() == 1
+
+
+def test_workspace_bytes(lib):
+    d = _lib.desc(1920, 1080, 3)
+    a = lib.wt_workspace_bytes(C.byref(d), 0)
+    b = lib.wt_workspace_bytes(C.byref(d), 1000)
+    c = lib.wt_workspace_bytes(C.byref(d), 132_710_400)
+    assert 0 < a < b < c
+    assert c >= 132_710_400 * 28  # binned copy: pixel, depth, alpha, rgb, stream index
+    assert lib.wt_workspace_bytes(C.byref(_lib.desc(16, 16, 11)), 10) == 0  # rank > 10
+    assert lib.wt_workspace_bytes(C.byref(_lib.desc(16, 16, 3, channels=2)), 10) == 0
+    assert lib.wt_workspace_bytes(None, 10) == 0
+    assert lib.wt_workspace_bytes(C.byref(_lib.desc(16, 16, 3)), 1 << 32) == 0
+
+
+def _err(lib):
+    return lib.wt_last_error().decode()
+
+
+def test_validation_errors_before_any_launch(lib):
+    d = _lib.desc(64, 64, 3)
+    f = _lib.Fragments(10, None, None, None, None)
+    ws = C.c_void_p(0x1000)  # never dereferenced: validation fails first
+    assert lib.wt_bin(None, C.byref(f), ws, 1 << 20, None) == _lib.WT_ERR_INVALID
+    assert "desc" in _err(lib)
+    assert lib.wt_bin(C.byref(d), C.byref(f), ws, 1 << 20, None) == _lib.WT_ERR_INVALID
+    assert "NULL" in _err(lib)
+    big = _lib.Fragments(1 << 32, 1, 1, 1, 1)
+    assert lib.wt_bin(C.byref(d), C.byref(big), ws, 1 << 20, None) == _lib.WT_ERR_RANGE
+    ok = _lib.Fragments(10, 8, 8, 8, 8)
+    assert lib.wt_bin(C.byref(d), C.byref(ok), ws, 16, None) == _lib.WT_ERR_RANGE
+    assert "workspace" in _err(lib)
+    assert lib.wt_bin(C.byref(d), C.byref(ok), None, 1 << 30, None) == _lib.WT_ERR_INVALID
+    assert lib.wt_bin(C.byref(_lib.desc(0, 5, 3)), C.byref(ok), ws, 1 << 30, None) == _lib.WT_ERR_INVALID
+    assert lib.wt_bin(C.byref(_lib.desc(65536, 65536, 3)), C.byref(ok), ws, 1 << 30, None) == _lib.WT_ERR_RANGE
+    assert lib.wt_bin(C.byref(_lib.desc(8, 8, 3, 1, 7)), C.byref(ok), ws, 1 << 30, None) == _lib.WT_ERR_INVALID
+    bg = _lib.bg3((0, 0, 0))
+    assert lib.wt_resolve(C.byref(d), None, bg, ws, None) == _lib.WT_ERR_INVALID
+    assert lib.wt_render(C.byref(d), C.byref(ok), None, None, ws, ws, 1 << 30, None) == _lib.WT_ERR_INVALID
+    assert lib.wt_build_binned(C.byref(d), None, ws, 1 << 30, None) == _lib.WT_ERR_INVALID
+    assert lib.wt_evaluate_binned(C.byref(d), ws, None, ws, 1 << 30, None) == _lib.WT_ERR_INVALID
+    assert lib.wt_backward(C.byref(d), C.byref(ok), ws, ws, bg, None, ws, ws, ws, 1 << 30, None) == \
+        _lib.WT_ERR_INVALID
+    n = C.c_uint64(0)
+    assert lib.wt_dropped_count(None, 1 << 20, C.byref(n), None) == _lib.WT_ERR_INVALID
+    assert lib.wt_dropped_count(ws, 8, C.byref(n), None) == _lib.WT_ERR_RANGE
+
+
+def test_python_binding_rejects_host_tensors():
+    import torch
+    import paper_2201_00094_amd as wt
+    spec = wt.FrameSpec(8, 8, 3)
+    fr = wt.Fragments(torch.zeros(4, dtype=torch.int32), torch.zeros(4), torch.zeros(4), torch.zeros(4, 3))
+    with pytest.raises(TypeError):
+        fr.c_struct(1)
+    with pytest.raises(ValueError):
+        wt.FrameSpec(8, 8, 3, dtype="f64").c_desc()

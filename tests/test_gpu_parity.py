@@ -1,0 +1,182 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Contract: coefficients within 1e-5 relative per element (exact zeros stay zero); composite rgb within 1e-4
+absolute; accumulations within 2e-5 relative. FP16/BF16 storage is compared with the oracle run at the same
+storage precision (coefficients within one storage rounding step), and its error against the exact oracle is
+reported.
+"""
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import (accum_to_oracle_layout, assert_close_abs, assert_coeffs, gpu_passes, gpu_render,
+                         oracle_frame, say, spec_of)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2201_00094_amd as wt
+    wt.load_library()
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_c1_render(orc, seed):
+    f = synth.frame_c1(seed=seed)
+    say("case c1 render seed", seed, "F", f.count)
+    g = gpu_render(f)
+    o = oracle_frame(orc, f)
+    assert g["dropped"] == 0
+    assert_coeffs(g["coeffs"], o["coeffs"])
+    assert_close_abs(g["out"], o["out"], 1e-4)
+
+
+def test_c1_three_passes(orc):
+    f = synth.frame_c1(seed=3)
+    say("case c1 build/evaluate/resolve")
+    g = gpu_passes(f)
+    o = oracle_frame(orc, f)
+    assert_coeffs(g["coeffs"], o["coeffs"])
+    S, sa = accum_to_oracle_layout(g["accum"], 1)
+    np.testing.assert_allclose(S, o["accum"], rtol=2e-5, atol=1e-7)
+    np.testing.assert_allclose(sa, o["suma"], rtol=2e-5, atol=1e-7)
+    assert_close_abs(g["out"], o["out"], 1e-4)
+
+
+@pytest.mark.parametrize("rank", [0, 1, 2, 3, 4, 5, 6])
+def test_ragged_frame_all_ranks(orc, rank):
+    """70 x 45 pixels: partial tiles on the right and bottom edges for every tile shape."""
+    f = synth.frame_c1(seed=10 + rank, width=70, height=45, rank=rank, mean=6.0)
+    say("case ragged 70x45 rank", rank)
+    g = gpu_render(f)
+    o = oracle_frame(orc, f)
+    assert_coeffs(g["coeffs"], o["coeffs"])
+    assert_close_abs(g["out"], o["out"], 1e-4)
+    p = gpu_passes(f)
+    assert_coeffs(p["coeffs"], o["coeffs"])
+    assert_close_abs(p["out"], o["out"], 1e-4)
+
+
+@pytest.mark.parametrize("rank", [8, 10])
+def test_high_rank_tiny_frame(orc, rank):
+    f = synth.frame_c1(seed=rank, width=9, height=7, rank=rank, mean=12.0)
+    say("case high rank", rank)
+    g = gpu_render(f)
+    o = oracle_frame(orc, f)
+    assert_coeffs(g["coeffs"], o["coeffs"])
+    assert_close_abs(g["out"], o["out"], 1e-4)
+
+
+@pytest.mark.parametrize("rank", [3, 4])
+def test_three_channels(orc, rank):
+    f = synth.frame_c3(seed=rank, width=50, height=37, rank=rank, particles=8.0)
+    say("case three channels rank", rank, "F", f.count)
+    g = gpu_render(f)
+    o = oracle_frame(orc, f)
+    assert_coeffs(g["coeffs"], o["coeffs"])
+    assert_close_abs(g["out"], o["out"], 1e-4)
+    p = gpu_passes(f)
+    S, sa = accum_to_oracle_layout(p["accum"], 3)
+    np.testing.assert_allclose(S, o["accum"], rtol=2e-5, atol=1e-7)
+    np.testing.assert_allclose(sa, o["suma"], rtol=2e-5, atol=1e-7)
+    assert_close_abs(p["out"], o["out"], 1e-4)
+
+
+@pytest.mark.parametrize("dtype,step", [("f16", 2.0 ** -11), ("bf16", 2.0 ** -8)])
+@pytest.mark.parametrize("channels", [1, 3])
+def test_reduced_precision_storage(orc, dtype, step, channels):
+    f = synth.frame_c1(seed=7, width=61, height=33) if channels == 1 else \
+        synth.frame_c3(seed=7, width=61, height=33, particles=8.0)
+    say("case storage", dtype, "channels", channels)
+    g = gpu_render(f, dtype=dtype)
+    o = oracle_frame(orc, f, storage=dtype)
+    ex = oracle_frame(orc, f, want=("out",))
+    # one storage rounding step apart at most: FP32 accumulation can move a value across a rounding boundary
+    assert_coeffs(g["coeffs"], o["coeffs"], rel=2 * step + 1e-5, what=dtype + " coeffs")
+    err_same = assert_close_abs(g["out"], o["out"], 1e-3, what=dtype + " out vs oracle at storage precision")
+    err_exact = float(np.abs(g["out"] - ex["out"]).max())
+    say("  %s: max |out - oracle(%s)| = %.2e, max |out - oracle(exact)| = %.2e" % (dtype, dtype, err_same, err_exact))
+    p = gpu_passes(f, dtype=dtype)
+    np.testing.assert_allclose(p["out"], g["out"], rtol=0, atol=1e-3)
+
+
+def test_order_independence_and_chunks(orc):
+    """Permuted and chunked streams give the same result within the parity tolerance (P6, P10)."""
+    f = synth.frame_c1(seed=11, width=90, height=70, mean=20.0)
+    say("case permutation/chunks")
+    o = oracle_frame(orc, f)
+    base = gpu_passes(f)
+    perm = f.subset(np.random.default_rng(1).permutation(f.count))
+    permuted = gpu_passes(perm)
+    chunked = gpu_passes(f, chunks=5)
+    for r in (base, permuted, chunked):
+        assert_coeffs(r["coeffs"], o["coeffs"])
+        assert_close_abs(r["out"], o["out"], 1e-4)
+
+
+def test_empty_frame_shows_background():
+    import torch
+    import paper_2201_00094_amd as wt
+    say("case empty frame")
+    spec = wt.FrameSpec(33, 17, 3)
+    fr = wt.Fragments(torch.zeros(0, dtype=torch.int32, device="cuda"), torch.zeros(0, device="cuda"),
+                      torch.zeros(0, device="cuda"), torch.zeros((0, 3), device="cuda"))
+    ws = wt.Workspace(spec, 0)
+    coeffs = spec.new_coeffs()
+    coeffs.fill_(7.0)
+    out = wt.render(spec, fr, (0.25, 0.5, 0.75), ws, coeffs=coeffs)
+    torch.cuda.synchronize()
+    assert (coeffs == 0).all()
+    assert torch.equal(out.cpu(), torch.tensor([[0.25, 0.5, 0.75]]).expand(33 * 17, 3))
+    assert wt.dropped_count(ws) == 0
+
+
+def test_edge_values_and_drops(orc):
+    W, H = 5, 4
+    pix = np.array([0, 0, 0, 1, 1, 2, 3, 3, 7, 100, 5, 6, 6], np.uint32)
+    depth = np.array([0.0, 1.0, 0.5, -3.0, 7.0, np.nan, 0.25, 0.75, 0.1, 0.2, 0.3, 0.6, 0.6], np.float32)
+    alpha = np.array([0.3, 0.9, 0.0, 1.0, -0.5, 0.5, 2.0, 0.99999, np.nan, 0.3, 1e-7, 0.5, 0.5], np.float32)
+    rgb = np.random.default_rng(0).random((13, 3), dtype=np.float32)
+    f = synth.Frame(W, H, 3, 1, pix, depth, alpha, rgb, (0.1, 0.2, 0.3), "edges")
+    say("case edge values")
+    g = gpu_render(f)
+    o = oracle_frame(orc, f, want=("coeffs", "out"))
+    assert g["dropped"] == 3 and o["dropped"] == 3
+    assert_coeffs(g["coeffs"], o["coeffs"])
+    assert_close_abs(g["out"], o["out"], 1e-4)
+
+
+@pytest.mark.parametrize("rank", [3, 4])
+def test_smoke_1080p_64_sampled(orc, rank):
+    """The benchmark workload (1920x1080, Poisson(64 g) fragments/px) in the benchmark's launch configuration,
+    checked on 1500 sampled pixels plus the 100 densest, and by sign/monotonicity over the whole frame."""
+    import torch
+    import paper_2201_00094_amd as wt
+    f = synth.frame_c2(seed=0, rank=rank)
+    say("case smoke 1080p rank", rank, "F", f.count)
+    spec = spec_of(f)
+    fr = wt.Fragments.from_numpy(f.pixel, f.depth, f.alpha, f.rgb)
+    ws = wt.Workspace(spec, f.count)
+    coeffs = spec.new_coeffs()
+    out = wt.render(spec, fr, f.bg, ws, coeffs=coeffs)
+    torch.cuda.synchronize()
+    assert wt.dropped_count(ws) == 0
+    c = coeffs[:, 0, :]
+    assert bool((c[:, 0] >= 0).all()) and bool((c[:, 1:] <= 0).all())
+    cnt = np.bincount(f.pixel, minlength=f.pixels)
+    rng = np.random.default_rng(rank)
+    sel = np.unique(np.concatenate([rng.choice(f.pixels, 1500, replace=False), np.argsort(cnt)[-100:]]))
+    mask = np.zeros(f.pixels, bool)
+    mask[sel] = True
+    o = oracle_frame(orc, f, mask=mask, want=("coeffs", "out"))
+    gc = coeffs.cpu().double().numpy()
+    go = out.cpu().double().numpy()
+    assert_coeffs(gc, o["coeffs"], sel=sel)
+    err = assert_close_abs(go, o["out"], 1e-4, sel=sel)
+    say("  max |out - oracle| on %d sampled pixels: %.2e" % (sel.size, err))
+    del fr, ws, coeffs, out
+    torch.cuda.empty_cache()

@@ -318,6 +318,29 @@ def test_dropped_fragments(orc):
     assert r["out"][1].tolist() == [0.0, 0.0, 0.0]
 
 
+# ---------------------------------------------------------------------------------------------- storage precision
+def test_storage_rounding_matches_ieee_conversions(orc):
+    """FP16 rounding against NumPy's binary16 conversion, BF16 against torch's (both round to nearest even)."""
+    import torch
+    rng = np.random.default_rng(5)
+    vals = np.concatenate([rng.standard_normal(4000) * 10.0 ** rng.uniform(-9, 4, 4000),
+                           [0.0, -0.0, 1.0, 65504.0, 65519.0, 65520.0, 2.0 ** -24, 2.0 ** -25, 3 * 2.0 ** -26]])
+    vals = vals.astype(np.float32).astype(np.float64)  # exactly representable in FP32: one rounding step
+    f16 = np.array([orc.round_storage(v, "f16") for v in vals])
+    np.testing.assert_array_equal(f16, vals.astype(np.float16).astype(np.float64))
+    b16 = np.array([orc.round_storage(v, "bf16") for v in vals])
+    ref = torch.from_numpy(vals.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(b16, ref)
+
+
+def test_storage_rounding_in_resolve(orc):
+    f = synth.frame_c1(seed=2, width=8, height=8)
+    ex = orc.resolve(8, 8, 3, f.pixel, f.depth, f.alpha, f.rgb, want=("coeffs", "out"))
+    h = orc.resolve(8, 8, 3, f.pixel, f.depth, f.alpha, f.rgb, want=("coeffs", "out"), storage="f16")
+    np.testing.assert_array_equal(h["coeffs"], ex["coeffs"].astype(np.float16).astype(np.float64))
+    assert 0 < np.abs(h["out"] - ex["out"]).max() < 1e-2
+
+
 # ---------------------------------------------------------------------------------------------- A-buffer
 def test_abuffer_golden_two_layers(orc):
     rows = [ln.split() for ln in open(os.path.join(GOLDEN, "two_layer_abuffer.txt")) if ln.strip() and ln[0] != "#"]
