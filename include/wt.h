@@ -117,6 +117,11 @@ wt_status wt_resolve(const wt_frame_desc* desc, const float* accum, const float*
 wt_status wt_render(const wt_frame_desc* desc, const wt_fragments* frags, const float* bg_rgb, void* coeffs,
                     float* out, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* The build, evaluate and resolve of wt_render over a stream already binned into ws by wt_bin (same desc and
+ * ws_bytes). Writes out[P][3] and, if coeffs is not NULL, the coefficients (both overwritten). */
+wt_status wt_render_binned(const wt_frame_desc* desc, const void* ws, size_t ws_bytes, const float* bg_rgb,
+                           void* coeffs, float* out, hipStream_t stream);
+
 /* Gradient of a scalar loss through wt_render with respect to alpha and colour. grad_out is dL/dout
  * [P][3]; coeffs are the frame's complete coefficients and accum its accumulation (as written by wt_build
  * and wt_evaluate, or recomputed). Writes grad_alpha[F * channels] and grad_rgb[F * 3] (overwritten, in

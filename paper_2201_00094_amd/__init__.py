@@ -6,5 +6,5 @@ if the library has not been built.
 """
 from ._lib import WTError, load as load_library  # noqa: F401
 from .wt import (FrameSpec, Fragments, Workspace, backward, bin, build, build_binned, dropped_count,  # noqa: F401
-                 evaluate, evaluate_binned, render, resolve, workspace_bytes)
+                 evaluate, evaluate_binned, render, render_binned, resolve, workspace_bytes)
 from .autograd import WaveletComposite, composite  # noqa: F401

@@ -37,6 +37,7 @@ SIGNATURES = {
     "wt_evaluate": (C.c_int, [_D, _F, _vp, _vp, _vp, _sz, _st]),
     "wt_resolve": (C.c_int, [_D, _vp, C.POINTER(C.c_float), _vp, _st]),
     "wt_render": (C.c_int, [_D, _F, C.POINTER(C.c_float), _vp, _vp, _vp, _sz, _st]),
+    "wt_render_binned": (C.c_int, [_D, _vp, _sz, C.POINTER(C.c_float), _vp, _vp, _st]),
     "wt_backward": (C.c_int, [_D, _F, _vp, _vp, C.POINTER(C.c_float), _vp, _vp, _vp, _vp, _sz, _st]),
     "wt_dropped_count": (C.c_int, [_vp, _sz, C.POINTER(C.c_uint64), _st]),
     "wt_last_error": (C.c_char_p, []),

@@ -103,7 +103,7 @@ wt_status wt_build_binned(const wt_frame_desc* desc, void* coeffs, const void* w
   WT_TRY(check_lds(g));
   wt::Layout l;
   WT_TRY(check_ws(g, ws, ws_bytes, 0, &l));
-  hipError_t e = wt::launch_build(g, wt::binned_view(g, l, ws), coeffs, stream);
+  hipError_t e = wt::launch_build(g, wt::binned_view(g, l, ws, false), coeffs, stream);
   if (e != hipSuccess) return hip_fail(e, "wt_build");
   return WT_OK;
 }
@@ -116,7 +116,7 @@ wt_status wt_evaluate_binned(const wt_frame_desc* desc, const void* coeffs, floa
   WT_TRY(check_lds(g));
   wt::Layout l;
   WT_TRY(check_ws(g, ws, ws_bytes, 0, &l));
-  hipError_t e = wt::launch_evaluate(g, wt::binned_view(g, l, ws), coeffs, accum, stream);
+  hipError_t e = wt::launch_evaluate(g, wt::binned_view(g, l, ws, false), coeffs, accum, stream);
   if (e != hipSuccess) return hip_fail(e, "wt_evaluate");
   return WT_OK;
 }
@@ -156,8 +156,21 @@ wt_status wt_render(const wt_frame_desc* desc, const wt_fragments* frags, const 
   WT_TRY(check_ws(g, ws, ws_bytes, frags->count, &l));
   hipError_t e = wt::launch_bin(g, *frags, ws, l, false, stream);
   if (e != hipSuccess) return hip_fail(e, "wt_render (bin)");
-  e = wt::launch_render(g, wt::binned_view(g, l, ws), bg_rgb, coeffs, out, stream);
+  e = wt::launch_render(g, wt::binned_view(g, l, ws, false), bg_rgb, coeffs, out, stream);
   if (e != hipSuccess) return hip_fail(e, "wt_render");
+  return WT_OK;
+}
+
+wt_status wt_render_binned(const wt_frame_desc* desc, const void* ws, size_t ws_bytes, const float* bg_rgb,
+                           void* coeffs, float* out, hipStream_t stream) {
+  WT_TRY(check_desc(desc));
+  if (!bg_rgb || !out) return fail(WT_ERR_INVALID, "bg_rgb or out is NULL");
+  const wt::Geom g = wt::make_geom(*desc);
+  WT_TRY(check_lds(g));
+  wt::Layout l;
+  WT_TRY(check_ws(g, ws, ws_bytes, 0, &l));
+  hipError_t e = wt::launch_render(g, wt::binned_view(g, l, ws, false), bg_rgb, coeffs, out, stream);
+  if (e != hipSuccess) return hip_fail(e, "wt_render_binned");
   return WT_OK;
 }
 
@@ -176,7 +189,7 @@ wt_status wt_backward(const wt_frame_desc* desc, const wt_fragments* frags, cons
   WT_TRY(check_ws(g, ws, ws_bytes, frags->count, &l));
   hipError_t e = wt::launch_bin(g, *frags, ws, l, true, stream);
   if (e != hipSuccess) return hip_fail(e, "wt_backward (bin)");
-  e = wt::launch_backward(g, wt::binned_view(g, l, ws), coeffs, accum, bg_rgb, grad_out, grad_alpha, grad_rgb,
+  e = wt::launch_backward(g, wt::binned_view(g, l, ws, true), coeffs, accum, bg_rgb, grad_out, grad_alpha, grad_rgb,
                           frags->count, stream);
   if (e == hipErrorNotSupported) return fail(WT_ERR_UNSUPPORTED, "wt_backward: not available for this frame");
   if (e != hipSuccess) return hip_fail(e, "wt_backward");

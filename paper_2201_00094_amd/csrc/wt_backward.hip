@@ -24,42 +24,44 @@ constexpr int kBwdThreads = 512;
 
 __device__ __forceinline__ float clamp01_b(float x) { return fminf(fmaxf(x, 0.f), 1.f); }
 
-__device__ __forceinline__ float cell_value(const float* cf, const Geom& g, uint32_t j, bool cells) {
-  if (cells) return cf[j];
+// Cell value Abar_j of one pixel/channel whose rows are TP floats apart: read directly (cells) or
+// synthesised from the coefficients.
+__device__ __forceinline__ float cell_value(const float* cf, uint32_t TP, const Geom& g, uint32_t j, bool cells) {
+  if (cells) return cf[j * TP];
   float A = cf[0];
   for (uint32_t n = 0; n <= g.rank; ++n) {
     const uint32_t k = j >> (g.L - n);
-    const float d = cf[(1u << n) + k];
+    const float d = cf[((1u << n) + k) * TP];
     A += ((j >> (g.L - 1 - n)) & 1u) ? -d : d;
   }
   return A;
 }
 
 template <int M>
-__device__ __forceinline__ void synth_fixed_b(float* cf) {
+__device__ __forceinline__ void synth_fixed_b(float* cf, uint32_t TP) {
   float v[M];
   v[0] = cf[0];
 #pragma unroll
   for (int s = 1; s < M; s <<= 1) {
 #pragma unroll
     for (int k = s - 1; k >= 0; --k) {
-      const float d = cf[s + k];
+      const float d = cf[(s + k) * TP];
       const float a = v[k];
       v[2 * k] = a + d;
       v[2 * k + 1] = a - d;
     }
   }
 #pragma unroll
-  for (int j = 0; j < M; ++j) cf[j] = v[j];
+  for (int j = 0; j < M; ++j) cf[j * TP] = v[j];
 }
 
-__device__ __forceinline__ void synth_b(float* cf, uint32_t M) {
+__device__ __forceinline__ void synth_b(float* cf, uint32_t TP, uint32_t M) {
   switch (M) {
-    case 2: synth_fixed_b<2>(cf); break;
-    case 4: synth_fixed_b<4>(cf); break;
-    case 8: synth_fixed_b<8>(cf); break;
-    case 16: synth_fixed_b<16>(cf); break;
-    default: synth_fixed_b<32>(cf); break;
+    case 2: synth_fixed_b<2>(cf, TP); break;
+    case 4: synth_fixed_b<4>(cf, TP); break;
+    case 8: synth_fixed_b<8>(cf, TP); break;
+    case 16: synth_fixed_b<16>(cf, TP); break;
+    default: synth_fixed_b<32>(cf, TP); break;
   }
 }
 
@@ -68,143 +70,139 @@ __global__ void k_zero_f32(float* __restrict__ p, uint64_t n) {
     p[i] = 0.f;
 }
 
+template <int C>
+struct BFrag {
+  uint32_t lp, src;
+  float x, al[C], rgb[3];
+};
+
+// Record i of a binning made with stream indices; false for a NaN fragment.
+template <int C>
+__device__ __forceinline__ bool load_bfrag(const Binned& b, uint32_t i, BFrag<C>& f) {
+  const uint32_t* r = b.rec + (uint64_t)i * b.D;
+  f.lp = r[0];
+  f.x = __uint_as_float(r[1]);
+  bool bad = isnan(f.x);
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    f.al[c] = __uint_as_float(r[2 + c]);
+    bad |= isnan(f.al[c]);
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) f.rgb[q] = __uint_as_float(r[2 + C + q]);
+  f.src = r[5 + C];
+  return !bad;
+}
+
+// LDS rows of TP values: ladj [C*M] FP64 cell adjoints, then their suffix sums; lc [C*M] FP32 cell values;
+// lg [3] dL/dout; lT [C] background transmittance.
 template <int C, typename TS, bool CELLS>
 __global__ __launch_bounds__(kBwdThreads) void k_backward(Binned b, Geom g, const TS* __restrict__ coeffs,
                                                           const float* __restrict__ accum, float bg0, float bg1,
                                                           float bg2, const float* __restrict__ grad_out,
                                                           float* __restrict__ grad_alpha,
                                                           float* __restrict__ grad_rgb) {
-  extern __shared__ float smem[];
-  const uint32_t per = C * g.M, nel = g.tile_px * per;
-  float* lc = smem;             // cell values [tile_px][C][M]
-  float* ladj = lc + nel;       // cell adjoints, then their suffix sums
-  float* lg = ladj + nel;       // dL/dout [tile_px][3]
-  float* lT = lg + g.tile_px * 3;  // background transmittance [tile_px][C]
+  extern __shared__ double smem_b[];
+  const uint32_t TP = g.tile_px, per = C * g.M;
+  double* ladj = smem_b;
+  float* lc = (float*)(ladj + per * TP);
+  float* lg = lc + per * TP;
+  float* lT = lg + 3 * TP;
   const uint32_t t = blockIdx.x;
   const uint32_t x0 = (t % g.tilesX) * g.TW, y0 = (t / g.tilesX) * g.TH;
-  for (uint32_t e = threadIdx.x; e < nel; e += blockDim.x) {
-    const uint32_t lp = e / per, rem = e - lp * per;
+  for (uint32_t lp = threadIdx.x; lp < TP; lp += blockDim.x) {
     const uint32_t px = x0 + (lp & (g.TW - 1)), py = y0 + lp / g.TW;
     const bool in = px < g.W && py < g.H;
-    lc[e] = in ? widen<TS>(coeffs[((uint64_t)py * g.W + px) * per + rem]) : 0.f;
-    ladj[e] = 0.f;
-  }
-  for (uint32_t e = threadIdx.x; e < g.tile_px * 3; e += blockDim.x) {
-    const uint32_t lp = e / 3, q = e - lp * 3;
-    const uint32_t px = x0 + (lp & (g.TW - 1)), py = y0 + lp / g.TW;
-    lg[e] = (px < g.W && py < g.H) ? grad_out[((uint64_t)py * g.W + px) * 3 + q] : 0.f;
-  }
-  for (uint32_t e = threadIdx.x; e < g.tile_px * C; e += blockDim.x) {
-    const uint32_t lp = e / C, c = e - lp * C;
-    const uint32_t px = x0 + (lp & (g.TW - 1)), py = y0 + lp / g.TW;
-    float T = 0.f;
-    if (px < g.W && py < g.H) {
-      const uint64_t p = (uint64_t)py * g.W + px;
-      T = __expf(-accum[p * g.AW + (C == 1 ? 3 : 4 + c)]);
+    const uint64_t p = in ? (uint64_t)py * g.W + px : 0;
+    for (uint32_t e = 0; e < per; ++e) {
+      lc[e * TP + lp] = in ? widen<TS>(coeffs[p * per + e]) : 0.f;
+      ladj[e * TP + lp] = 0.0;
     }
-    lT[e] = T;
+    for (uint32_t q = 0; q < 3; ++q) lg[q * TP + lp] = in ? grad_out[p * 3 + q] : 0.f;
+    for (uint32_t c = 0; c < C; ++c)
+      lT[c * TP + lp] = in ? __expf(-accum[p * g.AW + (C == 1 ? 3 : 4 + c)]) : 0.f;
   }
   __syncthreads();
   if (CELLS)
-    for (uint32_t q = threadIdx.x; q < g.tile_px * C; q += blockDim.x) synth_b(lc + q * g.M, g.M);
+    for (uint32_t q = threadIdx.x; q < TP * C; q += blockDim.x) {
+      const uint32_t c = q / TP, lp = q - c * TP;
+      synth_b(lc + (c * g.M) * TP + lp, TP, g.M);
+    }
   __syncthreads();
   const uint32_t beg = b.offsets[t * g.NX], end = b.offsets[(t + 1) * g.NX];
   // pass 1: cell adjoints
   for (uint32_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
-    const uint32_t lp = b.lpx[i];
-    float x = b.x[i];
-    float al[C];
-    bool bad = isnan(x);
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-      al[c] = b.alpha[c * b.cap + i];
-      bad |= isnan(al[c]);
-    }
-    if (bad) continue;
-    float rgb[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) rgb[q] = b.rgb[q * b.cap + i];
-    x = clamp01_b(x);
+    BFrag<C> f;
+    if (!load_bfrag<C>(b, i, f)) continue;
+    const float x = clamp01_b(f.x);
     const float u = x * (float)g.M;
     const uint32_t j = min((uint32_t)u, g.M - 1);
     const float tt = u - (float)j;
-    const float* gp = lg + lp * 3;
+    const float gq[3] = {lg[f.lp], lg[TP + f.lp], lg[2 * TP + f.lp]};
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      const float* cf = lc + (lp * C + c) * g.M;
-      const float hi = cell_value(cf, g, j, CELLS);
-      const float lo = j ? cell_value(cf, g, j - 1, CELLS) : 0.f;
+      const float* cf = lc + (c * g.M) * TP + f.lp;
+      const float hi = cell_value(cf, TP, g, j, CELLS);
+      const float lo = j ? cell_value(cf, TP, g, j - 1, CELLS) : 0.f;
       const float v = __expf(-fmaf(tt, hi, (1.f - tt) * lo));
-      const float alc = alpha_clamped(al[c]);
-      const float gc = (C == 1) ? (gp[0] * rgb[0] + gp[1] * rgb[1] + gp[2] * rgb[2]) : gp[c] * rgb[c];
+      const float alc = alpha_clamped(f.al[c]);
+      const float gc = (C == 1) ? (gq[0] * f.rgb[0] + gq[1] * f.rgb[1] + gq[2] * f.rgb[2]) : gq[c] * f.rgb[c];
       const float s = alc * v * gc;
-      float* adj = ladj + (lp * C + c) * g.M;
-      if (j) atomicAdd(adj + j - 1, -s * (1.f - tt));
-      atomicAdd(adj + j, -s * tt);
+      double* adj = ladj + (c * g.M) * TP + f.lp;
+      if (j) atomicAdd(adj + (j - 1) * TP, (double)(-s * (1.f - tt)));
+      atomicAdd(adj + j * TP, (double)(-s * tt));
     }
   }
   __syncthreads();
   // suffix sums of the cell adjoints
-  for (uint32_t q = threadIdx.x; q < g.tile_px * C; q += blockDim.x) {
-    float* adj = ladj + q * g.M;
-    float run = 0.f;
+  for (uint32_t q = threadIdx.x; q < TP * C; q += blockDim.x) {
+    const uint32_t c = q / TP, lp = q - c * TP;
+    double* adj = ladj + (c * g.M) * TP + lp;
+    double run = 0.0;
     for (int m = (int)g.M - 1; m >= 0; --m) {
-      run += adj[m];
-      adj[m] = run;
+      run += adj[m * TP];
+      adj[m * TP] = run;
     }
   }
   __syncthreads();
   // pass 2: per-fragment gradients, written at the fragment's stream position
   const float bg[3] = {bg0, bg1, bg2};
   for (uint32_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
-    const uint32_t lp = b.lpx[i];
-    float x = b.x[i];
-    float al[C];
-    bool bad = isnan(x);
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-      al[c] = b.alpha[c * b.cap + i];
-      bad |= isnan(al[c]);
-    }
-    if (bad) continue;
-    const uint64_t src = b.idx[i];
-    float rgb[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) rgb[q] = b.rgb[q * b.cap + i];
-    x = clamp01_b(x);
+    BFrag<C> f;
+    if (!load_bfrag<C>(b, i, f)) continue;
+    const uint64_t src = f.src;
+    const float x = clamp01_b(f.x);
     const float u = x * (float)g.M;
     const uint32_t j = min((uint32_t)u, g.M - 1);
     const float tt = u - (float)j;
-    const float* gp = lg + lp * 3;
+    const float gq[3] = {lg[f.lp], lg[TP + f.lp], lg[2 * TP + f.lp]};
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      const float* cf = lc + (lp * C + c) * g.M;
-      const float hi = cell_value(cf, g, j, CELLS);
-      const float lo = j ? cell_value(cf, g, j - 1, CELLS) : 0.f;
+      const float* cf = lc + (c * g.M) * TP + f.lp;
+      const float hi = cell_value(cf, TP, g, j, CELLS);
+      const float lo = j ? cell_value(cf, TP, g, j - 1, CELLS) : 0.f;
       const float v = __expf(-fmaf(tt, hi, (1.f - tt) * lo));
-      const float alc = alpha_clamped(al[c]);
-      const float* S = ladj + (lp * C + c) * g.M;
-      const float Sj = S[j];
-      const float Sj1 = (j + 1 < g.M) ? S[j + 1] : 0.f;
-      const float through_cells = ((float)(j + 1) - u) * (Sj - Sj1) + Sj1;
-      const float gbg = (C == 1) ? (gp[0] * bg[0] + gp[1] * bg[1] + gp[2] * bg[2]) : gp[c] * bg[c];
-      const float dLda = through_cells - gbg * lT[lp * C + c];
-      const float gc = (C == 1) ? (gp[0] * rgb[0] + gp[1] * rgb[1] + gp[2] * rgb[2]) : gp[c] * rgb[c];
-      const bool inside = al[c] > 0.f && al[c] < kAlphaMax;
+      const float alc = alpha_clamped(f.al[c]);
+      const double* S = ladj + (c * g.M) * TP + f.lp;
+      const double Sj = S[j * TP];
+      const double Sj1 = (j + 1 < g.M) ? S[(j + 1) * TP] : 0.0;
+      const float through_cells = (float)(((double)(j + 1) - (double)u) * (Sj - Sj1) + Sj1);
+      const float gbg = (C == 1) ? (gq[0] * bg[0] + gq[1] * bg[1] + gq[2] * bg[2]) : gq[c] * bg[c];
+      const float dLda = through_cells - gbg * lT[c * TP + f.lp];
+      const float gc = (C == 1) ? (gq[0] * f.rgb[0] + gq[1] * f.rgb[1] + gq[2] * f.rgb[2]) : gq[c] * f.rgb[c];
+      const bool inside = f.al[c] > 0.f && f.al[c] < kAlphaMax;
       grad_alpha[src * C + c] = inside ? v * gc + dLda / (1.f - alc) : 0.f;
       if (C == 1) {
 #pragma unroll
-        for (int q = 0; q < 3; ++q) grad_rgb[src * 3 + q] = gp[q] * alc * v;
+        for (int q = 0; q < 3; ++q) grad_rgb[src * 3 + q] = gq[q] * alc * v;
       } else {
-        grad_rgb[src * 3 + c] = gp[c] * alc * v;
+        grad_rgb[src * 3 + c] = gq[c] * alc * v;
       }
     }
   }
 }
 
-size_t lds_backward_bytes(const Geom& g) {
-  return (size_t)g.tile_px * (2 * g.C * g.M + 3 + g.C) * sizeof(float);
-}
+size_t lds_backward_bytes(const Geom& g) { return (size_t)g.tile_px * (12 * g.C * g.M + 4 * (3 + g.C)); }
 
 hipError_t launch_backward(const Geom& g, const Binned& b, const void* coeffs, const float* accum, const float* bg,
                            const float* grad_out, float* grad_alpha, float* grad_rgb, uint64_t count,

@@ -1,19 +1,23 @@
 // Ingest and screen-tile binning of an unordered fragment stream.
 //
-// The paper builds and evaluates inside a raster pipeline, where fragments of one screen region arrive on
+// The paper builds and evaluates inside a raster pipeline, where the fragments of one screen region arrive on
 // the same shader core (section 2.1). A stored stream carries no such locality, and on this GPU per-fragment
 // random atomics into a frame-sized coefficient buffer run at a few billion fragments per second. So the
-// stream is first regrouped by screen tile (a counting sort: histogram, scan, scatter), after which every
-// per-pixel update of the build and evaluate passes happens in the LDS of the compute unit owning the tile.
+// stream is first regrouped by screen tile with a counting sort (histogram, scan, scatter), after which every
+// per-pixel update of the build and evaluate passes happens in the LDS of the compute unit that owns the tile.
 //
 // Kernels:
-//   k_hist     reads pixel ids (4 B/fragment); per-workgroup LDS histogram per tile; range drops counted.
-//   k_scan     exclusive scan of the (tile, class) counts into segment offsets and write cursors.
-//   k_scatter  per chunk of kChunk fragments: LDS count, one cursor reservation per touched tile, then each
-//              fragment is written (SoA) at its reserved slot. NaN fragments are counted and still binned;
-//              the tile kernels skip them.
-// A chunk's class is chunk % NX in both k_hist and k_scatter; with one chunk per scatter workgroup the class
-// is also the XCD the workgroup runs on, so each (tile, class) write frontier is filled inside one L2.
+//   k_hist            pixel ids (4 B/fragment) -> per-(class, tile) counts; range drops counted.
+//   k_scan            exclusive scan of the counts, tile-major, into segment offsets and write cursors.
+//   k_scatter_staged  one chunk of kChunk fragments per workgroup: vector loads into registers, LDS count
+//                     per tile, one cursor reservation per touched tile, records placed in LDS in tile order,
+//                     then written as a flat run of dwords so that consecutive lanes store consecutive
+//                     addresses inside each tile's run.
+//   k_scatter_direct  same reservation, records stored straight from registers (many tiles).
+//   k_scatter_global  one cursor atomic per fragment (very many tiles).
+// A chunk's class is chunk % NX in both k_hist and the scatter; with one chunk per scatter workgroup the class
+// is also the XCD the workgroup runs on, so each (tile, class) run is written from a single L2.
+// NaN fragments are counted as dropped and still binned; the tile kernels skip them.
 #include <algorithm>
 
 #include "wt_common.h"
@@ -36,11 +40,13 @@ Geom make_geom(const wt_frame_desc& d, bool backward) {
   g.L = d.rank + 1;
   g.M = 1u << g.L;
   g.AW = (d.channels == 3) ? 8 : 4;
+  g.AL = (d.channels == 3) ? 6 : 4;
   g.dtype = d.coeff_dtype;
-  // Largest power-of-two tile whose FP32 coefficient tile fits the LDS budget, at most 32 x 32 pixels.
-  const uint32_t per_px = g.C * g.M * 4;
-  uint32_t px = std::max<uint32_t>(1, (backward ? kCoeffLdsBudget / 2 : kCoeffLdsBudget) / per_px);
-  px = std::min<uint32_t>(floor_pow2(px), 1024);
+  // Largest power-of-two tile whose LDS working set fits one compute unit: FP64 coefficient sums plus FP64
+  // accumulations (forward), or FP32 cells, FP64 cell adjoints and per-pixel gradient data (backward).
+  const uint32_t per_px = backward ? 12 * g.C * g.M + 4 * (3 + g.C) : 8 * (g.C * g.M + g.AL);
+  uint32_t px = std::max<uint32_t>(1, kLdsBytes / per_px);
+  px = std::min<uint32_t>(floor_pow2(px), kMaxTilePx);
   uint32_t e = 0;
   while ((1u << e) < px) ++e;
   g.TW = 1u << ((e + 1) / 2);
@@ -49,7 +55,7 @@ Geom make_geom(const wt_frame_desc& d, bool backward) {
   g.tilesX = (g.W + g.TW - 1) / g.TW;
   g.tilesY = (g.H + g.TH - 1) / g.TH;
   g.ntiles = g.tilesX * g.tilesY;
-  g.lds_bins = g.ntiles <= kMaxLdsBins ? 1 : 0;
+  g.lds_bins = g.ntiles <= kMaxLdsBins ? 2 : (g.ntiles <= 16384 ? 1 : 0);
   g.NX = g.lds_bins ? kClasses : 1;
   return g;
 }
@@ -67,16 +73,8 @@ Layout make_layout(const Geom& g, uint64_t cap) {
   o = align256(o + 4ull * (g.NX * (uint64_t)g.ntiles + 1));
   l.cursors = o;
   o = align256(o + 4ull * g.NX * g.ntiles);
-  l.lpx = o;
-  o = align256(o + 4ull * cap);
-  l.x = o;
-  o = align256(o + 4ull * cap);
-  l.alpha = o;
-  o = align256(o + 4ull * cap * g.C);
-  l.rgb = o;
-  o = align256(o + 12ull * cap);
-  l.idx = o;
-  o = align256(o + 4ull * cap);
+  l.records = o;
+  o = align256(o + 4ull * record_dwords(g.C, true) * cap);
   l.total = o;
   l.cap = cap;
   return l;
@@ -85,43 +83,33 @@ Layout make_layout(const Geom& g, uint64_t cap) {
 uint64_t capacity_for(const Geom& g, size_t ws_bytes) {
   const size_t fixed = make_layout(g, 0).total;
   if (ws_bytes < fixed) return 0;
-  const uint64_t per = 4 + 4 + 4ull * g.C + 12 + 4;
+  const uint64_t per = 4ull * record_dwords(g.C, true);
   uint64_t cap = (ws_bytes - fixed) / per;
   while (cap > 0 && make_layout(g, cap).total > ws_bytes) --cap;
   return cap;
 }
 
-Binned binned_view(const Geom& g, const Layout& l, const void* ws) {
+Binned binned_view(const Geom& g, const Layout& l, const void* ws, bool with_index) {
   const char* b = (const char*)ws;
   Binned v;
   v.offsets = (const uint32_t*)(b + l.offsets);
-  v.lpx = (const uint32_t*)(b + l.lpx);
-  v.x = (const float*)(b + l.x);
-  v.alpha = (const float*)(b + l.alpha);
-  v.rgb = (const float*)(b + l.rgb);
-  v.idx = (const uint32_t*)(b + l.idx);
-  v.cap = l.cap;
-  (void)g;
+  v.rec = (const uint32_t*)(b + l.records);
+  v.D = record_dwords(g.C, with_index);
   return v;
 }
-
-struct BinOut {
-  uint32_t* lpx;
-  float* x;
-  float* alpha;
-  float* rgb;
-  uint32_t* idx;  // nullptr: stream index not recorded
-  uint64_t cap;
-};
 
 __global__ void k_fill_u32(uint32_t* __restrict__ p, uint64_t n, uint32_t v) {
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
     p[i] = v;
 }
 
-__global__ __launch_bounds__(256) void k_hist_lds(const uint32_t* __restrict__ pixel, uint32_t F, Geom g,
-                                                  uint32_t* __restrict__ counts,
-                                                  unsigned long long* __restrict__ dropped) {
+// ------------------------------------------------------------------------------------------------ histogram
+
+constexpr int kHistThreads = 256;
+
+__global__ __launch_bounds__(kHistThreads) void k_hist_lds(const uint32_t* __restrict__ pixel, uint32_t F, Geom g,
+                                                           int vec, uint32_t* __restrict__ counts,
+                                                           unsigned long long* __restrict__ dropped) {
   extern __shared__ uint32_t lh[];
   for (uint32_t t = threadIdx.x; t < g.ntiles; t += blockDim.x) lh[t] = 0;
   __syncthreads();
@@ -129,14 +117,33 @@ __global__ __launch_bounds__(256) void k_hist_lds(const uint32_t* __restrict__ p
   const uint32_t nchunks = (uint32_t)(((uint64_t)F + kChunk - 1) / kChunk);
   uint32_t nd = 0;
   for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
-    const uint64_t base = (uint64_t)c * kChunk;
-    const uint64_t end = std::min<uint64_t>(base + kChunk, F);
-    for (uint64_t i = base + threadIdx.x; i < end; i += blockDim.x) {
-      const uint32_t p = pixel[i];
-      if (p < g.P)
-        atomicAdd(&lh[tile_of(g, p)], 1u);
-      else
-        ++nd;
+    const uint32_t base = c * kChunk;
+    const uint32_t n = std::min<uint32_t>(kChunk, F - base);
+    if (vec && n == kChunk) {
+      // kChunk / 4 uint4 per chunk, kChunk / (4 * kHistThreads) per thread, all issued before use
+      constexpr int V = kChunk / (4 * kHistThreads);
+      uint4 q[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) q[v] = ((const uint4*)(pixel + base))[v * kHistThreads + threadIdx.x];
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const uint32_t ps[4] = {q[v].x, q[v].y, q[v].z, q[v].w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          if (ps[k] < g.P)
+            atomicAdd(&lh[tile_of(g, ps[k])], 1u);
+          else
+            ++nd;
+        }
+      }
+    } else {
+      for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const uint32_t p = pixel[base + i];
+        if (p < g.P)
+          atomicAdd(&lh[tile_of(g, p)], 1u);
+        else
+          ++nd;
+      }
     }
   }
   __syncthreads();
@@ -148,7 +155,7 @@ __global__ __launch_bounds__(256) void k_hist_lds(const uint32_t* __restrict__ p
   if ((threadIdx.x & 63) == 0 && nd) atomicAdd(dropped, (unsigned long long)nd);
 }
 
-// Fallback for very many tiles (large ranks on large frames): one global atomic per fragment, one class.
+// Fallback for very many tiles: one global atomic per fragment, one class.
 __global__ __launch_bounds__(256) void k_hist_global(const uint32_t* __restrict__ pixel, uint32_t F, Geom g,
                                                      uint32_t* __restrict__ counts,
                                                      unsigned long long* __restrict__ dropped) {
@@ -163,6 +170,8 @@ __global__ __launch_bounds__(256) void k_hist_global(const uint32_t* __restrict_
   nd = wave_sum(nd);
   if ((threadIdx.x & 63) == 0 && nd) atomicAdd(dropped, (unsigned long long)nd);
 }
+
+// ------------------------------------------------------------------------------------------------ scan
 
 constexpr int kScanThreads = 1024;
 constexpr int kScanItems = 16;
@@ -213,69 +222,272 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t* __restric
   if (tid == 0) offsets[n] = carry;
 }
 
-__device__ __forceinline__ void put_fragment(const wt_fragments& f, const Geom& g, const BinOut& o, uint64_t i,
-                                             uint32_t pos, uint32_t local, uint32_t& nan_count) {
-  const float d = f.depth[i];
-  bool bad = isnan(d);
-  o.lpx[pos] = local;
-  o.x[pos] = d;
-  for (uint32_t c = 0; c < g.C; ++c) {
-    const float a = f.alpha[i * g.C + c];
-    bad |= isnan(a);
-    o.alpha[c * o.cap + pos] = a;
-  }
+// ------------------------------------------------------------------------------------------------ scatter
+
+constexpr uint32_t kPer = kChunk / kScatterThreads;  // fragments per thread
+static_assert(kPer % 4 == 0, "vector loads take fragments four at a time");
+
+// One chunk's fragments, held in registers by the thread that loaded them.
+template <int C>
+struct ChunkRegs {
+  uint32_t p[kPer];
+  float x[kPer];
+  float a[C * kPer];
+  float c[3 * kPer];
+};
+
+// Loads fragments [i0, i0 + kPer) of the chunk at base; out-of-range slots get pixel id 0xffffffff.
+template <int C>
+__device__ __forceinline__ void load_chunk(const wt_fragments& f, uint32_t base, uint32_t i0, uint32_t n, int vec,
+                                           ChunkRegs<C>& r) {
+  if (vec && i0 + kPer <= n) {
 #pragma unroll
-  for (int q = 0; q < 3; ++q) o.rgb[q * o.cap + pos] = f.rgb[i * 3 + q];
-  if (o.idx) o.idx[pos] = (uint32_t)i;
-  nan_count += bad ? 1u : 0u;
+    for (uint32_t v = 0; v < kPer / 4; ++v) {
+      const uint64_t i = (uint64_t)base + i0 + 4 * v;
+      const uint4 p4 = *(const uint4*)(f.pixel + i);
+      const float4 x4 = *(const float4*)(f.depth + i);
+      r.p[4 * v + 0] = p4.x; r.p[4 * v + 1] = p4.y; r.p[4 * v + 2] = p4.z; r.p[4 * v + 3] = p4.w;
+      r.x[4 * v + 0] = x4.x; r.x[4 * v + 1] = x4.y; r.x[4 * v + 2] = x4.z; r.x[4 * v + 3] = x4.w;
+#pragma unroll
+      for (int q = 0; q < C; ++q) {
+        const float4 a4 = *(const float4*)(f.alpha + C * i + 4 * q);
+        r.a[4 * C * v + 4 * q + 0] = a4.x; r.a[4 * C * v + 4 * q + 1] = a4.y;
+        r.a[4 * C * v + 4 * q + 2] = a4.z; r.a[4 * C * v + 4 * q + 3] = a4.w;
+      }
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const float4 c4 = *(const float4*)(f.rgb + 3 * i + 4 * q);
+        r.c[12 * v + 4 * q + 0] = c4.x; r.c[12 * v + 4 * q + 1] = c4.y;
+        r.c[12 * v + 4 * q + 2] = c4.z; r.c[12 * v + 4 * q + 3] = c4.w;
+      }
+    }
+  } else {
+#pragma unroll
+    for (uint32_t k = 0; k < kPer; ++k) {
+      const uint32_t li = i0 + k;
+      r.p[k] = 0xffffffffu;
+      if (li < n) {
+        const uint64_t i = (uint64_t)base + li;
+        r.p[k] = f.pixel[i];
+        r.x[k] = f.depth[i];
+#pragma unroll
+        for (int q = 0; q < C; ++q) r.a[C * k + q] = f.alpha[C * i + q];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) r.c[3 * k + q] = f.rgb[3 * i + q];
+      }
+    }
+  }
 }
 
-__global__ __launch_bounds__(256) void k_scatter_lds(wt_fragments f, Geom g, uint32_t* __restrict__ cursors, BinOut o,
-                                                     unsigned long long* __restrict__ dropped) {
-  extern __shared__ uint32_t lh[];
+template <int C>
+__device__ __forceinline__ bool has_nan(const ChunkRegs<C>& r, uint32_t k) {
+  bool bad = isnan(r.x[k]);
+#pragma unroll
+  for (int q = 0; q < C; ++q) bad |= isnan(r.a[C * k + q]);
+  return bad;
+}
+
+// Record dword j of fragment k (tile-local pixel `local`, stream index `src`).
+template <int C>
+__device__ __forceinline__ uint32_t record_word(const ChunkRegs<C>& r, uint32_t k, uint32_t local, uint32_t src,
+                                                uint32_t j) {
+  if (j == 0) return local;
+  if (j == 1) return __float_as_uint(r.x[k]);
+  if (j < 2 + C) return __float_as_uint(r.a[C * k + (j - 2)]);
+  if (j < 5 + C) return __float_as_uint(r.c[3 * k + (j - 2 - C)]);
+  return src;
+}
+
+// Block-wide exclusive scan of cnt[0, nt) in place; wsum holds kScatterThreads / 64 partial sums.
+__device__ __forceinline__ void block_scan_inplace(uint32_t* cnt, uint32_t nt, uint32_t* wsum) {
+  const uint32_t per = (nt + kScatterThreads - 1) / kScatterThreads;
+  const uint32_t t0 = threadIdx.x * per, t1 = std::min(t0 + per, nt);
+  uint32_t s = 0;
+  for (uint32_t t = t0; t < t1; ++t) s += cnt[t];
+  const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t inc = s;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t v = __shfl_up(inc, o, 64);
+    if (lane >= (uint32_t)o) inc += v;
+  }
+  if (lane == 63) wsum[wv] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t a = 0;
+    for (uint32_t w = 0; w < kScatterThreads / 64; ++w) {
+      const uint32_t v = wsum[w];
+      wsum[w] = a;
+      a += v;
+    }
+  }
+  __syncthreads();
+  uint32_t run = wsum[wv] + inc - s;
+  for (uint32_t t = t0; t < t1; ++t) {
+    const uint32_t v = cnt[t];
+    cnt[t] = run;
+    run += v;
+  }
+}
+
+// LDS: srec[kChunk][D] sorted records, sg[kChunk] global slot of each sorted record, cnt[nt], gb[nt].
+template <int C, bool IDX>
+__global__ __launch_bounds__(kScatterThreads) void k_scatter_staged(wt_fragments f, Geom g, int vec,
+                                                                    uint32_t* __restrict__ cursors,
+                                                                    uint32_t* __restrict__ out,
+                                                                    unsigned long long* __restrict__ dropped) {
+  constexpr uint32_t D = record_dwords(C, IDX);
+  extern __shared__ uint32_t sm[];
+  uint32_t* srec = sm;
+  uint32_t* sg = srec + kChunk * D;
+  uint32_t* cnt = sg + kChunk;
+  uint32_t* gb = cnt + g.ntiles;
+  __shared__ uint32_t wsum[kScatterThreads / 64];
+  __shared__ uint32_t nvalid;
   const uint32_t F = (uint32_t)f.count;
   const uint32_t cls = blockIdx.x % g.NX;
-  const uint64_t base = (uint64_t)blockIdx.x * kChunk;
-  const uint64_t end = std::min<uint64_t>(base + kChunk, F);
-  for (uint32_t t = threadIdx.x; t < g.ntiles; t += blockDim.x) lh[t] = 0;
+  const uint32_t base = blockIdx.x * kChunk;
+  const uint32_t n = std::min<uint32_t>(kChunk, F - base);
+  for (uint32_t t = threadIdx.x; t < g.ntiles; t += blockDim.x) cnt[t] = 0;
+  if (threadIdx.x == 0) nvalid = 0;
+  ChunkRegs<C> r;
+  const uint32_t i0 = threadIdx.x * kPer;
+  load_chunk<C>(f, base, i0, n, vec, r);
   __syncthreads();
-  for (uint64_t i = base + threadIdx.x; i < end; i += blockDim.x) {
-    const uint32_t p = f.pixel[i];
-    if (p < g.P) atomicAdd(&lh[tile_of(g, p)], 1u);
+  uint32_t tile[kPer], rank[kPer], local[kPer];
+  uint32_t nan_count = 0, mine = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < kPer; ++k) {
+    tile[k] = 0xffffffffu;
+    if (r.p[k] < g.P) {
+      tile_locate(g, r.p[k], tile[k], local[k]);
+      rank[k] = atomicAdd(&cnt[tile[k]], 1u);
+      nan_count += has_nan<C>(r, k) ? 1u : 0u;
+      ++mine;
+    }
+  }
+  mine = wave_sum(mine);
+  if ((threadIdx.x & 63) == 0 && mine) atomicAdd(&nvalid, mine);
+  __syncthreads();
+  for (uint32_t t = threadIdx.x; t < g.ntiles; t += blockDim.x) {
+    const uint32_t v = cnt[t];
+    gb[t] = v ? atomicAdd(&cursors[cls * g.ntiles + t], v) : 0u;
+  }
+  block_scan_inplace(cnt, g.ntiles, wsum);
+  __syncthreads();
+#pragma unroll
+  for (uint32_t k = 0; k < kPer; ++k) {
+    if (tile[k] == 0xffffffffu) continue;
+    const uint32_t sp = cnt[tile[k]] + rank[k];
+    uint32_t* d = srec + sp * D;
+#pragma unroll
+    for (uint32_t j = 0; j < D; ++j) d[j] = record_word<C>(r, k, local[k], base + i0 + k, j);
+    sg[sp] = gb[tile[k]] + rank[k];
+  }
+  __syncthreads();
+  const uint32_t nw = nvalid * D;
+  for (uint32_t j = threadIdx.x; j < nw; j += blockDim.x) {
+    const uint32_t s = j / D;
+    out[(uint64_t)sg[s] * D + (j - s * D)] = srec[j];
+  }
+  nan_count = wave_sum(nan_count);
+  if ((threadIdx.x & 63) == 0 && nan_count) atomicAdd(dropped, (unsigned long long)nan_count);
+}
+
+template <int C, bool IDX>
+__global__ __launch_bounds__(kScatterThreads) void k_scatter_direct(wt_fragments f, Geom g, int vec,
+                                                                    uint32_t* __restrict__ cursors,
+                                                                    uint32_t* __restrict__ out,
+                                                                    unsigned long long* __restrict__ dropped) {
+  constexpr uint32_t D = record_dwords(C, IDX);
+  extern __shared__ uint32_t cnt[];
+  const uint32_t F = (uint32_t)f.count;
+  const uint32_t cls = blockIdx.x % g.NX;
+  const uint32_t base = blockIdx.x * kChunk;
+  const uint32_t n = std::min<uint32_t>(kChunk, F - base);
+  for (uint32_t t = threadIdx.x; t < g.ntiles; t += blockDim.x) cnt[t] = 0;
+  ChunkRegs<C> r;
+  const uint32_t i0 = threadIdx.x * kPer;
+  load_chunk<C>(f, base, i0, n, vec, r);
+  __syncthreads();
+  uint32_t tile[kPer], rank[kPer], local[kPer];
+  uint32_t nan_count = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < kPer; ++k) {
+    tile[k] = 0xffffffffu;
+    if (r.p[k] < g.P) {
+      tile_locate(g, r.p[k], tile[k], local[k]);
+      rank[k] = atomicAdd(&cnt[tile[k]], 1u);
+      nan_count += has_nan<C>(r, k) ? 1u : 0u;
+    }
   }
   __syncthreads();
   for (uint32_t t = threadIdx.x; t < g.ntiles; t += blockDim.x) {
-    const uint32_t v = lh[t];
-    if (v) lh[t] = atomicAdd(&cursors[cls * g.ntiles + t], v);
+    const uint32_t v = cnt[t];
+    if (v) cnt[t] = atomicAdd(&cursors[cls * g.ntiles + t], v);
   }
   __syncthreads();
-  uint32_t nan_count = 0;
-  for (uint64_t i = base + threadIdx.x; i < end; i += blockDim.x) {
-    const uint32_t p = f.pixel[i];
-    if (p >= g.P) continue;
-    uint32_t tile, local;
-    tile_locate(g, p, tile, local);
-    const uint32_t pos = atomicAdd(&lh[tile], 1u);
-    put_fragment(f, g, o, i, pos, local, nan_count);
+#pragma unroll
+  for (uint32_t k = 0; k < kPer; ++k) {
+    if (tile[k] == 0xffffffffu) continue;
+    uint32_t* d = out + (uint64_t)(cnt[tile[k]] + rank[k]) * D;
+#pragma unroll
+    for (uint32_t j = 0; j < D; ++j) d[j] = record_word<C>(r, k, local[k], base + i0 + k, j);
   }
   nan_count = wave_sum(nan_count);
   if ((threadIdx.x & 63) == 0 && nan_count) atomicAdd(dropped, (unsigned long long)nan_count);
 }
 
-__global__ __launch_bounds__(256) void k_scatter_global(wt_fragments f, Geom g, uint32_t* __restrict__ cursors,
-                                                        BinOut o, unsigned long long* __restrict__ dropped) {
+template <int C, bool IDX>
+__global__ __launch_bounds__(kScatterThreads) void k_scatter_global(wt_fragments f, Geom g, int vec,
+                                                                    uint32_t* __restrict__ cursors,
+                                                                    uint32_t* __restrict__ out,
+                                                                    unsigned long long* __restrict__ dropped) {
+  constexpr uint32_t D = record_dwords(C, IDX);
+  const uint32_t F = (uint32_t)f.count;
+  const uint32_t base = blockIdx.x * kChunk;
+  const uint32_t n = std::min<uint32_t>(kChunk, F - base);
+  ChunkRegs<C> r;
+  const uint32_t i0 = threadIdx.x * kPer;
+  load_chunk<C>(f, base, i0, n, vec, r);
   uint32_t nan_count = 0;
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < f.count;
-       i += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t p = f.pixel[i];
-    if (p >= g.P) continue;
+#pragma unroll
+  for (uint32_t k = 0; k < kPer; ++k) {
+    if (r.p[k] >= g.P) continue;
     uint32_t tile, local;
-    tile_locate(g, p, tile, local);
-    const uint32_t pos = atomicAdd(&cursors[tile], 1u);
-    put_fragment(f, g, o, i, pos, local, nan_count);
+    tile_locate(g, r.p[k], tile, local);
+    nan_count += has_nan<C>(r, k) ? 1u : 0u;
+    uint32_t* d = out + (uint64_t)atomicAdd(&cursors[tile], 1u) * D;
+#pragma unroll
+    for (uint32_t j = 0; j < D; ++j) d[j] = record_word<C>(r, k, local, base + i0 + k, j);
   }
   nan_count = wave_sum(nan_count);
   if ((threadIdx.x & 63) == 0 && nan_count) atomicAdd(dropped, (unsigned long long)nan_count);
+}
+
+static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+template <int C, bool IDX>
+static hipError_t launch_scatter(const Geom& g, const wt_fragments& f, int vec, uint32_t* cursors, uint32_t* out,
+                                 unsigned long long* dropped, uint32_t nchunks, hipStream_t s) {
+  if (g.lds_bins == 2) {
+    constexpr uint32_t D = record_dwords(C, IDX);
+    const size_t lds = (size_t)(kChunk * D + kChunk + 2 * g.ntiles) * 4;
+    auto k = k_scatter_staged<C, IDX>;
+    if (lds > 65536) {
+      hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k, dim3(nchunks), dim3(kScatterThreads), lds, s, f, g, vec, cursors, out, dropped);
+  } else if (g.lds_bins == 1) {
+    const size_t lds = (size_t)g.ntiles * 4;
+    hipLaunchKernelGGL((k_scatter_direct<C, IDX>), dim3(nchunks), dim3(kScatterThreads), lds, s, f, g, vec, cursors,
+                       out, dropped);
+  } else {
+    hipLaunchKernelGGL((k_scatter_global<C, IDX>), dim3(nchunks), dim3(kScatterThreads), 0, s, f, g, vec, cursors,
+                       out, dropped);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_bin(const Geom& g, const wt_fragments& f, void* ws, const Layout& l, bool record_index,
@@ -284,6 +496,7 @@ hipError_t launch_bin(const Geom& g, const wt_fragments& f, void* ws, const Layo
   uint32_t* counts = (uint32_t*)(b + l.counts);
   uint32_t* offsets = (uint32_t*)(b + l.offsets);
   uint32_t* cursors = (uint32_t*)(b + l.cursors);
+  uint32_t* records = (uint32_t*)(b + l.records);
   unsigned long long* dropped = (unsigned long long*)(b + l.header);
   const uint64_t ncount = (uint64_t)g.NX * g.ntiles;
   // zero the header's counters and the tile counts (fill kernels: safe inside captured graphs)
@@ -292,29 +505,24 @@ hipError_t launch_bin(const Geom& g, const wt_fragments& f, void* ws, const Layo
                      counts, ncount, 0u);
   const uint32_t F = (uint32_t)f.count;
   const uint32_t nchunks = (uint32_t)(((uint64_t)F + kChunk - 1) / kChunk);
+  const int vec = aligned16(f.pixel) && aligned16(f.depth) && aligned16(f.alpha) && aligned16(f.rgb);
   if (F > 0) {
     if (g.lds_bins) {
       const uint32_t grid = std::min<uint32_t>(((nchunks + g.NX - 1) / g.NX) * g.NX, 2048);
-      hipLaunchKernelGGL(k_hist_lds, dim3(grid), dim3(256), g.ntiles * 4, s, f.pixel, F, g, counts, dropped);
+      hipLaunchKernelGGL(k_hist_lds, dim3(grid), dim3(kHistThreads), g.ntiles * 4, s, f.pixel, F, g, vec, counts,
+                         dropped);
     } else {
       hipLaunchKernelGGL(k_hist_global, dim3(2048), dim3(256), 0, s, f.pixel, F, g, counts, dropped);
     }
   }
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, counts, g, offsets, cursors);
-  if (F > 0) {
-    BinOut o;
-    o.lpx = (uint32_t*)(b + l.lpx);
-    o.x = (float*)(b + l.x);
-    o.alpha = (float*)(b + l.alpha);
-    o.rgb = (float*)(b + l.rgb);
-    o.idx = record_index ? (uint32_t*)(b + l.idx) : nullptr;
-    o.cap = l.cap;
-    if (g.lds_bins)
-      hipLaunchKernelGGL(k_scatter_lds, dim3(nchunks), dim3(256), g.ntiles * 4, s, f, g, cursors, o, dropped);
-    else
-      hipLaunchKernelGGL(k_scatter_global, dim3(4096), dim3(256), 0, s, f, g, cursors, o, dropped);
-  }
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || F == 0) return e;
+  if (g.C == 1)
+    return record_index ? launch_scatter<1, true>(g, f, vec, cursors, records, dropped, nchunks, s)
+                        : launch_scatter<1, false>(g, f, vec, cursors, records, dropped, nchunks, s);
+  return record_index ? launch_scatter<3, true>(g, f, vec, cursors, records, dropped, nchunks, s)
+                      : launch_scatter<3, false>(g, f, vec, cursors, records, dropped, nchunks, s);
 }
 
 }  // namespace wt

@@ -13,10 +13,11 @@ namespace wt {
 // and each XCD has its own L2. The binning keeps one write frontier per (tile, XCD class) so that the
 // partial cache lines of a frontier are filled inside a single L2 before they are written back.
 constexpr uint32_t kClasses = 8;
-constexpr uint32_t kChunk = 8192;          // fragments per scatter workgroup
-constexpr uint32_t kMaxLdsBins = 16384;    // tiles a per-workgroup LDS histogram can hold (64 KB)
-constexpr uint32_t kLdsBytes = 160 * 1024; // LDS of one CDNA4 compute unit
-constexpr uint32_t kCoeffLdsBudget = 128 * 1024;
+constexpr uint32_t kChunk = 2048;          // fragments per scatter workgroup (staged in LDS, sorted by tile)
+constexpr uint32_t kScatterThreads = 512;  // kChunk / kScatterThreads fragments per thread, a multiple of 4
+constexpr uint32_t kMaxLdsBins = 4096;     // tiles the LDS-staged scatter handles; beyond: global fallback
+constexpr uint32_t kLdsBytes = 160 * 1024; // LDS of one CDNA4 compute unit (also the per-workgroup limit)
+constexpr uint32_t kMaxTilePx = 2048;
 constexpr float kAlphaMax = 0.99999994f;   // 1 - 2^-24
 
 // Frame geometry as the kernels see it.
@@ -26,22 +27,23 @@ struct Geom {
   uint32_t TW, TH;       // tile extent in pixels (powers of two)
   uint32_t tilesX, tilesY, ntiles, tile_px;
   uint32_t NX;           // write-frontier classes (kClasses, or 1 when the tile count is large)
-  uint32_t lds_bins;     // 1: per-workgroup LDS histograms; 0: global atomics per fragment
-  uint32_t AW;           // accum floats per pixel: 4 (C = 1) or 8 (C = 3)
+  uint32_t lds_bins;     // 1: LDS-staged scatter; 0: global atomics per fragment
+  uint32_t AW;           // accum floats per pixel in global memory: 4 (C = 1) or 8 (C = 3)
+  uint32_t AL;           // accumulation floats per pixel in LDS: 4 (C = 1) or 6 (C = 3)
   uint32_t dtype;        // wt_dtype of the coefficient storage
 };
 
-// Device workspace: a header, the tile tables and the binned fragment arrays (structure of arrays).
+// Binned fragment record (array of structures, D dwords):
+//   [0] tile-local pixel index, [1] depth, [2 .. 2+C) alpha, [2+C .. 5+C) rgb, [5+C] stream index (optional)
+constexpr uint32_t record_dwords(uint32_t C, bool with_index) { return 5 + C + (with_index ? 1 : 0); }
+
+// Device workspace: a header, the tile tables and the binned records.
 struct Layout {
   size_t header;   // uint64 dropped counter + spare
   size_t counts;   // uint32 [NX][ntiles]
   size_t offsets;  // uint32 [ntiles * NX + 1], tile-major: segment (t, x) = [off[t*NX+x], off[t*NX+x+1])
   size_t cursors;  // uint32 [NX][ntiles]
-  size_t lpx;      // uint32 [cap] tile-local pixel index
-  size_t x;        // float [cap]
-  size_t alpha;    // float [C][cap]
-  size_t rgb;      // float [3][cap]
-  size_t idx;      // uint32 [cap] stream index of the binned fragment
+  size_t records;  // uint32 [cap][D], D up to record_dwords(C, true)
   size_t total;    // bytes
   uint64_t cap;    // fragment capacity
 };
@@ -49,21 +51,17 @@ struct Layout {
 // Pointers into a workspace, as passed to kernels.
 struct Binned {
   const uint32_t* offsets;
-  const uint32_t* lpx;
-  const float* x;
-  const float* alpha;  // channel c at alpha + c * cap
-  const float* rgb;    // channel q at rgb + q * cap
-  const uint32_t* idx;
-  uint64_t cap;
+  const uint32_t* rec;
+  uint32_t D;      // dwords per record
 };
 
-// backward = true picks tiles half the size: the gradient kernel holds cell values and their adjoints.
+// backward = true picks tiles for the gradient kernel, which holds cell values and their adjoints.
 Geom make_geom(const wt_frame_desc& d, bool backward = false);
 Layout make_layout(const Geom& g, uint64_t cap);
 uint64_t capacity_for(const Geom& g, size_t ws_bytes);
 size_t lds_tile_bytes(const Geom& g, bool with_accum);
 size_t lds_backward_bytes(const Geom& g);
-Binned binned_view(const Geom& g, const Layout& l, const void* ws);
+Binned binned_view(const Geom& g, const Layout& l, const void* ws, bool with_index);
 
 // Launchers (return hipError_t of the launch).
 hipError_t launch_bin(const Geom& g, const wt_fragments& f, void* ws, const Layout& l, bool record_index,

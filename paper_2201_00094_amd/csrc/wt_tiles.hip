@@ -1,9 +1,10 @@
 // Per-tile build, evaluate and resolve kernels over a binned fragment stream.
 //
-// One workgroup owns one screen tile. Its coefficient tile [tile_px][C][M] lives in LDS as FP32; every
-// fragment of the tile is applied with LDS float atomics, so no per-fragment update ever leaves the compute
-// unit. Global memory sees one coalesced load and/or store of each coefficient tile and of each
-// accumulation tile, plus the streaming read of the binned fragments.
+// One workgroup owns one screen tile. Its coefficient tile lives in LDS, coefficient-major
+// ([channel * M + m][pixel]: the updates of a wavefront go to random pixels, hence random banks), and every
+// fragment of the tile is applied with LDS atomics, so no per-fragment update leaves the compute unit.
+// Global memory sees the streaming read of the binned records plus one coalesced load and/or store of each
+// coefficient and accumulation tile.
 //
 //   build     (section 2.3.1): chi += a (1 - x); for n = 0..N: d[2^n + k] -= a tau(2^n x - k),
 //             k = min(floor(2^n x), 2^n - 1), tau(t) = t on [0, 1/2), 1 - t on [1/2, 1]; a = -ln(1 - alpha).
@@ -21,49 +22,85 @@
 
 namespace wt {
 
-constexpr int kTileThreads = 512;
+constexpr int kTileThreads = 1024;
 
-__device__ __forceinline__ void tile_origin(const Geom& g, uint32_t t, uint32_t& x0, uint32_t& y0) {
-  x0 = (t % g.tilesX) * g.TW;
-  y0 = (t / g.tilesX) * g.TH;
+// ------------------------------------------------------------------------------------------- tile addressing
+
+struct TileRef {
+  uint32_t x0, y0;   // origin in the frame
+  uint32_t beg, end; // binned record range
+};
+
+__device__ __forceinline__ TileRef tile_ref(const Geom& g, const Binned& b, uint32_t t) {
+  TileRef r;
+  r.x0 = (t % g.tilesX) * g.TW;
+  r.y0 = (t / g.tilesX) * g.TH;
+  r.beg = b.offsets[t * g.NX];
+  r.end = b.offsets[(t + 1) * g.NX];
+  return r;
 }
 
-// Global element index of tile-local element e (per elements per pixel); false when the pixel is off-frame.
-__device__ __forceinline__ bool tile_elem(const Geom& g, uint32_t x0, uint32_t y0, uint32_t e, uint32_t per,
-                                          uint64_t& gi) {
-  const uint32_t lp = e / per;
-  const uint32_t rem = e - lp * per;
-  const uint32_t px = x0 + (lp & (g.TW - 1));
-  const uint32_t py = y0 + lp / g.TW;
+// Frame pixel of tile-local pixel lp, or false when it lies outside the frame.
+__device__ __forceinline__ bool tile_pixel(const Geom& g, const TileRef& r, uint32_t lp, uint64_t& p) {
+  p = 0;
+  const uint32_t px = r.x0 + (lp & (g.TW - 1));
+  const uint32_t py = r.y0 + lp / g.TW;
   if (px >= g.W || py >= g.H) return false;
-  gi = ((uint64_t)py * g.W + px) * per + rem;
+  p = (uint64_t)py * g.W + px;
   return true;
 }
 
 __device__ __forceinline__ float clamp01(float x) { return fminf(fmaxf(x, 0.f), 1.f); }
 
+// ------------------------------------------------------------------------------------------- records
+
 template <int C>
-__device__ __forceinline__ bool load_fragment(const Binned& b, uint32_t i, uint32_t& lp, float& x, float (&al)[C]) {
-  lp = b.lpx[i];
-  x = b.x[i];
-  bool bad = isnan(x);
+struct Frag {
+  uint32_t lp;
+  float x;
+  float al[C];
+  float rgb[3];
+};
+
+// Pixel, depth and alpha of record i; false for a NaN fragment (skipped, already counted as dropped).
+template <int C>
+__device__ __forceinline__ bool load_head(const Binned& b, uint32_t i, Frag<C>& f) {
+  const uint32_t* r = b.rec + (uint64_t)i * b.D;
+  f.lp = r[0];
+  f.x = __uint_as_float(r[1]);
+  bool bad = isnan(f.x);
 #pragma unroll
   for (int c = 0; c < C; ++c) {
-    al[c] = b.alpha[c * b.cap + i];
-    bad |= isnan(al[c]);
+    f.al[c] = __uint_as_float(r[2 + c]);
+    bad |= isnan(f.al[c]);
   }
   return !bad;
 }
 
-// Build: the N + 2 coefficient updates of one fragment, per channel, into the LDS tile.
 template <int C>
-__device__ __forceinline__ void build_add(float* lc, const Geom& g, uint32_t lp, float x, const float (&al)[C]) {
-  x = clamp01(x);
+__device__ __forceinline__ bool load_full(const Binned& b, uint32_t i, Frag<C>& f) {
+  const uint32_t* r = b.rec + (uint64_t)i * b.D;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) f.rgb[q] = __uint_as_float(r[2 + C + q]);
+  return load_head<C>(b, i, f);
+}
+
+// ------------------------------------------------------------------------------------------- build
+
+// On-chip sums are FP64: on gfx950 an LDS FP64 atomic add sustains about nine times the rate of an FP32 one,
+// and every FP32 term then rounds once while the sum rounds nowhere.
+using acc_t = double;
+
+// The N + 2 coefficient updates of one fragment, per channel. lc is [C*M][TP] of acc_t.
+template <int C>
+__device__ __forceinline__ void build_add(acc_t* lc, const Geom& g, const Frag<C>& f) {
+  const uint32_t TP = g.tile_px;
+  const float x = clamp01(f.x);
   float a[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) {
-    a[c] = absorbance(alpha_clamped(al[c]));
-    atomicAdd(lc + (lp * C + c) * g.M, a[c] * (1.f - x));
+    a[c] = absorbance(alpha_clamped(f.al[c]));
+    atomicAdd(lc + (c * g.M) * TP + f.lp, (acc_t)(a[c] * (1.f - x)));
   }
   for (uint32_t n = 0; n <= g.rank; ++n) {
     const uint32_t s = 1u << n;
@@ -72,205 +109,303 @@ __device__ __forceinline__ void build_add(float* lc, const Geom& g, uint32_t lp,
     const float t = u - (float)k;
     const float tau = t < 0.5f ? t : 1.f - t;
 #pragma unroll
-    for (int c = 0; c < C; ++c) atomicAdd(lc + (lp * C + c) * g.M + s + k, -a[c] * tau);
+    for (int c = 0; c < C; ++c) atomicAdd(lc + (c * g.M + s + k) * TP + f.lp, (acc_t)(-a[c] * tau));
   }
 }
 
-// Cell value Abar_j straight from the stored coefficients (used when M is too large to expand per pixel).
-__device__ __forceinline__ float cell_from_coeffs(const float* cf, const Geom& g, uint32_t j) {
-  float A = cf[0];
+template <int C>
+__device__ __forceinline__ void build_tile(const Binned& b, const Geom& g, const TileRef& r, acc_t* lc) {
+  uint32_t i = r.beg + threadIdx.x;
+  // two records per thread per step keep more loads in flight
+  for (; i + blockDim.x < r.end; i += 2 * blockDim.x) {
+    Frag<C> f0, f1;
+    const bool ok0 = load_head<C>(b, i, f0);
+    const bool ok1 = load_head<C>(b, i + blockDim.x, f1);
+    if (ok0) build_add<C>(lc, g, f0);
+    if (ok1) build_add<C>(lc, g, f1);
+  }
+  if (i < r.end) {
+    Frag<C> f0;
+    if (load_head<C>(b, i, f0)) build_add<C>(lc, g, f0);
+  }
+}
+
+// ------------------------------------------------------------------------------------------- cells
+
+// Cell value Abar_j straight from the stored coefficients of one pixel/channel (column stride TP).
+template <typename T>
+__device__ __forceinline__ float cell_from_coeffs(const T* cf, uint32_t TP, const Geom& g, uint32_t j) {
+  T A = cf[0];
   for (uint32_t n = 0; n <= g.rank; ++n) {
     const uint32_t k = j >> (g.L - n);
-    const float d = cf[(1u << n) + k];
+    const T d = cf[((1u << n) + k) * TP];
     A += ((j >> (g.L - 1 - n)) & 1u) ? -d : d;
   }
-  return A;
+  return (float)A;
 }
 
-// In-place inverse of the level-scaled Haar transform for one pixel/channel: coefficients -> cell values.
+// Inverse of the level-scaled Haar transform on M values held in registers: coefficients -> cell values.
 template <int M>
-__device__ __forceinline__ void synth_fixed(float* cf) {
-  float v[M];
-  v[0] = cf[0];
+__device__ __forceinline__ void synth_regs(float (&v)[M]) {
+  float w[M];
+  w[0] = v[0];
 #pragma unroll
   for (int s = 1; s < M; s <<= 1) {
 #pragma unroll
     for (int k = s - 1; k >= 0; --k) {
-      const float d = cf[s + k];
-      const float a = v[k];
-      v[2 * k] = a + d;
-      v[2 * k + 1] = a - d;
+      const float d = v[s + k];
+      const float a = w[k];
+      w[2 * k] = a + d;
+      w[2 * k + 1] = a - d;
     }
   }
 #pragma unroll
-  for (int j = 0; j < M; ++j) cf[j] = v[j];
+  for (int j = 0; j < M; ++j) v[j] = w[j];
 }
 
-__device__ __forceinline__ void synth(float* cf, uint32_t M) {
-  switch (M) {
-    case 2: synth_fixed<2>(cf); break;
-    case 4: synth_fixed<4>(cf); break;
-    case 8: synth_fixed<8>(cf); break;
-    case 16: synth_fixed<16>(cf); break;
-    default: synth_fixed<32>(cf); break;
+// Cells of an FP32 coefficient tile, in place (one pixel/channel per thread).
+template <int C, int M>
+__device__ __forceinline__ void synth_tile_f32(float* lc, uint32_t TP) {
+  for (uint32_t q = threadIdx.x; q < TP * C; q += blockDim.x) {
+    const uint32_t c = q / TP, lp = q - c * TP;
+    float* cf = lc + (c * M) * TP + lp;
+    float v[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) v[m] = cf[m * TP];
+    synth_regs<M>(v);
+#pragma unroll
+    for (int m = 0; m < M; ++m) cf[m * TP] = v[m];
   }
 }
 
-// Evaluate: visibility at the fragment's depth and its contribution to the accumulation tile.
-template <int C, bool CELLS>
-__device__ __forceinline__ void eval_add(const float* lc, float* la, const Geom& g, uint32_t lp, float x,
-                                         const float (&al)[C], const float (&rgb)[3]) {
-  x = clamp01(x);
+template <int C>
+__device__ __forceinline__ void synth_tile_f32(float* lc, const Geom& g) {
+  switch (g.M) {
+    case 2: synth_tile_f32<C, 2>(lc, g.tile_px); break;
+    case 4: synth_tile_f32<C, 4>(lc, g.tile_px); break;
+    case 8: synth_tile_f32<C, 8>(lc, g.tile_px); break;
+    case 16: synth_tile_f32<C, 16>(lc, g.tile_px); break;
+    default: synth_tile_f32<C, 32>(lc, g.tile_px); break;
+  }
+}
+
+// Writes M values of TS for one pixel/channel, 16 bytes at a time where the layout allows.
+template <typename TS, int M>
+__device__ __forceinline__ void store_row(TS* dst, const TS (&s)[M]) {
+  if ((M * sizeof(TS)) % 16 == 0) {
+#pragma unroll
+    for (int k = 0; k < (int)(M * sizeof(TS) / 16); ++k) {
+      uint4 u;
+      __builtin_memcpy(&u, (const char*)s + 16 * k, 16);
+      ((uint4*)dst)[k] = u;
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m < M; ++m) dst[m] = s[m];
+  }
+}
+
+// FP64 coefficient tile -> storage precision (stored when coeffs is not null) -> FP32 cells in the first half
+// of the same LDS region. Requires TP * C <= blockDim.x: each thread holds at most one pixel/channel.
+template <int C, typename TS, int M>
+__device__ __forceinline__ void coeffs_to_cells(const Geom& g, const TileRef& r, acc_t* lc64, TS* coeffs) {
+  const uint32_t TP = g.tile_px;
+  const uint32_t q = threadIdx.x;
+  const bool have = q < TP * C;
+  const uint32_t c = have ? q / TP : 0, lp = have ? q - c * TP : 0;
+  float v[M];
+  if (have) {
+    TS s[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      s[m] = narrow<TS>((float)lc64[(c * M + m) * TP + lp]);
+      v[m] = widen<TS>(s[m]);
+    }
+    uint64_t p;
+    if (coeffs && tile_pixel(g, r, lp, p)) store_row<TS, M>(coeffs + (p * C + c) * M, s);
+    synth_regs<M>(v);
+  }
+  __syncthreads();  // every FP64 value has been read before the FP32 cells overwrite the region
+  if (have) {
+    float* lc32 = (float*)lc64;
+#pragma unroll
+    for (int m = 0; m < M; ++m) lc32[(c * M + m) * TP + lp] = v[m];
+  }
+}
+
+template <int C, typename TS>
+__device__ __forceinline__ void coeffs_to_cells(const Geom& g, const TileRef& r, acc_t* lc64, TS* coeffs) {
+  switch (g.M) {
+    case 2: coeffs_to_cells<C, TS, 2>(g, r, lc64, coeffs); break;
+    case 4: coeffs_to_cells<C, TS, 4>(g, r, lc64, coeffs); break;
+    case 8: coeffs_to_cells<C, TS, 8>(g, r, lc64, coeffs); break;
+    case 16: coeffs_to_cells<C, TS, 16>(g, r, lc64, coeffs); break;
+    default: coeffs_to_cells<C, TS, 32>(g, r, lc64, coeffs); break;
+  }
+}
+
+// ------------------------------------------------------------------------------------------- evaluate
+
+// la is [AL][TP] of acc_t: rows 0..2 colour, then sum a (C = 1) or sum a_r, a_g, a_b (C = 3).
+// lc holds FP32 cells (CELLS) or coefficients of type T (otherwise), [C*M][TP].
+template <int C, bool CELLS, typename T>
+__device__ __forceinline__ void eval_add(const T* lc, acc_t* la, const Geom& g, const Frag<C>& f) {
+  const uint32_t TP = g.tile_px;
+  const float x = clamp01(f.x);
   const float u = x * (float)g.M;
   const uint32_t j = min((uint32_t)u, g.M - 1);
   const float t = u - (float)j;
 #pragma unroll
   for (int c = 0; c < C; ++c) {
-    const float* cf = lc + (lp * C + c) * g.M;
+    const T* cf = lc + (c * g.M) * TP + f.lp;
     float lo, hi;
     if (CELLS) {
-      hi = cf[j];
-      lo = j ? cf[j - 1] : 0.f;
+      hi = (float)cf[j * TP];
+      lo = j ? (float)cf[(j - 1) * TP] : 0.f;
     } else {
-      hi = cell_from_coeffs(cf, g, j);
-      lo = j ? cell_from_coeffs(cf, g, j - 1) : 0.f;
+      hi = cell_from_coeffs<T>(cf, TP, g, j);
+      lo = j ? cell_from_coeffs<T>(cf, TP, g, j - 1) : 0.f;
     }
     const float At = fmaf(t, hi, (1.f - t) * lo);
     const float v = __expf(-At);
-    const float alc = alpha_clamped(al[c]);
+    const float alc = alpha_clamped(f.al[c]);
     const float a = absorbance(alc);
     if (C == 1) {
       const float w = alc * v;
-      atomicAdd(la + lp * 4 + 0, w * rgb[0]);
-      atomicAdd(la + lp * 4 + 1, w * rgb[1]);
-      atomicAdd(la + lp * 4 + 2, w * rgb[2]);
-      atomicAdd(la + lp * 4 + 3, a);
+      atomicAdd(la + 0 * TP + f.lp, (acc_t)(w * f.rgb[0]));
+      atomicAdd(la + 1 * TP + f.lp, (acc_t)(w * f.rgb[1]));
+      atomicAdd(la + 2 * TP + f.lp, (acc_t)(w * f.rgb[2]));
+      atomicAdd(la + 3 * TP + f.lp, (acc_t)a);
     } else {
-      atomicAdd(la + lp * 8 + c, alc * rgb[c] * v);
-      atomicAdd(la + lp * 8 + 4 + c, a);
+      atomicAdd(la + c * TP + f.lp, (acc_t)(alc * f.rgb[c] * v));
+      atomicAdd(la + (3 + c) * TP + f.lp, (acc_t)a);
     }
   }
 }
 
-template <int C, bool CELLS>
-__device__ __forceinline__ void eval_tile_fragments(const Binned& b, const Geom& g, uint32_t t, const float* lc,
-                                                    float* la) {
-  const uint32_t beg = b.offsets[t * g.NX], end = b.offsets[(t + 1) * g.NX];
-  for (uint32_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
-    uint32_t lp;
-    float x, al[C], rgb[3];
-    if (!load_fragment<C>(b, i, lp, x, al)) continue;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) rgb[q] = b.rgb[q * b.cap + i];
-    eval_add<C, CELLS>(lc, la, g, lp, x, al, rgb);
+template <int C, bool CELLS, typename T>
+__device__ __forceinline__ void eval_tile(const Binned& b, const Geom& g, const TileRef& r, const T* lc,
+                                          acc_t* la) {
+  uint32_t i = r.beg + threadIdx.x;
+  for (; i + blockDim.x < r.end; i += 2 * blockDim.x) {
+    Frag<C> f0, f1;
+    const bool ok0 = load_full<C>(b, i, f0);
+    const bool ok1 = load_full<C>(b, i + blockDim.x, f1);
+    if (ok0) eval_add<C, CELLS, T>(lc, la, g, f0);
+    if (ok1) eval_add<C, CELLS, T>(lc, la, g, f1);
+  }
+  if (i < r.end) {
+    Frag<C> f0;
+    if (load_full<C>(b, i, f0)) eval_add<C, CELLS, T>(lc, la, g, f0);
   }
 }
 
-template <int C>
-__device__ __forceinline__ void build_tile_fragments(const Binned& b, const Geom& g, uint32_t t, float* lc) {
-  const uint32_t beg = b.offsets[t * g.NX], end = b.offsets[(t + 1) * g.NX];
-  for (uint32_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
-    uint32_t lp;
-    float x, al[C];
-    if (!load_fragment<C>(b, i, lp, x, al)) continue;
-    build_add<C>(lc, g, lp, x, al);
-  }
-}
+// ------------------------------------------------------------------------------------------- tile <-> global
 
-template <bool CELLS>
-__device__ __forceinline__ void synth_tile(float* lc, const Geom& g) {
-  if (CELLS)
-    for (uint32_t q = threadIdx.x; q < g.tile_px * g.C; q += blockDim.x) synth(lc + q * g.M, g.M);
+// Coefficient tile between LDS ([C*M][TP] of T) and global memory ([P][C][M] of TS). Work item q covers VW
+// consecutive elements of one pixel, so consecutive lanes touch consecutive global addresses.
+// MODE 0: load (zero off-frame), 1: store, 2: round to TS in place and store when coeffs is not null.
+template <int C, typename TS, int MODE, typename T>
+__device__ __forceinline__ void coeff_tile_io(const Geom& g, const TileRef& r, T* lc, TS* coeffs) {
+  const uint32_t TP = g.tile_px, per = C * g.M;
+  const uint32_t VW = g.M < 4 ? g.M : 4;
+  const uint32_t groups = per / VW;
+  for (uint32_t q = threadIdx.x; q < TP * groups; q += blockDim.x) {
+    const uint32_t lp = q / groups, e0 = (q - lp * groups) * VW;
+    uint64_t p;
+    const bool in = tile_pixel(g, r, lp, p);
+    TS* gp = coeffs ? coeffs + p * per + e0 : nullptr;
+    for (uint32_t e = 0; e < VW; ++e) {
+      T* l = lc + (e0 + e) * TP + lp;  // row (c * M + m) = e0 + e
+      if (MODE == 0) {
+        *l = in ? (T)widen<TS>(gp[e]) : (T)0;
+      } else if (MODE == 1) {
+        if (in) gp[e] = narrow<TS>((float)*l);
+      } else {
+        const TS s = narrow<TS>((float)*l);
+        *l = (T)widen<TS>(s);
+        if (in && gp) gp[e] = s;
+      }
+    }
+  }
 }
 
 // ------------------------------------------------------------------------------------------- kernels
 
+// LDS of the tile kernels, per pixel: render 8 (C M + AL) bytes, build 8 C M, evaluate 4 C M + 8 AL.
 template <int C, typename TS>
 __global__ __launch_bounds__(kTileThreads) void k_build(Binned b, Geom g, TS* __restrict__ coeffs) {
-  extern __shared__ float smem[];
-  float* lc = smem;
-  const uint32_t t = blockIdx.x;
-  uint32_t x0, y0;
-  tile_origin(g, t, x0, y0);
-  const uint32_t per = C * g.M, nel = g.tile_px * per;
-  for (uint32_t e = threadIdx.x; e < nel; e += blockDim.x) {
-    uint64_t gi;
-    lc[e] = tile_elem(g, x0, y0, e, per, gi) ? widen<TS>(coeffs[gi]) : 0.f;
-  }
+  extern __shared__ acc_t smem_d[];
+  acc_t* lc = smem_d;
+  const TileRef r = tile_ref(g, b, blockIdx.x);
+  coeff_tile_io<C, TS, 0>(g, r, lc, coeffs);
   __syncthreads();
-  build_tile_fragments<C>(b, g, t, lc);
+  build_tile<C>(b, g, r, lc);
   __syncthreads();
-  for (uint32_t e = threadIdx.x; e < nel; e += blockDim.x) {
-    uint64_t gi;
-    if (tile_elem(g, x0, y0, e, per, gi)) coeffs[gi] = narrow<TS>(lc[e]);
-  }
+  coeff_tile_io<C, TS, 1>(g, r, lc, coeffs);
 }
 
 template <int C, typename TS, bool CELLS>
 __global__ __launch_bounds__(kTileThreads) void k_evaluate(Binned b, Geom g, const TS* __restrict__ coeffs,
                                                            float* __restrict__ accum) {
-  extern __shared__ float smem[];
-  const uint32_t per = C * g.M, nel = g.tile_px * per;
-  float* lc = smem;
-  float* la = smem + nel;
-  const uint32_t t = blockIdx.x;
-  uint32_t x0, y0;
-  tile_origin(g, t, x0, y0);
-  for (uint32_t e = threadIdx.x; e < nel; e += blockDim.x) {
-    uint64_t gi;
-    lc[e] = tile_elem(g, x0, y0, e, per, gi) ? widen<TS>(coeffs[gi]) : 0.f;
-  }
-  const uint32_t nacc = g.tile_px * g.AW;
-  for (uint32_t e = threadIdx.x; e < nacc; e += blockDim.x) {
-    uint64_t gi;
-    la[e] = tile_elem(g, x0, y0, e, g.AW, gi) ? accum[gi] : 0.f;
+  extern __shared__ acc_t smem_d[];
+  const uint32_t TP = g.tile_px;
+  acc_t* la = smem_d;                              // [AL][TP] FP64
+  float* lc = (float*)(smem_d + g.AL * TP);        // [C*M][TP] FP32
+  const TileRef r = tile_ref(g, b, blockIdx.x);
+  coeff_tile_io<C, TS, 0>(g, r, lc, const_cast<TS*>(coeffs));
+  for (uint32_t lp = threadIdx.x; lp < TP; lp += blockDim.x) {
+    uint64_t p;
+    const bool in = tile_pixel(g, r, lp, p);
+    for (uint32_t k = 0; k < 3; ++k) la[k * TP + lp] = in ? accum[p * g.AW + k] : 0.0;
+    for (uint32_t c = 0; c < C; ++c)
+      la[(3 + c) * TP + lp] = in ? accum[p * g.AW + (C == 1 ? 3 : 4 + c)] : 0.0;
   }
   __syncthreads();
-  synth_tile<CELLS>(lc, g);
+  if (CELLS) synth_tile_f32<C>(lc, g);
   __syncthreads();
-  eval_tile_fragments<C, CELLS>(b, g, t, lc, la);
+  eval_tile<C, CELLS, float>(b, g, r, lc, la);
   __syncthreads();
-  for (uint32_t e = threadIdx.x; e < nacc; e += blockDim.x) {
-    uint64_t gi;
-    if (tile_elem(g, x0, y0, e, g.AW, gi)) accum[gi] = la[e];
+  for (uint32_t lp = threadIdx.x; lp < TP; lp += blockDim.x) {
+    uint64_t p;
+    if (!tile_pixel(g, r, lp, p)) continue;
+    for (uint32_t k = 0; k < 3; ++k) accum[p * g.AW + k] = (float)la[k * TP + lp];
+    for (uint32_t c = 0; c < C; ++c) accum[p * g.AW + (C == 1 ? 3 : 4 + c)] = (float)la[(3 + c) * TP + lp];
   }
 }
 
 template <int C, typename TS, bool CELLS>
 __global__ __launch_bounds__(kTileThreads) void k_render(Binned b, Geom g, TS* __restrict__ coeffs, float bg0,
                                                          float bg1, float bg2, float* __restrict__ out) {
-  extern __shared__ float smem[];
-  const uint32_t per = C * g.M, nel = g.tile_px * per;
-  const uint32_t nacc = g.tile_px * g.AW;
-  float* lc = smem;
-  float* la = smem + nel;
-  const uint32_t t = blockIdx.x;
-  uint32_t x0, y0;
-  tile_origin(g, t, x0, y0);
-  for (uint32_t e = threadIdx.x; e < nel + nacc; e += blockDim.x) smem[e] = 0.f;
+  extern __shared__ acc_t smem_d[];
+  const uint32_t TP = g.tile_px;
+  acc_t* lc = smem_d;                    // [C*M][TP] FP64, then FP32 cells in its first half (CELLS)
+  acc_t* la = smem_d + C * g.M * TP;     // [AL][TP] FP64
+  const TileRef r = tile_ref(g, b, blockIdx.x);
+  for (uint32_t e = threadIdx.x; e < (C * g.M + g.AL) * TP; e += blockDim.x) smem_d[e] = 0.0;
   __syncthreads();
-  build_tile_fragments<C>(b, g, t, lc);
+  build_tile<C>(b, g, r, lc);
   __syncthreads();
-  // Coefficients at storage precision: stored (optionally) and used for the evaluation.
-  for (uint32_t e = threadIdx.x; e < nel; e += blockDim.x) {
-    const TS s = narrow<TS>(lc[e]);
-    lc[e] = widen<TS>(s);
-    uint64_t gi;
-    if (coeffs && tile_elem(g, x0, y0, e, per, gi)) coeffs[gi] = s;
+  // coefficients at storage precision: stored (optionally) and used for the evaluation
+  if (CELLS) {
+    coeffs_to_cells<C, TS>(g, r, lc, coeffs);
+    __syncthreads();
+    eval_tile<C, true, float>(b, g, r, (const float*)lc, la);
+  } else {
+    coeff_tile_io<C, TS, 2>(g, r, lc, coeffs);
+    __syncthreads();
+    eval_tile<C, false, acc_t>(b, g, r, lc, la);
   }
   __syncthreads();
-  synth_tile<CELLS>(lc, g);
-  __syncthreads();
-  eval_tile_fragments<C, CELLS>(b, g, t, lc, la);
-  __syncthreads();
   const float bg[3] = {bg0, bg1, bg2};
-  for (uint32_t e = threadIdx.x; e < g.tile_px * 3; e += blockDim.x) {
-    const uint32_t lp = e / 3, q = e - lp * 3;
-    uint64_t gi;
-    if (!tile_elem(g, x0, y0, e, 3, gi)) continue;
-    const float colour = la[lp * g.AW + q];
-    const float suma = (C == 1) ? la[lp * 4 + 3] : la[lp * 8 + 4 + q];
-    out[gi] = colour + bg[q] * __expf(-suma);
+  for (uint32_t lp = threadIdx.x; lp < TP; lp += blockDim.x) {
+    uint64_t p;
+    if (!tile_pixel(g, r, lp, p)) continue;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const float suma = (float)la[(3 + (C == 1 ? 0 : q)) * TP + lp];
+      out[p * 3 + q] = (float)la[q * TP + lp] + bg[q] * __expf(-suma);
+    }
   }
 }
 
@@ -290,12 +425,18 @@ __global__ __launch_bounds__(256) void k_resolve(const float* __restrict__ accum
 // ------------------------------------------------------------------------------------------- launchers
 
 size_t lds_tile_bytes(const Geom& g, bool with_accum) {
-  return (size_t)g.tile_px * (g.C * g.M + (with_accum ? g.AW : 0)) * sizeof(float);
+  return (size_t)g.tile_px * (g.C * g.M + (with_accum ? g.AL : 0)) * sizeof(acc_t);
 }
+
+static size_t lds_eval_bytes(const Geom& g) { return (size_t)g.tile_px * (4 * g.C * g.M + 8 * g.AL); }
+
+// The render kernel expands cells in registers, one pixel/channel per thread.
+static bool render_cells(const Geom& g) { return g.M <= 32 && g.tile_px * g.C <= (uint32_t)kTileThreads; }
 
 template <typename K>
 static hipError_t prep(K kernel, size_t lds) {
-  if (lds > 65536) return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (lds > 65536)
+    return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   return hipSuccess;
 }
 
@@ -326,7 +467,7 @@ hipError_t launch_build(const Geom& g, const Binned& b, void* coeffs, hipStream_
 }
 
 hipError_t launch_evaluate(const Geom& g, const Binned& b, const void* coeffs, float* accum, hipStream_t s) {
-  const size_t lds = lds_tile_bytes(g, true);
+  const size_t lds = lds_eval_bytes(g);
   return dispatch(g, [&](auto cc, auto* tag) {
     constexpr int C = decltype(cc)::value;
     using TS = std::remove_pointer_t<decltype(tag)>;
@@ -343,7 +484,7 @@ hipError_t launch_render(const Geom& g, const Binned& b, const float* bg, void* 
   return dispatch(g, [&](auto cc, auto* tag) {
     constexpr int C = decltype(cc)::value;
     using TS = std::remove_pointer_t<decltype(tag)>;
-    auto k = (g.M <= 32) ? k_render<C, TS, true> : k_render<C, TS, false>;
+    auto k = render_cells(g) ? k_render<C, TS, true> : k_render<C, TS, false>;
     hipError_t err = prep(k, lds);
     if (err != hipSuccess) return err;
     hipLaunchKernelGGL(k, dim3(g.ntiles), dim3(kTileThreads), lds, s, b, g, (TS*)coeffs, bg[0], bg[1], bg[2], out);

@@ -180,6 +180,16 @@ def render(spec: FrameSpec, frags: Fragments, bg, ws: Workspace, out: torch.Tens
     return out
 
 
+def render_binned(spec: FrameSpec, ws: Workspace, bg, out: torch.Tensor, coeffs: torch.Tensor = None, stream=None):
+    """Build, evaluate and resolve of a stream already binned into ``ws`` by :func:`bin`."""
+    _check(out, (torch.float32,), (spec.pixels, 3), "out")
+    if coeffs is not None:
+        _check(coeffs, (TORCH_DTYPES[spec.dtype],), spec.coeff_shape(), "coeffs")
+    _lib.check(_lib.load().wt_render_binned(C.byref(spec.c_desc()), ws.ptr, ws.nbytes, _lib.bg3(bg), _ptr(coeffs),
+                                            _ptr(out), _stream(stream)), "wt_render_binned")
+    return out
+
+
 def backward(spec: FrameSpec, frags: Fragments, coeffs: torch.Tensor, accum: torch.Tensor, bg, grad_out: torch.Tensor,
              ws: Workspace, grad_alpha: torch.Tensor = None, grad_rgb: torch.Tensor = None, stream=None):
     dev = frags.pixel.device
