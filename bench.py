@@ -3,8 +3,9 @@
 
 One step is the whole path for one frame of the smoke workload (1920x1080, Poisson(64 g(x,y)) fragments per
 pixel, g a seeded clipped blob field of mean 1, depth Normal(0.5, 0.1), alpha U[0.02, 0.1], unsorted stream,
-rank 3, FP32 coefficients): screen-tile binning (wt_bin), then build + evaluate + resolve (wt_render_binned),
-writing the frame's coefficients and its composite. Inputs are resident in HBM before the timed region.
+rank 3, FP32 coefficients): screen-tile binning (wt_bin_count, wt_bin_scatter), then build + evaluate + resolve
+(wt_render_binned), writing the frame's coefficients and its composite. Inputs are resident in HBM before the
+timed region.
 
 Prints one JSON line: whole-job fragments/s, p50/p99 frame latency, the roofline of the dominant kernel
 (timed with events on the library's stream) and the FP64 CPU oracle timed on a bounded sample of the same
@@ -72,6 +73,13 @@ def main():
     ap.add_argument("--cpu-fraction", type=float, default=0.1,
                     help="share of the frame's pixels the CPU oracle baseline resolves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", default="frame", choices=("frame", "serve", "copy"),
+                    help="frame: the headline single-frame step (default); serve: the continuous-batching trace; "
+                         "copy: a plain device copy of known size (calibrates the HBM byte counters)")
+    ap.add_argument("--requests", type=int, default=200, help="serve mode: requests in the trace")
+    ap.add_argument("--load", type=float, default=0.8, help="serve mode: arrival rate as a share of solo capacity")
+    ap.add_argument("--budget-gb", type=float, default=32.0, help="serve mode: HBM admission budget")
+    ap.add_argument("--slots", type=int, default=4, help="serve mode: concurrent requests (HIP streams)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -79,6 +87,11 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path (asked for --gpus %d, WORLD_SIZE %d)"
               % (args.gpus, world), file=sys.stderr)
         sys.exit(2)
+
+    if args.mode == "serve":
+        return run_serve(args)
+    if args.mode == "copy":
+        return run_copy(args)
 
     import torch
 
@@ -100,7 +113,8 @@ def main():
     stream = torch.cuda.current_stream()
 
     def step():
-        wt.bin(spec, fr, ws, stream=stream)
+        wt.bin_count(spec, fr, ws, stream=stream)
+        wt.bin_scatter(spec, fr, ws, stream=stream)
         wt.render_binned(spec, ws, f.bg, out, coeffs, stream=stream)
 
     for _ in range(args.warmup):
@@ -110,27 +124,37 @@ def main():
         raise RuntimeError("fragments were dropped from a clean stream")
 
     K = args.steps
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
+    # events on the library's stream between its calls: count (hist + scan), scatter, render (one kernel each
+    # for the last two)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(K)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(K):
         ev[k][0].record(stream)
-        wt.bin(spec, fr, ws, stream=stream)
+        wt.bin_count(spec, fr, ws, stream=stream)
         ev[k][1].record(stream)
-        wt.render_binned(spec, ws, f.bg, out, coeffs, stream=stream)
+        wt.bin_scatter(spec, fr, ws, stream=stream)
         ev[k][2].record(stream)
+        wt.render_binned(spec, ws, f.bg, out, coeffs, stream=stream)
+        ev[k][3].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
-    frame_ms = np.array([ev[k][0].elapsed_time(ev[k][2]) for k in range(K)])
-    bin_ms = np.array([ev[k][0].elapsed_time(ev[k][1]) for k in range(K)])
-    render_ms = np.array([ev[k][1].elapsed_time(ev[k][2]) for k in range(K)])
+    frame_ms = np.array([ev[k][0].elapsed_time(ev[k][3]) for k in range(K)])
+    count_ms = np.array([ev[k][0].elapsed_time(ev[k][1]) for k in range(K)])
+    scatter_ms = np.array([ev[k][1].elapsed_time(ev[k][2]) for k in range(K)])
+    render_ms = np.array([ev[k][2].elapsed_time(ev[k][3]) for k in range(K)])
     ms_per_step = wall * 1e3 / K
     F, P, M = f.count, f.pixels, spec.M
     sbytes = {"f32": 4, "f16": 2, "bf16": 2}[args.dtype]
     b_alg = algorithmic_bytes(F, P, M, sbytes)
-    b_render = render_kernel_bytes(F, P, M, sbytes)
-    render_gbs = b_render / (render_ms.mean() * 1e-3) / 1e9
+    kernels = {
+        "k_render": (render_kernel_bytes(F, P, M, sbytes), float(render_ms.mean())),
+        "k_scatter_staged": (scatter_kernel_bytes(F), float(scatter_ms.mean())),
+    }
+    dom = max(kernels, key=lambda k: kernels[k][1])
+    dom_bytes, dom_ms = kernels[dom]
+    dom_gbs = dom_bytes / (dom_ms * 1e-3) / 1e9
 
     line = {
         "metric": METRIC,
@@ -151,15 +175,104 @@ def main():
                    "fragments": F, "seed": args.seed},
         "p50_ms": float(np.percentile(frame_ms, 50)),
         "p99_ms": float(np.percentile(frame_ms, 99)),
-        "phase_ms": {"bin": float(bin_ms.mean()), "render": float(render_ms.mean())},
+        "phase_ms": {"count": float(count_ms.mean()), "scatter": float(scatter_ms.mean()),
+                     "render": float(render_ms.mean())},
         "path_alg_bytes": b_alg,
         "path_hbm_frac": b_alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
-        "roofline": {"bound": "hbm", "kernel": "k_render", "achieved": render_gbs, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": render_gbs / HBM_PEAK_GBS, "traffic": None,
-                     "alg_bytes_per_launch": b_render},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": dom_gbs, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": dom_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "alg_bytes_per_launch": dom_bytes, "avg_ms": dom_ms},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(f, args.cpu_fraction, args.seed)
+    print(json.dumps(line))
+
+
+def run_copy(args):
+    """A plain 1 GiB device-to-device copy, repeated: the reference for scaling the FETCH_SIZE / WRITE_SIZE
+    counters of the path's kernels to HBM bytes."""
+    import torch
+    n = 1 << 28  # floats: 1 GiB
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(max(args.steps, 1)):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "copy", "bytes_read": n * 4, "bytes_written": n * 4, "copies": max(args.steps, 1)}))
+
+
+def run_serve(args):
+    """Poisson arrivals of frames whose size is drawn from 640x360 .. 3840x2160, rank from {3, 4} and storage from
+    {f32, f16}, 24 fragments/px; admitted by HBM footprint into a fixed number of slots; p50/p99 latency from
+    arrival to completion and whole-trace fragments/s. A sample of requests is re-rendered alone and compared."""
+    import torch
+
+    import paper_2201_00094_amd as wt
+    import synth
+    from paper_2201_00094_amd.serve import FrameRequest, GpuExecutor, Server
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    pool = {}
+    for (w, h) in synth.REQUEST_RESOLUTIONS:
+        for s in range(2):
+            pix, dep, al, rgb = synth.torch_frame(1000 * s + w, w, h, mean=24.0, device=dev)
+            pool[(w, h, s)] = wt.Fragments(pix, dep, al, rgb)
+    torch.cuda.synchronize()
+    # solo service time per (size, rank, storage), warm
+    solo = {}
+    for (w, h, s), fr in pool.items():
+        if s:
+            continue
+        for rank in (3, 4):
+            for dt in ("f32", "f16"):
+                spec = wt.FrameSpec(w, h, rank, 1, dt)
+                ws = wt.Workspace(spec, fr.count, device=dev)
+                for _ in range(2):
+                    wt.render(spec, fr, (0.2, 0.2, 0.2), ws)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(3):
+                    wt.render(spec, fr, (0.2, 0.2, 0.2), ws)
+                torch.cuda.synchronize()
+                solo[(w, h, rank, dt)] = (time.perf_counter() - t0) / 3
+                del ws
+    torch.cuda.empty_cache()
+    mean_service = float(np.mean(list(solo.values())))
+    rate = args.load / mean_service
+    trace = synth.poisson_arrivals(args.seed, args.requests, rate)
+    ex = GpuExecutor(slots=args.slots, device=dev)
+    srv = Server(ex, slots=args.slots, budget_bytes=int(args.budget_gb * (1 << 30)))
+    futs = []
+    t0 = time.perf_counter()
+    for i, r in enumerate(trace):
+        now = time.perf_counter() - t0
+        if r["t"] > now:
+            time.sleep(r["t"] - now)
+        fr = pool[(r["width"], r["height"], r["seed"] % 2)]
+        futs.append(srv.submit(FrameRequest(r["width"], r["height"], r["rank"], fr, dtype=r["dtype"],
+                                            bg=(0.2, 0.2, 0.2), tag=i)))
+    results = [f.result(timeout=600) for f in futs]
+    srv.close()
+    stats = srv.stats.summary()
+    # solo vs mix on a sample
+    worst = 0.0
+    for i in np.random.default_rng(args.seed).choice(len(trace), min(16, len(trace)), replace=False):
+        r = trace[i]
+        fr = pool[(r["width"], r["height"], r["seed"] % 2)]
+        spec = wt.FrameSpec(r["width"], r["height"], r["rank"], 1, r["dtype"])
+        alone = wt.render(spec, fr, (0.2, 0.2, 0.2), wt.Workspace(spec, fr.count, device=dev))
+        torch.cuda.synchronize()
+        worst = max(worst, float((alone - results[i].out).abs().max()))
+    line = {"metric": "served frames: p50/p99 latency (arrival to completion) and fragments/s", "mode": "serve",
+            "value": stats["fragments_per_s"], "unit": "fragments/s", "n_gpus": 1, "requests": len(trace),
+            "rate_hz": rate, "load": args.load, "mean_solo_ms": mean_service * 1e3, "p50_ms": stats["p50_ms"],
+            "p99_ms": stats["p99_ms"], "mean_ms": stats["mean_ms"], "slots": args.slots,
+            "budget_gb": args.budget_gb, "max_inflight": stats["max_inflight"],
+            "max_gb_inflight": stats["max_bytes_inflight"] / (1 << 30), "solo_vs_mix_max_abs": worst,
+            "data": "synthetic", "dtype": "f32/f16 storage mix",
+            "config": {"workload": "Poisson arrivals; 640x360..3840x2160, rank 3/4, f32/f16 storage, "
+                                   "Poisson(24) fragments/px"}}
     print(json.dumps(line))
 
 

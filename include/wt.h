@@ -87,6 +87,14 @@ size_t wt_workspace_bytes(const wt_frame_desc* desc, uint64_t max_fragments);
 wt_status wt_bin(const wt_frame_desc* desc, const wt_fragments* frags, void* ws, size_t ws_bytes,
                  hipStream_t stream);
 
+/* The two halves of wt_bin, for callers that time or schedule them separately: wt_bin_count zeroes the
+ * drop counter, counts fragments per screen tile and lays out the tile segments; wt_bin_scatter then copies
+ * the stream into them. wt_bin_scatter must follow wt_bin_count on the same stream with the same arguments. */
+wt_status wt_bin_count(const wt_frame_desc* desc, const wt_fragments* frags, void* ws, size_t ws_bytes,
+                       hipStream_t stream);
+wt_status wt_bin_scatter(const wt_frame_desc* desc, const wt_fragments* frags, void* ws, size_t ws_bytes,
+                         hipStream_t stream);
+
 /* Build pass over a binned stream (section 2.3.1): coeffs += the coefficients of every binned fragment.
  * coeffs must hold P * channels * M elements of desc->coeff_dtype; the caller zeroes it before the first
  * contribution of a frame. */

@@ -5,6 +5,7 @@ marshals torch tensors into it. Importing it does not load the library; the firs
 if the library has not been built.
 """
 from ._lib import WTError, load as load_library  # noqa: F401
-from .wt import (FrameSpec, Fragments, Workspace, backward, bin, build, build_binned, dropped_count,  # noqa: F401
+from .wt import (FrameSpec, Fragments, Workspace, backward, bin, bin_count, bin_scatter, build,  # noqa: F401
+                 build_binned, dropped_count,
                  evaluate, evaluate_binned, render, render_binned, resolve, workspace_bytes)
 from .autograd import WaveletComposite, composite  # noqa: F401

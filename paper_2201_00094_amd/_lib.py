@@ -31,6 +31,8 @@ _vp, _sz, _st = C.c_void_p, C.c_size_t, C.c_void_p
 SIGNATURES = {
     "wt_workspace_bytes": (C.c_size_t, [_D, C.c_uint64]),
     "wt_bin": (C.c_int, [_D, _F, _vp, _sz, _st]),
+    "wt_bin_count": (C.c_int, [_D, _F, _vp, _sz, _st]),
+    "wt_bin_scatter": (C.c_int, [_D, _F, _vp, _sz, _st]),
     "wt_build_binned": (C.c_int, [_D, _vp, _vp, _sz, _st]),
     "wt_evaluate_binned": (C.c_int, [_D, _vp, _vp, _vp, _sz, _st]),
     "wt_build": (C.c_int, [_D, _F, _vp, _vp, _sz, _st]),

@@ -95,6 +95,32 @@ wt_status wt_bin(const wt_frame_desc* desc, const wt_fragments* frags, void* ws,
   return WT_OK;
 }
 
+wt_status wt_bin_count(const wt_frame_desc* desc, const wt_fragments* frags, void* ws, size_t ws_bytes,
+                       hipStream_t stream) {
+  WT_TRY(check_desc(desc));
+  WT_TRY(check_frags(frags));
+  const wt::Geom g = wt::make_geom(*desc);
+  WT_TRY(check_lds(g));
+  wt::Layout l;
+  WT_TRY(check_ws(g, ws, ws_bytes, frags->count, &l));
+  hipError_t e = wt::launch_bin_count(g, *frags, ws, l, stream);
+  if (e != hipSuccess) return hip_fail(e, "wt_bin_count");
+  return WT_OK;
+}
+
+wt_status wt_bin_scatter(const wt_frame_desc* desc, const wt_fragments* frags, void* ws, size_t ws_bytes,
+                         hipStream_t stream) {
+  WT_TRY(check_desc(desc));
+  WT_TRY(check_frags(frags));
+  const wt::Geom g = wt::make_geom(*desc);
+  WT_TRY(check_lds(g));
+  wt::Layout l;
+  WT_TRY(check_ws(g, ws, ws_bytes, frags->count, &l));
+  hipError_t e = wt::launch_bin_scatter(g, *frags, ws, l, false, stream);
+  if (e != hipSuccess) return hip_fail(e, "wt_bin_scatter");
+  return WT_OK;
+}
+
 wt_status wt_build_binned(const wt_frame_desc* desc, void* coeffs, const void* ws, size_t ws_bytes,
                           hipStream_t stream) {
   WT_TRY(check_desc(desc));

@@ -79,7 +79,8 @@ struct BFrag {
 // Record i of a binning made with stream indices; false for a NaN fragment.
 template <int C>
 __device__ __forceinline__ bool load_bfrag(const Binned& b, uint32_t i, BFrag<C>& f) {
-  const uint32_t* r = b.rec + (uint64_t)i * b.D;
+  const uint32_t* r = b.head + (uint64_t)i * b.DH;
+  const uint32_t* rt = b.tail + (uint64_t)i * b.DT;
   f.lp = r[0];
   f.x = __uint_as_float(r[1]);
   bool bad = isnan(f.x);
@@ -89,8 +90,8 @@ __device__ __forceinline__ bool load_bfrag(const Binned& b, uint32_t i, BFrag<C>
     bad |= isnan(f.al[c]);
   }
 #pragma unroll
-  for (int q = 0; q < 3; ++q) f.rgb[q] = __uint_as_float(r[2 + C + q]);
-  f.src = r[5 + C];
+  for (int q = 0; q < 3; ++q) f.rgb[q] = __uint_as_float(rt[q]);
+  f.src = rt[3];
   return !bad;
 }
 
@@ -108,7 +109,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(Binned b, Geom g, cons
   float* lc = (float*)(ladj + per * TP);
   float* lg = lc + per * TP;
   float* lT = lg + 3 * TP;
-  const uint32_t t = blockIdx.x;
+  const uint32_t t = b.order[blockIdx.x];
   const uint32_t x0 = (t % g.tilesX) * g.TW, y0 = (t / g.tilesX) * g.TH;
   for (uint32_t lp = threadIdx.x; lp < TP; lp += blockDim.x) {
     const uint32_t px = x0 + (lp & (g.TW - 1)), py = y0 + lp / g.TW;

@@ -9,15 +9,16 @@
 // Kernels:
 //   k_hist            pixel ids (4 B/fragment) -> per-(class, tile) counts; range drops counted.
 //   k_scan            exclusive scan of the counts, tile-major, into segment offsets and write cursors.
-//   k_scatter_staged  one chunk of kChunk fragments per workgroup: vector loads into registers, LDS count
+//   k_scatter_staged  one chunk (kPer fragments per thread) per workgroup: vector loads into registers, LDS count
 //                     per tile, one cursor reservation per touched tile, records placed in LDS in tile order,
-//                     then written as a flat run of dwords so that consecutive lanes store consecutive
-//                     addresses inside each tile's run.
-//   k_scatter_direct  same reservation, records stored straight from registers (many tiles).
+//                     then written as flat runs of dwords (head array, then tail array) so that consecutive
+//                     lanes store consecutive addresses inside each tile's run.
 //   k_scatter_global  one cursor atomic per fragment (very many tiles).
 // A chunk's class is chunk % NX in both k_hist and the scatter; with one chunk per scatter workgroup the class
 // is also the XCD the workgroup runs on, so each (tile, class) run is written from a single L2.
 // NaN fragments are counted as dropped and still binned; the tile kernels skip them.
+#include <stdlib.h>
+
 #include <algorithm>
 
 #include "wt_common.h"
@@ -42,11 +43,26 @@ Geom make_geom(const wt_frame_desc& d, bool backward) {
   g.AW = (d.channels == 3) ? 8 : 4;
   g.AL = (d.channels == 3) ? 6 : 4;
   g.dtype = d.coeff_dtype;
-  // Largest power-of-two tile whose LDS working set fits one compute unit: FP64 coefficient sums plus FP64
-  // accumulations (forward), or FP32 cells, FP64 cell adjoints and per-pixel gradient data (backward).
-  const uint32_t per_px = backward ? 12 * g.C * g.M + 4 * (3 + g.C) : 8 * (g.C * g.M + g.AL);
-  uint32_t px = std::max<uint32_t>(1, kLdsBytes / per_px);
-  px = std::min<uint32_t>(floor_pow2(px), kMaxTilePx);
+  // Largest power-of-two tile whose LDS working set fits one compute unit. Forward: FP64 endpoint masses
+  // (M + 1 per channel) and three FP64 colour sums, or, where the tile would hold more pixel/channels than a
+  // workgroup has threads or M > 32, FP64 coefficient sums plus FP64 accumulations. Backward: FP32 cells,
+  // FP64 cell adjoints and per-pixel gradient data.
+  auto tile_for = [](uint32_t per_px) {
+    const uint32_t px = std::max<uint32_t>(1, kLdsBytes / per_px);
+    return std::min<uint32_t>(floor_pow2(px), kMaxTilePx);
+  };
+  uint32_t px;
+  g.ep = 0;
+  if (backward) {
+    px = tile_for(12 * g.C * g.M + 4 * (3 + g.C));
+  } else {
+    px = tile_for(8 * g.C * (g.M + 1) + 24);
+    if (g.M <= 32 && px * g.C <= kTileThreads) {
+      g.ep = 1;
+    } else {
+      px = tile_for(8 * (g.C * g.M + g.AL));
+    }
+  }
   uint32_t e = 0;
   while ((1u << e) < px) ++e;
   g.TW = 1u << ((e + 1) / 2);
@@ -55,8 +71,13 @@ Geom make_geom(const wt_frame_desc& d, bool backward) {
   g.tilesX = (g.W + g.TW - 1) / g.TW;
   g.tilesY = (g.H + g.TH - 1) / g.TH;
   g.ntiles = g.tilesX * g.tilesY;
-  g.lds_bins = g.ntiles <= kMaxLdsBins ? 2 : (g.ntiles <= 16384 ? 1 : 0);
+  g.lds_bins = g.ntiles <= kMaxLdsBins ? 1 : 0;
   g.NX = g.lds_bins ? kClasses : 1;
+  // scatter workgroup: 1024 threads (one per CU, larger chunks) by default; WT_SCATTER_WG=512 selects two
+  // 512-thread workgroups per CU (tuning override) where their tile tables fit half the LDS
+  const char* wg = getenv("WT_SCATTER_WG");
+  g.sthreads = (wg && atoi(wg) == 512 && g.ntiles <= 4096) ? 512 : 1024;
+  g.chunk = g.sthreads * kPer;
   return g;
 }
 
@@ -73,8 +94,12 @@ Layout make_layout(const Geom& g, uint64_t cap) {
   o = align256(o + 4ull * (g.NX * (uint64_t)g.ntiles + 1));
   l.cursors = o;
   o = align256(o + 4ull * g.NX * g.ntiles);
-  l.records = o;
-  o = align256(o + 4ull * record_dwords(g.C, true) * cap);
+  l.order = o;
+  o = align256(o + 4ull * g.ntiles);
+  l.heads = o;
+  o = align256(o + 4ull * head_dwords(g.C) * cap);
+  l.tails = o;
+  o = align256(o + 4ull * tail_dwords(true) * cap);
   l.total = o;
   l.cap = cap;
   return l;
@@ -93,8 +118,11 @@ Binned binned_view(const Geom& g, const Layout& l, const void* ws, bool with_ind
   const char* b = (const char*)ws;
   Binned v;
   v.offsets = (const uint32_t*)(b + l.offsets);
-  v.rec = (const uint32_t*)(b + l.records);
-  v.D = record_dwords(g.C, with_index);
+  v.order = (const uint32_t*)(b + l.order);
+  v.head = (const uint32_t*)(b + l.heads);
+  v.tail = (const uint32_t*)(b + l.tails);
+  v.DH = head_dwords(g.C);
+  v.DT = tail_dwords(with_index);
   return v;
 }
 
@@ -114,26 +142,28 @@ __global__ __launch_bounds__(kHistThreads) void k_hist_lds(const uint32_t* __res
   for (uint32_t t = threadIdx.x; t < g.ntiles; t += blockDim.x) lh[t] = 0;
   __syncthreads();
   const uint32_t cls = blockIdx.x % g.NX;
-  const uint32_t nchunks = (uint32_t)(((uint64_t)F + kChunk - 1) / kChunk);
+  const uint32_t nchunks = (uint32_t)(((uint64_t)F + g.chunk - 1) / g.chunk);
   uint32_t nd = 0;
   for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
-    const uint32_t base = c * kChunk;
-    const uint32_t n = std::min<uint32_t>(kChunk, F - base);
-    if (vec && n == kChunk) {
-      // kChunk / 4 uint4 per chunk, kChunk / (4 * kHistThreads) per thread, all issued before use
-      constexpr int V = kChunk / (4 * kHistThreads);
-      uint4 q[V];
+    const uint32_t base = c * g.chunk;
+    const uint32_t n = std::min<uint32_t>(g.chunk, F - base);
+    if (vec && n == g.chunk) {
+      // chunk / 4 uint4 per chunk; four per thread in flight at a time
+      const uint4* q4 = (const uint4*)(pixel + base);
+      for (uint32_t v0 = 0; v0 < g.chunk / 4; v0 += 4 * kHistThreads) {
+        uint4 q[4];
 #pragma unroll
-      for (int v = 0; v < V; ++v) q[v] = ((const uint4*)(pixel + base))[v * kHistThreads + threadIdx.x];
+        for (int v = 0; v < 4; ++v) q[v] = q4[v0 + v * kHistThreads + threadIdx.x];
 #pragma unroll
-      for (int v = 0; v < V; ++v) {
-        const uint32_t ps[4] = {q[v].x, q[v].y, q[v].z, q[v].w};
+        for (int v = 0; v < 4; ++v) {
+          const uint32_t ps[4] = {q[v].x, q[v].y, q[v].z, q[v].w};
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          if (ps[k] < g.P)
-            atomicAdd(&lh[tile_of(g, ps[k])], 1u);
-          else
-            ++nd;
+          for (int k = 0; k < 4; ++k) {
+            if (ps[k] < g.P)
+              atomicAdd(&lh[tile_of(g, ps[k])], 1u);
+            else
+              ++nd;
+          }
         }
       }
     } else {
@@ -175,12 +205,16 @@ __global__ __launch_bounds__(256) void k_hist_global(const uint32_t* __restrict_
 
 constexpr int kScanThreads = 1024;
 constexpr int kScanItems = 16;
+constexpr uint32_t kOrderMax = 4096;  // tile counts up to this are ordered by size; beyond, raster order
 
-// Exclusive scan over segments in (tile, class) order. counts/cursors are class-major [NX][ntiles].
+// Exclusive scan over segments in (tile, class) order (counts/cursors are class-major [NX][ntiles]), then the
+// tile order for the tile kernels: heaviest tile first, so the last workgroups to start are the light ones.
 __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t* __restrict__ counts, Geom g,
                                                        uint32_t* __restrict__ offsets,
-                                                       uint32_t* __restrict__ cursors) {
+                                                       uint32_t* __restrict__ cursors,
+                                                       uint32_t* __restrict__ order) {
   __shared__ uint32_t sums[kScanThreads];
+  __shared__ unsigned long long keys[kOrderMax];
   const uint64_t n = (uint64_t)g.ntiles * g.NX;
   const uint32_t tid = threadIdx.x;
   uint32_t carry = 0;
@@ -220,11 +254,43 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t* __restric
     __syncthreads();
   }
   if (tid == 0) offsets[n] = carry;
+  if (g.ntiles > kOrderMax) {
+    for (uint32_t t = tid; t < g.ntiles; t += kScanThreads) order[t] = t;
+    return;
+  }
+  // bitonic sort of (~count, tile) ascending over the next power of two >= ntiles
+  uint32_t N = 1;
+  while (N < g.ntiles) N <<= 1;
+  for (uint32_t t = tid; t < N; t += kScanThreads) {
+    unsigned long long key = ~0ull;
+    if (t < g.ntiles) {
+      uint32_t c = 0;
+      for (uint32_t x = 0; x < g.NX; ++x) c += counts[x * g.ntiles + t];
+      key = ((unsigned long long)(~c) << 32) | t;
+    }
+    keys[t] = key;
+  }
+  __syncthreads();
+  for (uint32_t size = 2; size <= N; size <<= 1) {
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      for (uint32_t i = tid; i < N / 2; i += kScanThreads) {
+        const uint32_t lo = 2 * i - (i & (stride - 1));
+        const uint32_t hi = lo + stride;
+        const bool up = (lo & size) == 0;
+        const unsigned long long a = keys[lo], b = keys[hi];
+        if ((a > b) == up) {
+          keys[lo] = b;
+          keys[hi] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (uint32_t t = tid; t < g.ntiles; t += kScanThreads) order[t] = (uint32_t)(keys[t] & 0xffffffffu);
 }
 
 // ------------------------------------------------------------------------------------------------ scatter
 
-constexpr uint32_t kPer = kChunk / kScatterThreads;  // fragments per thread
 static_assert(kPer % 4 == 0, "vector loads take fragments four at a time");
 
 // One chunk's fragments, held in registers by the thread that loaded them.
@@ -298,9 +364,10 @@ __device__ __forceinline__ uint32_t record_word(const ChunkRegs<C>& r, uint32_t 
   return src;
 }
 
-// Block-wide exclusive scan of cnt[0, nt) in place; wsum holds kScatterThreads / 64 partial sums.
+// Block-wide exclusive scan of cnt[0, nt) in place; wsum holds THREADS / 64 partial sums.
+template <int THREADS>
 __device__ __forceinline__ void block_scan_inplace(uint32_t* cnt, uint32_t nt, uint32_t* wsum) {
-  const uint32_t per = (nt + kScatterThreads - 1) / kScatterThreads;
+  const uint32_t per = (nt + THREADS - 1) / THREADS;
   const uint32_t t0 = threadIdx.x * per, t1 = std::min(t0 + per, nt);
   uint32_t s = 0;
   for (uint32_t t = t0; t < t1; ++t) s += cnt[t];
@@ -315,7 +382,7 @@ __device__ __forceinline__ void block_scan_inplace(uint32_t* cnt, uint32_t nt, u
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t a = 0;
-    for (uint32_t w = 0; w < kScatterThreads / 64; ++w) {
+    for (uint32_t w = 0; w < THREADS / 64; ++w) {
       const uint32_t v = wsum[w];
       wsum[w] = a;
       a += v;
@@ -330,24 +397,27 @@ __device__ __forceinline__ void block_scan_inplace(uint32_t* cnt, uint32_t nt, u
   }
 }
 
-// LDS: srec[kChunk][D] sorted records, sg[kChunk] global slot of each sorted record, cnt[nt], gb[nt].
-template <int C, bool IDX>
-__global__ __launch_bounds__(kScatterThreads) void k_scatter_staged(wt_fragments f, Geom g, int vec,
+// LDS: srec[S][D] one round of sorted records, sg[S] their global slots, cnt[nt], gb[nt]. The chunk's sorted
+// order is written in rounds of S records (S = stage, a power of two chosen by the host to fit the LDS).
+template <int C, bool IDX, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_scatter_staged(wt_fragments f, Geom g, int vec,
+                                                                    uint32_t stage,
                                                                     uint32_t* __restrict__ cursors,
-                                                                    uint32_t* __restrict__ out,
+                                                                    uint32_t* __restrict__ head,
+                                                                    uint32_t* __restrict__ tail,
                                                                     unsigned long long* __restrict__ dropped) {
-  constexpr uint32_t D = record_dwords(C, IDX);
+  constexpr uint32_t D = record_dwords(C, IDX), DH = head_dwords(C), DT = tail_dwords(IDX);
   extern __shared__ uint32_t sm[];
   uint32_t* srec = sm;
-  uint32_t* sg = srec + kChunk * D;
-  uint32_t* cnt = sg + kChunk;
+  uint32_t* sg = srec + stage * D;
+  uint32_t* cnt = sg + stage;
   uint32_t* gb = cnt + g.ntiles;
-  __shared__ uint32_t wsum[kScatterThreads / 64];
+  __shared__ uint32_t wsum[THREADS / 64];
   __shared__ uint32_t nvalid;
   const uint32_t F = (uint32_t)f.count;
   const uint32_t cls = blockIdx.x % g.NX;
-  const uint32_t base = blockIdx.x * kChunk;
-  const uint32_t n = std::min<uint32_t>(kChunk, F - base);
+  const uint32_t base = blockIdx.x * g.chunk;
+  const uint32_t n = std::min<uint32_t>(g.chunk, F - base);
   for (uint32_t t = threadIdx.x; t < g.ntiles; t += blockDim.x) cnt[t] = 0;
   if (threadIdx.x == 0) nvalid = 0;
   ChunkRegs<C> r;
@@ -373,80 +443,48 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter_staged(wt_fragments
     const uint32_t v = cnt[t];
     gb[t] = v ? atomicAdd(&cursors[cls * g.ntiles + t], v) : 0u;
   }
-  block_scan_inplace(cnt, g.ntiles, wsum);
+  block_scan_inplace<THREADS>(cnt, g.ntiles, wsum);
   __syncthreads();
+  uint32_t sp[kPer];
 #pragma unroll
-  for (uint32_t k = 0; k < kPer; ++k) {
-    if (tile[k] == 0xffffffffu) continue;
-    const uint32_t sp = cnt[tile[k]] + rank[k];
-    uint32_t* d = srec + sp * D;
+  for (uint32_t k = 0; k < kPer; ++k) sp[k] = (tile[k] == 0xffffffffu) ? 0xffffffffu : cnt[tile[k]] + rank[k];
+  const uint32_t total = nvalid;
+  for (uint32_t r0 = 0; r0 < total; r0 += stage) {
 #pragma unroll
-    for (uint32_t j = 0; j < D; ++j) d[j] = record_word<C>(r, k, local[k], base + i0 + k, j);
-    sg[sp] = gb[tile[k]] + rank[k];
-  }
-  __syncthreads();
-  const uint32_t nw = nvalid * D;
-  for (uint32_t j = threadIdx.x; j < nw; j += blockDim.x) {
-    const uint32_t s = j / D;
-    out[(uint64_t)sg[s] * D + (j - s * D)] = srec[j];
-  }
-  nan_count = wave_sum(nan_count);
-  if ((threadIdx.x & 63) == 0 && nan_count) atomicAdd(dropped, (unsigned long long)nan_count);
-}
-
-template <int C, bool IDX>
-__global__ __launch_bounds__(kScatterThreads) void k_scatter_direct(wt_fragments f, Geom g, int vec,
-                                                                    uint32_t* __restrict__ cursors,
-                                                                    uint32_t* __restrict__ out,
-                                                                    unsigned long long* __restrict__ dropped) {
-  constexpr uint32_t D = record_dwords(C, IDX);
-  extern __shared__ uint32_t cnt[];
-  const uint32_t F = (uint32_t)f.count;
-  const uint32_t cls = blockIdx.x % g.NX;
-  const uint32_t base = blockIdx.x * kChunk;
-  const uint32_t n = std::min<uint32_t>(kChunk, F - base);
-  for (uint32_t t = threadIdx.x; t < g.ntiles; t += blockDim.x) cnt[t] = 0;
-  ChunkRegs<C> r;
-  const uint32_t i0 = threadIdx.x * kPer;
-  load_chunk<C>(f, base, i0, n, vec, r);
-  __syncthreads();
-  uint32_t tile[kPer], rank[kPer], local[kPer];
-  uint32_t nan_count = 0;
+    for (uint32_t k = 0; k < kPer; ++k) {
+      if (sp[k] < r0 || sp[k] >= r0 + stage) continue;  // also skips invalid slots (0xffffffff)
+      const uint32_t s = sp[k] - r0;
+      uint32_t* d = srec + s * D;
 #pragma unroll
-  for (uint32_t k = 0; k < kPer; ++k) {
-    tile[k] = 0xffffffffu;
-    if (r.p[k] < g.P) {
-      tile_locate(g, r.p[k], tile[k], local[k]);
-      rank[k] = atomicAdd(&cnt[tile[k]], 1u);
-      nan_count += has_nan<C>(r, k) ? 1u : 0u;
+      for (uint32_t j = 0; j < D; ++j) d[j] = record_word<C>(r, k, local[k], base + i0 + k, j);
+      sg[s] = gb[tile[k]] + rank[k];
     }
-  }
-  __syncthreads();
-  for (uint32_t t = threadIdx.x; t < g.ntiles; t += blockDim.x) {
-    const uint32_t v = cnt[t];
-    if (v) cnt[t] = atomicAdd(&cursors[cls * g.ntiles + t], v);
-  }
-  __syncthreads();
-#pragma unroll
-  for (uint32_t k = 0; k < kPer; ++k) {
-    if (tile[k] == 0xffffffffu) continue;
-    uint32_t* d = out + (uint64_t)(cnt[tile[k]] + rank[k]) * D;
-#pragma unroll
-    for (uint32_t j = 0; j < D; ++j) d[j] = record_word<C>(r, k, local[k], base + i0 + k, j);
+    __syncthreads();
+    const uint32_t ns = std::min(stage, total - r0);
+    for (uint32_t j = threadIdx.x; j < ns * DH; j += blockDim.x) {
+      const uint32_t s = j / DH, w = j - s * DH;
+      head[(uint64_t)sg[s] * DH + w] = srec[s * D + w];
+    }
+    for (uint32_t j = threadIdx.x; j < ns * DT; j += blockDim.x) {
+      const uint32_t s = j / DT, w = j - s * DT;
+      tail[(uint64_t)sg[s] * DT + w] = srec[s * D + DH + w];
+    }
+    __syncthreads();
   }
   nan_count = wave_sum(nan_count);
   if ((threadIdx.x & 63) == 0 && nan_count) atomicAdd(dropped, (unsigned long long)nan_count);
 }
 
-template <int C, bool IDX>
-__global__ __launch_bounds__(kScatterThreads) void k_scatter_global(wt_fragments f, Geom g, int vec,
+template <int C, bool IDX, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_scatter_global(wt_fragments f, Geom g, int vec,
                                                                     uint32_t* __restrict__ cursors,
-                                                                    uint32_t* __restrict__ out,
+                                                                    uint32_t* __restrict__ head,
+                                                                    uint32_t* __restrict__ tail,
                                                                     unsigned long long* __restrict__ dropped) {
-  constexpr uint32_t D = record_dwords(C, IDX);
+  constexpr uint32_t DH = head_dwords(C), DT = tail_dwords(IDX);
   const uint32_t F = (uint32_t)f.count;
-  const uint32_t base = blockIdx.x * kChunk;
-  const uint32_t n = std::min<uint32_t>(kChunk, F - base);
+  const uint32_t base = blockIdx.x * g.chunk;
+  const uint32_t n = std::min<uint32_t>(g.chunk, F - base);
   ChunkRegs<C> r;
   const uint32_t i0 = threadIdx.x * kPer;
   load_chunk<C>(f, base, i0, n, vec, r);
@@ -457,9 +495,11 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter_global(wt_fragments
     uint32_t tile, local;
     tile_locate(g, r.p[k], tile, local);
     nan_count += has_nan<C>(r, k) ? 1u : 0u;
-    uint32_t* d = out + (uint64_t)atomicAdd(&cursors[tile], 1u) * D;
+    const uint64_t pos = atomicAdd(&cursors[tile], 1u);
 #pragma unroll
-    for (uint32_t j = 0; j < D; ++j) d[j] = record_word<C>(r, k, local, base + i0 + k, j);
+    for (uint32_t j = 0; j < DH; ++j) head[pos * DH + j] = record_word<C>(r, k, local, base + i0 + k, j);
+#pragma unroll
+    for (uint32_t j = 0; j < DT; ++j) tail[pos * DT + j] = record_word<C>(r, k, local, base + i0 + k, DH + j);
   }
   nan_count = wave_sum(nan_count);
   if ((threadIdx.x & 63) == 0 && nan_count) atomicAdd(dropped, (unsigned long long)nan_count);
@@ -467,36 +507,42 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter_global(wt_fragments
 
 static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
-template <int C, bool IDX>
-static hipError_t launch_scatter(const Geom& g, const wt_fragments& f, int vec, uint32_t* cursors, uint32_t* out,
-                                 unsigned long long* dropped, uint32_t nchunks, hipStream_t s) {
-  if (g.lds_bins == 2) {
+template <int C, bool IDX, int THREADS>
+static hipError_t launch_scatter_t(const Geom& g, const wt_fragments& f, int vec, uint32_t* cursors, uint32_t* head,
+                                   uint32_t* tail, unsigned long long* dropped, uint32_t nchunks, hipStream_t s) {
+  if (g.lds_bins) {
     constexpr uint32_t D = record_dwords(C, IDX);
-    const size_t lds = (size_t)(kChunk * D + kChunk + 2 * g.ntiles) * 4;
-    auto k = k_scatter_staged<C, IDX>;
+    // largest power-of-two round that fits beside the tile tables (1 KB left for static LDS); with 512 threads
+    // the round is capped so that two workgroups share a compute unit
+    const size_t budget = (THREADS == 512 ? kLdsBytes / 2 : kLdsBytes) - 1024;
+    uint32_t stage = g.chunk;
+    while (stage > 256 && (size_t)(stage * (D + 1) + 2 * g.ntiles) * 4 > budget) stage >>= 1;
+    const size_t lds = (size_t)(stage * (D + 1) + 2 * g.ntiles) * 4;
+    auto k = k_scatter_staged<C, IDX, THREADS>;
     if (lds > 65536) {
       hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k, dim3(nchunks), dim3(kScatterThreads), lds, s, f, g, vec, cursors, out, dropped);
-  } else if (g.lds_bins == 1) {
-    const size_t lds = (size_t)g.ntiles * 4;
-    hipLaunchKernelGGL((k_scatter_direct<C, IDX>), dim3(nchunks), dim3(kScatterThreads), lds, s, f, g, vec, cursors,
-                       out, dropped);
+    hipLaunchKernelGGL(k, dim3(nchunks), dim3(THREADS), lds, s, f, g, vec, stage, cursors, head, tail, dropped);
   } else {
-    hipLaunchKernelGGL((k_scatter_global<C, IDX>), dim3(nchunks), dim3(kScatterThreads), 0, s, f, g, vec, cursors,
-                       out, dropped);
+    hipLaunchKernelGGL((k_scatter_global<C, IDX, THREADS>), dim3(nchunks), dim3(THREADS), 0, s, f, g, vec, cursors,
+                       head, tail, dropped);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_bin(const Geom& g, const wt_fragments& f, void* ws, const Layout& l, bool record_index,
-                      hipStream_t s) {
+template <int C, bool IDX>
+static hipError_t launch_scatter(const Geom& g, const wt_fragments& f, int vec, uint32_t* cursors, uint32_t* head,
+                                 uint32_t* tail, unsigned long long* dropped, uint32_t nchunks, hipStream_t s) {
+  if (g.sthreads == 512) return launch_scatter_t<C, IDX, 512>(g, f, vec, cursors, head, tail, dropped, nchunks, s);
+  return launch_scatter_t<C, IDX, 1024>(g, f, vec, cursors, head, tail, dropped, nchunks, s);
+}
+
+hipError_t launch_bin_count(const Geom& g, const wt_fragments& f, void* ws, const Layout& l, hipStream_t s) {
   char* b = (char*)ws;
   uint32_t* counts = (uint32_t*)(b + l.counts);
   uint32_t* offsets = (uint32_t*)(b + l.offsets);
   uint32_t* cursors = (uint32_t*)(b + l.cursors);
-  uint32_t* records = (uint32_t*)(b + l.records);
   unsigned long long* dropped = (unsigned long long*)(b + l.header);
   const uint64_t ncount = (uint64_t)g.NX * g.ntiles;
   // zero the header's counters and the tile counts (fill kernels: safe inside captured graphs)
@@ -504,8 +550,8 @@ hipError_t launch_bin(const Geom& g, const wt_fragments& f, void* ws, const Layo
   hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<uint64_t>((ncount + 255) / 256, 4096)), dim3(256), 0, s,
                      counts, ncount, 0u);
   const uint32_t F = (uint32_t)f.count;
-  const uint32_t nchunks = (uint32_t)(((uint64_t)F + kChunk - 1) / kChunk);
-  const int vec = aligned16(f.pixel) && aligned16(f.depth) && aligned16(f.alpha) && aligned16(f.rgb);
+  const uint32_t nchunks = (uint32_t)(((uint64_t)F + g.chunk - 1) / g.chunk);
+  const int vec = aligned16(f.pixel);
   if (F > 0) {
     if (g.lds_bins) {
       const uint32_t grid = std::min<uint32_t>(((nchunks + g.NX - 1) / g.NX) * g.NX, 2048);
@@ -515,14 +561,34 @@ hipError_t launch_bin(const Geom& g, const wt_fragments& f, void* ws, const Layo
       hipLaunchKernelGGL(k_hist_global, dim3(2048), dim3(256), 0, s, f.pixel, F, g, counts, dropped);
     }
   }
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, counts, g, offsets, cursors);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || F == 0) return e;
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, counts, g, offsets, cursors,
+                     (uint32_t*)(b + l.order));
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_scatter(const Geom& g, const wt_fragments& f, void* ws, const Layout& l, bool record_index,
+                              hipStream_t s) {
+  char* b = (char*)ws;
+  uint32_t* cursors = (uint32_t*)(b + l.cursors);
+  uint32_t* head = (uint32_t*)(b + l.heads);
+  uint32_t* tail = (uint32_t*)(b + l.tails);
+  unsigned long long* dropped = (unsigned long long*)(b + l.header);
+  const uint32_t F = (uint32_t)f.count;
+  if (F == 0) return hipSuccess;
+  const uint32_t nchunks = (uint32_t)(((uint64_t)F + g.chunk - 1) / g.chunk);
+  const int vec = aligned16(f.pixel) && aligned16(f.depth) && aligned16(f.alpha) && aligned16(f.rgb);
   if (g.C == 1)
-    return record_index ? launch_scatter<1, true>(g, f, vec, cursors, records, dropped, nchunks, s)
-                        : launch_scatter<1, false>(g, f, vec, cursors, records, dropped, nchunks, s);
-  return record_index ? launch_scatter<3, true>(g, f, vec, cursors, records, dropped, nchunks, s)
-                      : launch_scatter<3, false>(g, f, vec, cursors, records, dropped, nchunks, s);
+    return record_index ? launch_scatter<1, true>(g, f, vec, cursors, head, tail, dropped, nchunks, s)
+                        : launch_scatter<1, false>(g, f, vec, cursors, head, tail, dropped, nchunks, s);
+  return record_index ? launch_scatter<3, true>(g, f, vec, cursors, head, tail, dropped, nchunks, s)
+                      : launch_scatter<3, false>(g, f, vec, cursors, head, tail, dropped, nchunks, s);
+}
+
+hipError_t launch_bin(const Geom& g, const wt_fragments& f, void* ws, const Layout& l, bool record_index,
+                      hipStream_t s) {
+  hipError_t e = launch_bin_count(g, f, ws, l, s);
+  if (e != hipSuccess) return e;
+  return launch_bin_scatter(g, f, ws, l, record_index, s);
 }
 
 }  // namespace wt

@@ -13,11 +13,11 @@ namespace wt {
 // and each XCD has its own L2. The binning keeps one write frontier per (tile, XCD class) so that the
 // partial cache lines of a frontier are filled inside a single L2 before they are written back.
 constexpr uint32_t kClasses = 8;
-constexpr uint32_t kChunk = 2048;          // fragments per scatter workgroup (staged in LDS, sorted by tile)
-constexpr uint32_t kScatterThreads = 512;  // kChunk / kScatterThreads fragments per thread, a multiple of 4
-constexpr uint32_t kMaxLdsBins = 4096;     // tiles the LDS-staged scatter handles; beyond: global fallback
+constexpr uint32_t kPer = 8;               // fragments per scatter thread (held in registers)
+constexpr uint32_t kMaxLdsBins = 16384;    // tiles the LDS-staged scatter handles; beyond: global fallback
 constexpr uint32_t kLdsBytes = 160 * 1024; // LDS of one CDNA4 compute unit (also the per-workgroup limit)
 constexpr uint32_t kMaxTilePx = 2048;
+constexpr uint32_t kTileThreads = 1024;    // workgroup size of the per-tile kernels
 constexpr float kAlphaMax = 0.99999994f;   // 1 - 2^-24
 
 // Frame geometry as the kernels see it.
@@ -27,15 +27,21 @@ struct Geom {
   uint32_t TW, TH;       // tile extent in pixels (powers of two)
   uint32_t tilesX, tilesY, ntiles, tile_px;
   uint32_t NX;           // write-frontier classes (kClasses, or 1 when the tile count is large)
-  uint32_t lds_bins;     // 1: LDS-staged scatter; 0: global atomics per fragment
+  uint32_t lds_bins;     // 1: LDS-staged scatter; 0: one global atomic per fragment
   uint32_t AW;           // accum floats per pixel in global memory: 4 (C = 1) or 8 (C = 3)
   uint32_t AL;           // accumulation floats per pixel in LDS: 4 (C = 1) or 6 (C = 3)
   uint32_t dtype;        // wt_dtype of the coefficient storage
+  uint32_t ep;           // 1: the build accumulates endpoint masses (M <= 32, one pixel/channel per thread)
+  uint32_t sthreads;     // scatter workgroup size (512 or 1024)
+  uint32_t chunk;        // fragments per scatter workgroup = sthreads * kPer (also the class granularity)
 };
 
-// Binned fragment record (array of structures, D dwords):
-//   [0] tile-local pixel index, [1] depth, [2 .. 2+C) alpha, [2+C .. 5+C) rgb, [5+C] stream index (optional)
-constexpr uint32_t record_dwords(uint32_t C, bool with_index) { return 5 + C + (with_index ? 1 : 0); }
+// Binned fragment records, two arrays of structures in the same order:
+//   head [cap][2 + C]: tile-local pixel index, depth, alpha[C]   (everything the build pass reads)
+//   tail [cap][3 or 4]: rgb[3], then the stream index when recorded
+constexpr uint32_t head_dwords(uint32_t C) { return 2 + C; }
+constexpr uint32_t tail_dwords(bool with_index) { return 3 + (with_index ? 1 : 0); }
+constexpr uint32_t record_dwords(uint32_t C, bool with_index) { return head_dwords(C) + tail_dwords(with_index); }
 
 // Device workspace: a header, the tile tables and the binned records.
 struct Layout {
@@ -43,7 +49,9 @@ struct Layout {
   size_t counts;   // uint32 [NX][ntiles]
   size_t offsets;  // uint32 [ntiles * NX + 1], tile-major: segment (t, x) = [off[t*NX+x], off[t*NX+x+1])
   size_t cursors;  // uint32 [NX][ntiles]
-  size_t records;  // uint32 [cap][D], D up to record_dwords(C, true)
+  size_t order;    // uint32 [ntiles]: tiles by descending fragment count (heaviest first)
+  size_t heads;    // uint32 [cap][head_dwords(C)]
+  size_t tails;    // uint32 [cap][tail_dwords(true)]
   size_t total;    // bytes
   uint64_t cap;    // fragment capacity
 };
@@ -51,8 +59,10 @@ struct Layout {
 // Pointers into a workspace, as passed to kernels.
 struct Binned {
   const uint32_t* offsets;
-  const uint32_t* rec;
-  uint32_t D;      // dwords per record
+  const uint32_t* order;  // workgroup b processes tile order[b]
+  const uint32_t* head;
+  const uint32_t* tail;
+  uint32_t DH, DT; // dwords per head / tail entry
 };
 
 // backward = true picks tiles for the gradient kernel, which holds cell values and their adjoints.
@@ -66,6 +76,9 @@ Binned binned_view(const Geom& g, const Layout& l, const void* ws, bool with_ind
 // Launchers (return hipError_t of the launch).
 hipError_t launch_bin(const Geom& g, const wt_fragments& f, void* ws, const Layout& l, bool record_index,
                       hipStream_t s);
+hipError_t launch_bin_count(const Geom& g, const wt_fragments& f, void* ws, const Layout& l, hipStream_t s);
+hipError_t launch_bin_scatter(const Geom& g, const wt_fragments& f, void* ws, const Layout& l, bool record_index,
+                              hipStream_t s);
 hipError_t launch_build(const Geom& g, const Binned& b, void* coeffs, hipStream_t s);
 hipError_t launch_evaluate(const Geom& g, const Binned& b, const void* coeffs, float* accum, hipStream_t s);
 hipError_t launch_resolve(const Geom& g, const float* accum, const float* bg, float* out, hipStream_t s);

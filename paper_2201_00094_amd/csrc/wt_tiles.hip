@@ -22,7 +22,6 @@
 
 namespace wt {
 
-constexpr int kTileThreads = 1024;
 
 // ------------------------------------------------------------------------------------------- tile addressing
 
@@ -65,7 +64,7 @@ struct Frag {
 // Pixel, depth and alpha of record i; false for a NaN fragment (skipped, already counted as dropped).
 template <int C>
 __device__ __forceinline__ bool load_head(const Binned& b, uint32_t i, Frag<C>& f) {
-  const uint32_t* r = b.rec + (uint64_t)i * b.D;
+  const uint32_t* r = b.head + (uint64_t)i * b.DH;
   f.lp = r[0];
   f.x = __uint_as_float(r[1]);
   bool bad = isnan(f.x);
@@ -79,9 +78,9 @@ __device__ __forceinline__ bool load_head(const Binned& b, uint32_t i, Frag<C>& 
 
 template <int C>
 __device__ __forceinline__ bool load_full(const Binned& b, uint32_t i, Frag<C>& f) {
-  const uint32_t* r = b.rec + (uint64_t)i * b.D;
+  const uint32_t* r = b.tail + (uint64_t)i * b.DT;
 #pragma unroll
-  for (int q = 0; q < 3; ++q) f.rgb[q] = __uint_as_float(r[2 + C + q]);
+  for (int q = 0; q < 3; ++q) f.rgb[q] = __uint_as_float(r[q]);
   return load_head<C>(b, i, f);
 }
 
@@ -244,11 +243,154 @@ __device__ __forceinline__ void coeffs_to_cells(const Geom& g, const TileRef& r,
   }
 }
 
+// ------------------------------------------------------------------------------------------- endpoint masses
+//
+// A fragment's contribution to every coefficient depends on its depth only through its finest cell j and the
+// offset t = M x - j in it: 1 - x and every tent tau(2^n x - k) are linear on a finest cell (their kinks lie on
+// cell boundaries for n <= N). So the N + 2 closed-form updates of section 2.3.1 factor exactly through two
+// endpoint masses, e_j += a (1 - t) and e_{j+1} += a t, per fragment and channel:
+//   chi     = sum_m e_m (1 - m/M),   d_{n,k} = -sum_m e_m tau(2^n m / M - k),   sum a = sum_m e_m,
+// with exact dyadic weights and all terms of one sign (no cancellation). Two LDS atomics per fragment instead
+// of N + 2, and the absorbance total comes for free.
+
+template <int C>
+__device__ __forceinline__ void build_ep_add(acc_t* le, const Geom& g, const Frag<C>& f) {
+  const uint32_t TP = g.tile_px, M1 = g.M + 1;
+  const float x = clamp01(f.x);
+  const float u = x * (float)g.M;
+  const uint32_t j = min((uint32_t)u, g.M - 1);
+  const float t = u - (float)j;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const float a = absorbance(alpha_clamped(f.al[c]));
+    acc_t* e = le + (c * M1 + j) * TP + f.lp;
+    atomicAdd(e, (acc_t)(a * (1.f - t)));
+    atomicAdd(e + TP, (acc_t)(a * t));
+  }
+}
+
+template <int C>
+__device__ __forceinline__ void build_ep_tile(const Binned& b, const Geom& g, const TileRef& r, acc_t* le) {
+  uint32_t i = r.beg + threadIdx.x;
+  for (; i + blockDim.x < r.end; i += 2 * blockDim.x) {
+    Frag<C> f0, f1;
+    const bool ok0 = load_head<C>(b, i, f0);
+    const bool ok1 = load_head<C>(b, i + blockDim.x, f1);
+    if (ok0) build_ep_add<C>(le, g, f0);
+    if (ok1) build_ep_add<C>(le, g, f1);
+  }
+  if (i < r.end) {
+    Frag<C> f0;
+    if (load_head<C>(b, i, f0)) build_ep_add<C>(le, g, f0);
+  }
+}
+
+// Coefficients (stored layout) and absorbance total of one pixel/channel from its M + 1 endpoint masses.
+template <int M>
+__device__ __forceinline__ void endpoints_to_coeffs(const acc_t (&e)[M + 1], acc_t (&cf)[M], acc_t& suma) {
+  acc_t chi = 0, tot = 0;
+#pragma unroll
+  for (int m = 0; m <= M; ++m) {
+    chi += e[m] * ((acc_t)(M - m) / (acc_t)M);
+    tot += e[m];
+  }
+  cf[0] = chi;
+  suma = tot;
+#pragma unroll
+  for (int s = 1; s < M; s <<= 1) {  // level n with s = 2^n; support of d_{n,k}: endpoints k w .. (k+1) w
+    const int w = M / s;
+#pragma unroll
+    for (int k = 0; k < s; ++k) {
+      acc_t acc = 0;
+#pragma unroll
+      for (int i = 1; i < w; ++i) acc += e[k * w + i] * ((acc_t)(2 * i <= w ? i : w - i) / (acc_t)w);
+      cf[s + k] = -acc;
+    }
+  }
+}
+
+// Render: endpoint masses -> coefficients at storage precision (stored when coeffs is not null) -> FP32 cells,
+// and the absorbance total, written over the endpoint region as floats: cells [C*M][TP], then suma [C][TP].
+template <int C, typename TS, int M>
+__device__ __forceinline__ void ep_render_convert(const Geom& g, const TileRef& r, acc_t* le, TS* coeffs) {
+  const uint32_t TP = g.tile_px;
+  const uint32_t q = threadIdx.x;
+  const bool have = q < TP * C;
+  const uint32_t c = have ? q / TP : 0, lp = have ? q - c * TP : 0;
+  float v[M];
+  float sa = 0.f;
+  if (have) {
+    acc_t e[M + 1], cf[M], suma;
+#pragma unroll
+    for (int m = 0; m <= M; ++m) e[m] = le[(c * (M + 1) + m) * TP + lp];
+    endpoints_to_coeffs<M>(e, cf, suma);
+    TS s[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      s[m] = narrow<TS>((float)cf[m]);
+      v[m] = widen<TS>(s[m]);
+    }
+    uint64_t p;
+    if (coeffs && tile_pixel(g, r, lp, p)) store_row<TS, M>(coeffs + (p * C + c) * M, s);
+    synth_regs<M>(v);
+    sa = (float)suma;
+  }
+  __syncthreads();  // every endpoint mass has been read before the FP32 values overwrite the region
+  if (have) {
+    float* lc32 = (float*)le;
+#pragma unroll
+    for (int m = 0; m < M; ++m) lc32[(c * M + m) * TP + lp] = v[m];
+    lc32[(C * M + c) * TP + lp] = sa;
+  }
+}
+
+template <int C, typename TS>
+__device__ __forceinline__ void ep_render_convert(const Geom& g, const TileRef& r, acc_t* le, TS* coeffs) {
+  switch (g.M) {
+    case 2: ep_render_convert<C, TS, 2>(g, r, le, coeffs); break;
+    case 4: ep_render_convert<C, TS, 4>(g, r, le, coeffs); break;
+    case 8: ep_render_convert<C, TS, 8>(g, r, le, coeffs); break;
+    case 16: ep_render_convert<C, TS, 16>(g, r, le, coeffs); break;
+    default: ep_render_convert<C, TS, 32>(g, r, le, coeffs); break;
+  }
+}
+
+// Build (accumulating): coeffs += coefficients of the endpoint masses, one pixel/channel per thread.
+template <int C, typename TS, int M>
+__device__ __forceinline__ void ep_build_store(const Geom& g, const TileRef& r, const acc_t* le, TS* coeffs) {
+  const uint32_t TP = g.tile_px;
+  const uint32_t q = threadIdx.x;
+  if (q >= TP * C) return;
+  const uint32_t c = q / TP, lp = q - c * TP;
+  uint64_t p;
+  if (!tile_pixel(g, r, lp, p)) return;
+  acc_t e[M + 1], cf[M], suma;
+#pragma unroll
+  for (int m = 0; m <= M; ++m) e[m] = le[(c * (M + 1) + m) * TP + lp];
+  endpoints_to_coeffs<M>(e, cf, suma);
+  TS* gp = coeffs + (p * C + c) * M;
+  TS s[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) s[m] = narrow<TS>((float)(cf[m] + (acc_t)widen<TS>(gp[m])));
+  store_row<TS, M>(gp, s);
+}
+
+template <int C, typename TS>
+__device__ __forceinline__ void ep_build_store(const Geom& g, const TileRef& r, const acc_t* le, TS* coeffs) {
+  switch (g.M) {
+    case 2: ep_build_store<C, TS, 2>(g, r, le, coeffs); break;
+    case 4: ep_build_store<C, TS, 4>(g, r, le, coeffs); break;
+    case 8: ep_build_store<C, TS, 8>(g, r, le, coeffs); break;
+    case 16: ep_build_store<C, TS, 16>(g, r, le, coeffs); break;
+    default: ep_build_store<C, TS, 32>(g, r, le, coeffs); break;
+  }
+}
+
 // ------------------------------------------------------------------------------------------- evaluate
 
 // la is [AL][TP] of acc_t: rows 0..2 colour, then sum a (C = 1) or sum a_r, a_g, a_b (C = 3).
 // lc holds FP32 cells (CELLS) or coefficients of type T (otherwise), [C*M][TP].
-template <int C, bool CELLS, typename T>
+template <int C, bool CELLS, typename T, bool SUMA = true>
 __device__ __forceinline__ void eval_add(const T* lc, acc_t* la, const Geom& g, const Frag<C>& f) {
   const uint32_t TP = g.tile_px;
   const float x = clamp01(f.x);
@@ -269,21 +411,20 @@ __device__ __forceinline__ void eval_add(const T* lc, acc_t* la, const Geom& g, 
     const float At = fmaf(t, hi, (1.f - t) * lo);
     const float v = __expf(-At);
     const float alc = alpha_clamped(f.al[c]);
-    const float a = absorbance(alc);
     if (C == 1) {
       const float w = alc * v;
       atomicAdd(la + 0 * TP + f.lp, (acc_t)(w * f.rgb[0]));
       atomicAdd(la + 1 * TP + f.lp, (acc_t)(w * f.rgb[1]));
       atomicAdd(la + 2 * TP + f.lp, (acc_t)(w * f.rgb[2]));
-      atomicAdd(la + 3 * TP + f.lp, (acc_t)a);
+      if (SUMA) atomicAdd(la + 3 * TP + f.lp, (acc_t)absorbance(alc));
     } else {
       atomicAdd(la + c * TP + f.lp, (acc_t)(alc * f.rgb[c] * v));
-      atomicAdd(la + (3 + c) * TP + f.lp, (acc_t)a);
+      if (SUMA) atomicAdd(la + (3 + c) * TP + f.lp, (acc_t)absorbance(alc));
     }
   }
 }
 
-template <int C, bool CELLS, typename T>
+template <int C, bool CELLS, typename T, bool SUMA = true>
 __device__ __forceinline__ void eval_tile(const Binned& b, const Geom& g, const TileRef& r, const T* lc,
                                           acc_t* la) {
   uint32_t i = r.beg + threadIdx.x;
@@ -291,12 +432,12 @@ __device__ __forceinline__ void eval_tile(const Binned& b, const Geom& g, const 
     Frag<C> f0, f1;
     const bool ok0 = load_full<C>(b, i, f0);
     const bool ok1 = load_full<C>(b, i + blockDim.x, f1);
-    if (ok0) eval_add<C, CELLS, T>(lc, la, g, f0);
-    if (ok1) eval_add<C, CELLS, T>(lc, la, g, f1);
+    if (ok0) eval_add<C, CELLS, T, SUMA>(lc, la, g, f0);
+    if (ok1) eval_add<C, CELLS, T, SUMA>(lc, la, g, f1);
   }
   if (i < r.end) {
     Frag<C> f0;
-    if (load_full<C>(b, i, f0)) eval_add<C, CELLS, T>(lc, la, g, f0);
+    if (load_full<C>(b, i, f0)) eval_add<C, CELLS, T, SUMA>(lc, la, g, f0);
   }
 }
 
@@ -337,7 +478,15 @@ template <int C, typename TS>
 __global__ __launch_bounds__(kTileThreads) void k_build(Binned b, Geom g, TS* __restrict__ coeffs) {
   extern __shared__ acc_t smem_d[];
   acc_t* lc = smem_d;
-  const TileRef r = tile_ref(g, b, blockIdx.x);
+  const TileRef r = tile_ref(g, b, b.order[blockIdx.x]);
+  if (g.ep) {
+    for (uint32_t e = threadIdx.x; e < C * (g.M + 1) * g.tile_px; e += blockDim.x) lc[e] = 0.0;
+    __syncthreads();
+    build_ep_tile<C>(b, g, r, lc);
+    __syncthreads();
+    ep_build_store<C, TS>(g, r, lc, coeffs);
+    return;
+  }
   coeff_tile_io<C, TS, 0>(g, r, lc, coeffs);
   __syncthreads();
   build_tile<C>(b, g, r, lc);
@@ -352,7 +501,7 @@ __global__ __launch_bounds__(kTileThreads) void k_evaluate(Binned b, Geom g, con
   const uint32_t TP = g.tile_px;
   acc_t* la = smem_d;                              // [AL][TP] FP64
   float* lc = (float*)(smem_d + g.AL * TP);        // [C*M][TP] FP32
-  const TileRef r = tile_ref(g, b, blockIdx.x);
+  const TileRef r = tile_ref(g, b, b.order[blockIdx.x]);
   coeff_tile_io<C, TS, 0>(g, r, lc, const_cast<TS*>(coeffs));
   for (uint32_t lp = threadIdx.x; lp < TP; lp += blockDim.x) {
     uint64_t p;
@@ -379,9 +528,34 @@ __global__ __launch_bounds__(kTileThreads) void k_render(Binned b, Geom g, TS* _
                                                          float bg1, float bg2, float* __restrict__ out) {
   extern __shared__ acc_t smem_d[];
   const uint32_t TP = g.tile_px;
+  const TileRef r = tile_ref(g, b, b.order[blockIdx.x]);
+  const float bg[3] = {bg0, bg1, bg2};
+  if (g.ep) {
+    // LDS: endpoint masses [C*(M+1)][TP] FP64 (then FP32 cells [C*M][TP] and sums of a [C][TP] in their
+    // place), colour sums [3][TP] FP64
+    acc_t* le = smem_d;
+    acc_t* la = smem_d + C * (g.M + 1) * TP;
+    for (uint32_t e = threadIdx.x; e < (C * (g.M + 1) + 3) * TP; e += blockDim.x) smem_d[e] = 0.0;
+    __syncthreads();
+    build_ep_tile<C>(b, g, r, le);
+    __syncthreads();
+    ep_render_convert<C, TS>(g, r, le, coeffs);
+    __syncthreads();
+    const float* cells = (const float*)le;
+    eval_tile<C, true, float, false>(b, g, r, cells, la);
+    __syncthreads();
+    const float* sa = cells + C * g.M * TP;
+    for (uint32_t lp = threadIdx.x; lp < TP; lp += blockDim.x) {
+      uint64_t p;
+      if (!tile_pixel(g, r, lp, p)) continue;
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        out[p * 3 + q] = (float)la[q * TP + lp] + bg[q] * __expf(-sa[(C == 1 ? 0 : q) * TP + lp]);
+    }
+    return;
+  }
   acc_t* lc = smem_d;                    // [C*M][TP] FP64, then FP32 cells in its first half (CELLS)
   acc_t* la = smem_d + C * g.M * TP;     // [AL][TP] FP64
-  const TileRef r = tile_ref(g, b, blockIdx.x);
   for (uint32_t e = threadIdx.x; e < (C * g.M + g.AL) * TP; e += blockDim.x) smem_d[e] = 0.0;
   __syncthreads();
   build_tile<C>(b, g, r, lc);
@@ -397,7 +571,6 @@ __global__ __launch_bounds__(kTileThreads) void k_render(Binned b, Geom g, TS* _
     eval_tile<C, false, acc_t>(b, g, r, lc, la);
   }
   __syncthreads();
-  const float bg[3] = {bg0, bg1, bg2};
   for (uint32_t lp = threadIdx.x; lp < TP; lp += blockDim.x) {
     uint64_t p;
     if (!tile_pixel(g, r, lp, p)) continue;
@@ -424,7 +597,10 @@ __global__ __launch_bounds__(256) void k_resolve(const float* __restrict__ accum
 
 // ------------------------------------------------------------------------------------------- launchers
 
+// LDS of the render (with_accum) and build kernels: endpoint masses (+ three colour sums), or coefficient
+// sums (+ AL accumulations).
 size_t lds_tile_bytes(const Geom& g, bool with_accum) {
+  if (g.ep) return (size_t)g.tile_px * (g.C * (g.M + 1) + (with_accum ? 3 : 0)) * sizeof(acc_t);
   return (size_t)g.tile_px * (g.C * g.M + (with_accum ? g.AL : 0)) * sizeof(acc_t);
 }
 

@@ -127,6 +127,18 @@ def bin(spec: FrameSpec, frags: Fragments, ws: Workspace, stream=None):
                           _stream(stream)), "wt_bin")
 
 
+def bin_count(spec: FrameSpec, frags: Fragments, ws: Workspace, stream=None):
+    """First half of :func:`bin`: per-tile counts and segment layout."""
+    _lib.check(_lib.load().wt_bin_count(C.byref(spec.c_desc()), C.byref(frags.c_struct(spec.channels)), ws.ptr,
+                                        ws.nbytes, _stream(stream)), "wt_bin_count")
+
+
+def bin_scatter(spec: FrameSpec, frags: Fragments, ws: Workspace, stream=None):
+    """Second half of :func:`bin`: copy the stream into its tile segments (after :func:`bin_count`)."""
+    _lib.check(_lib.load().wt_bin_scatter(C.byref(spec.c_desc()), C.byref(frags.c_struct(spec.channels)), ws.ptr,
+                                          ws.nbytes, _stream(stream)), "wt_bin_scatter")
+
+
 def build_binned(spec: FrameSpec, coeffs: torch.Tensor, ws: Workspace, stream=None):
     _check(coeffs, (TORCH_DTYPES[spec.dtype],), spec.coeff_shape(), "coeffs")
     _lib.check(_lib.load().wt_build_binned(C.byref(spec.c_desc()), _ptr(coeffs), ws.ptr, ws.nbytes, _stream(stream)),

@@ -194,3 +194,25 @@ def poisson_arrivals(seed, n, rate_hz, resolutions=REQUEST_RESOLUTIONS, ranks=(3
     seeds = rng.integers(0, 2 ** 31 - 1, n)
     return [dict(t=float(t[i]), width=resolutions[res[i]][0], height=resolutions[res[i]][1], rank=ranks[rk[i]],
                  dtype=dtypes[dt[i]], seed=int(seeds[i])) for i in range(n)]
+
+
+def torch_frame(seed, width, height, mean=24.0, rank=3, device="cuda"):
+    """Device-side generator with the c1/c4 distributions (Poisson(mean) fragments/px, depth in (0.05, 1],
+    alpha U[0.05, 0.6], rgb U[0,1]^3, shuffled), seeded with torch's generator on the device. Returns
+    (pixel int32, depth, alpha, rgb) device tensors. Used where NumPy generation of many large frames would be
+    too slow (serving traces); it is not bit-compatible with the NumPy streams."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    P = width * height
+    counts = torch.poisson(torch.full((P,), float(mean), device=device), generator=g).to(torch.int64)
+    pixel = torch.repeat_interleave(torch.arange(P, device=device, dtype=torch.int32), counts)
+    F = int(pixel.numel())
+    perm = torch.randperm(F, generator=g, device=device)
+    pixel = pixel[perm].contiguous()
+    del perm
+    depth = (1.0 - 0.95 * torch.rand(F, generator=g, device=device)).contiguous()
+    alpha = (0.05 + 0.55 * torch.rand(F, generator=g, device=device)).contiguous()
+    rgb = torch.rand((F, 3), generator=g, device=device).contiguous()
+    return pixel, depth, alpha, rgb
+

@@ -180,3 +180,20 @@ def test_smoke_1080p_64_sampled(orc, rank):
     say("  max |out - oracle| on %d sampled pixels: %.2e" % (sel.size, err))
     del fr, ws, coeffs, out
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("width,height", [(1200, 1100), (2000, 1100)])
+def test_many_tiles(orc, width, height):
+    """Three channels at rank 4 use 16 x 8 tiles: about 10,000 tiles (LDS-staged binning with large tile tables)
+    and about 17,000 tiles (one cursor atomic per fragment)."""
+    f = synth.frame_c3(seed=width, width=width, height=height, rank=4, particles=1.0)
+    say("case many tiles", width, height, "F", f.count)
+    g = gpu_render(f)
+    rng = np.random.default_rng(width)
+    sel = np.unique(rng.choice(f.pixels, 3000, replace=False))
+    mask = np.zeros(f.pixels, bool)
+    mask[sel] = True
+    o = oracle_frame(orc, f, mask=mask, want=("coeffs", "out"))
+    assert g["dropped"] == 0
+    assert_coeffs(g["coeffs"], o["coeffs"], sel=sel)
+    assert_close_abs(g["out"], o["out"], 1e-4, sel=sel)

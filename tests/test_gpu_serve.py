@@ -1,0 +1,58 @@
+"""Serving on the GPU: every request's composite is the same alone and in a concurrent mix of frame sizes, ranks
+and storage types (within the parity tolerance), and the mix really overlaps on the device."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def test_served_results_match_solo(orc):
+    import torch
+    import paper_2201_00094_amd as wt
+    from paper_2201_00094_amd.serve import FrameRequest, GpuExecutor, Server
+
+    shapes = [(64, 48, 3, "f32"), (200, 120, 4, "f32"), (320, 240, 3, "f16"), (96, 96, 4, "bf16"),
+              (257, 131, 3, "f32"), (500, 300, 4, "f16")]
+    pool = []
+    for i, (w, h, rank, dt) in enumerate(shapes):
+        f = synth.frame_c4(seed=i, width=w, height=h, rank=rank, mean=24.0)
+        fr = wt.Fragments.from_numpy(f.pixel, f.depth, f.alpha, f.rgb)
+        spec = wt.FrameSpec(w, h, rank, 1, dt)
+        solo = wt.render(spec, fr, f.bg, wt.Workspace(spec, f.count))
+        pool.append((f, fr, spec, solo))
+    torch.cuda.synchronize()
+    say("case serving mix of", len(pool), "frames")
+    srv = Server(GpuExecutor(slots=4), slots=4, budget_bytes=8 << 30)
+    futs = []
+    for rep in range(4):
+        for i, (f, fr, spec, _) in enumerate(pool):
+            futs.append(srv.submit(FrameRequest(spec.width, spec.height, spec.rank, fr, dtype=spec.dtype, bg=f.bg,
+                                                tag=(rep, i))))
+    results = [fu.result(timeout=120) for fu in futs]
+    srv.close()
+    torch.cuda.synchronize()
+    worst = 0.0
+    for r in results:
+        f, fr, spec, solo = pool[r.tag[1]]
+        d = float((r.out - solo).abs().max())
+        worst = max(worst, d)
+        assert d <= 1e-5, (r.tag, d)
+    # the first frame against the oracle too
+    f, fr, spec, solo = pool[0]
+    o = orc.resolve(f.width, f.height, f.rank, f.pixel, f.depth, f.alpha, f.rgb, bg=f.bg, want=("out",))["out"]
+    assert np.abs(solo.cpu().double().numpy() - o).max() <= 1e-4
+    s = srv.stats.summary()
+    say("  served %d requests, worst |served - solo| %.2e, max in flight %d, p50 %.3f ms p99 %.3f ms" %
+        (s["completed"], worst, s["max_inflight"], s["p50_ms"], s["p99_ms"]))
+    assert s["completed"] == len(futs)
+    assert s["max_inflight"] >= 2

@@ -1,0 +1,147 @@
+"""Scheduler of the serving loop, driven on the CPU by an executor that runs the FP64 oracle on worker threads.
+The GPU path of the same scheduler is tested in test_gpu_serve.py."""
+import threading
+import time
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import synth
+from paper_2201_00094_amd.serve import FrameRequest, FrameResult, RequestTooLarge, Server
+
+
+class OracleExecutor:
+    """Fake device: each launch resolves the frame with the oracle on a worker thread; footprint is a simple
+    function of the frame so tests can reason about admission."""
+
+    def __init__(self, orc, workers=4, delay=0.0, fail_tag=None):
+        self.orc = orc
+        self.pool = ThreadPoolExecutor(workers)
+        self.delay = delay
+        self.fail_tag = fail_tag
+        self.lock = threading.Lock()
+        self.active = 0
+        self.max_active = 0
+
+    def footprint(self, req):
+        return req.pixels * 100 + req.count * 10
+
+    def _run(self, req):
+        with self.lock:
+            self.active += 1
+            self.max_active = max(self.max_active, self.active)
+        try:
+            if self.delay:
+                time.sleep(self.delay)
+            f = req.frags
+            r = self.orc.resolve(req.width, req.height, req.rank, f.pixel, f.depth, f.alpha, f.rgb, bg=req.bg,
+                                 want=("out",))
+            return r["out"]
+        finally:
+            with self.lock:
+                self.active -= 1
+
+    def launch(self, req, slot):
+        if self.fail_tag is not None and req.tag == self.fail_tag:
+            raise RuntimeError("launch failed on purpose")
+        return self.pool.submit(self._run, req)
+
+    def done(self, h):
+        return h.done()
+
+    def finish(self, h):
+        return FrameResult(out=h.result())
+
+
+def _req(seed, w, h, rank=3, tag=None):
+    f = synth.frame_c1(seed=seed, width=w, height=h, rank=rank, mean=4.0)
+    return FrameRequest(w, h, rank, f, bg=(0.2, 0.2, 0.2), tag=tag)
+
+
+def test_all_requests_complete_with_their_own_result(orc):
+    ex = OracleExecutor(orc)
+    srv = Server(ex, slots=3, budget_bytes=10 ** 9)
+    reqs = [_req(s, 8 + s, 5 + (s % 3), tag=s) for s in range(12)]
+    futs = [srv.submit(r) for r in reqs]
+    res = [f.result(timeout=60) for f in futs]
+    srv.close()
+    for r, q in zip(res, reqs):
+        assert r.tag == q.tag
+        alone = orc.resolve(q.width, q.height, q.rank, q.frags.pixel, q.frags.depth, q.frags.alpha, q.frags.rgb,
+                            bg=q.bg, want=("out",))["out"]
+        np.testing.assert_array_equal(r.out, alone)
+        assert r.t_submit <= r.t_admit <= r.t_done
+    s = srv.stats.summary()
+    assert s["completed"] == 12 and s["max_inflight"] <= 3 and ex.max_active <= 3
+
+
+def test_budget_is_never_exceeded_and_big_requests_serialise(orc):
+    ex = OracleExecutor(orc, delay=0.02)
+    big = [_req(100 + i, 40, 30, tag="big%d" % i) for i in range(3)]
+    fp = max(ex.footprint(r) for r in big)
+    srv = Server(ex, slots=4, budget_bytes=int(fp * 1.5))
+    futs = [srv.submit(r) for r in big]
+    for f in futs:
+        f.result(timeout=60)
+    srv.close()
+    assert srv.stats.max_inflight == 1
+    assert srv.stats.max_bytes_inflight <= int(fp * 1.5)
+
+
+def test_oversized_request_is_rejected(orc):
+    ex = OracleExecutor(orc)
+    srv = Server(ex, slots=2, budget_bytes=1000)
+    fut = srv.submit(_req(1, 16, 16))
+    with pytest.raises(RequestTooLarge):
+        fut.result(timeout=10)
+    srv.close()
+    assert srv.stats.rejected == 1
+
+
+def test_backfill_admits_small_requests_behind_a_blocked_one(orc):
+    ex = OracleExecutor(orc, delay=0.05)
+    a = _req(1, 40, 30, tag="a")
+    blocked = _req(2, 40, 30, tag="blocked")
+    smalls = [_req(10 + i, 4, 4, tag="s%d" % i) for i in range(3)]
+    fa = ex.footprint(a)
+    srv = Server(ex, slots=4, budget_bytes=int(fa * 1.6), max_bypass=8)
+    futs = [srv.submit(a), srv.submit(blocked)] + [srv.submit(r) for r in smalls]
+    res = {f.result(timeout=60).tag: f.result() for f in futs}
+    srv.close()
+    # the small requests started before the blocked big one (it had to wait for `a`)
+    assert all(res["s%d" % i].t_admit < res["blocked"].t_admit for i in range(3))
+
+
+def test_bypass_limit_stops_backfilling(orc):
+    ex = OracleExecutor(orc, delay=0.03)
+    a = _req(1, 40, 30, tag="a")
+    blocked = _req(2, 40, 30, tag="blocked")
+    smalls = [_req(10 + i, 4, 4, tag="s%d" % i) for i in range(6)]
+    fa = ex.footprint(a)
+    srv = Server(ex, slots=8, budget_bytes=int(fa * 1.6), max_bypass=2)
+    futs = [srv.submit(a), srv.submit(blocked)] + [srv.submit(r) for r in smalls]
+    res = {f.result(timeout=60).tag: f.result() for f in futs}
+    srv.close()
+    passed = sum(res["s%d" % i].t_admit < res["blocked"].t_admit for i in range(6))
+    assert passed <= 2
+
+
+def test_launch_failure_is_reported_and_releases_resources(orc):
+    ex = OracleExecutor(orc, fail_tag="bad")
+    srv = Server(ex, slots=1, budget_bytes=10 ** 9)
+    f_bad = srv.submit(_req(1, 8, 8, tag="bad"))
+    f_ok = srv.submit(_req(2, 8, 8, tag="ok"))
+    with pytest.raises(RuntimeError):
+        f_bad.result(timeout=30)
+    assert f_ok.result(timeout=30).tag == "ok"
+    srv.close()
+
+
+def test_poisson_trace_generator():
+    tr = synth.poisson_arrivals(3, 200, rate_hz=100.0)
+    assert len(tr) == 200
+    t = np.array([r["t"] for r in tr])
+    assert (np.diff(t) > 0).all()
+    assert 1.0 < t[-1] < 4.0  # about 2 s of arrivals at 100/s
+    assert {r["rank"] for r in tr} == {3, 4} and {r["dtype"] for r in tr} == {"f32", "f16"}
