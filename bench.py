@@ -14,6 +14,9 @@ frame on the host cores.
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -27,6 +30,35 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 METRIC = "resolved fragments/s (build+eval) 1080p×64 frag/px; % HBM peak; p99 ms"
+CSRC = os.path.join(ROOT, "paper_2201_00094_amd", "csrc")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_smoke1080p.json")
+# short kernel names used in the JSON line -> prefix of the demangled name in rocprofv3's output
+KERNEL_PREFIX = {"k_scatter_staged": "void wt::k_scatter_staged<", "k_render": "void wt::k_render<",
+                 "k_hist_lds": "wt::k_hist_lds("}
+
+
+def sources_digest():
+    """SHA-256 over the kernel sources: HBM counter readings are valid only for the sources they were taken on."""
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(CSRC, "*"))):
+        if p.endswith((".hip", ".h")):
+            h.update(os.path.basename(p).encode())
+            with open(p, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, rank, dtype):
+    """HBM bytes per launch of ``kernel`` from the committed counter summary, or None when the summary was taken
+    on other kernel sources or another workload."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("sources_sha256") != sources_digest():
+        return None
+    return t.get("workloads", {}).get("r%d_%s" % (rank, dtype), {}).get(kernel)
 
 
 def algorithmic_bytes(F, P, M, coeff_bytes):
@@ -70,12 +102,16 @@ def main():
     ap.add_argument("--rank", type=int, default=3)
     ap.add_argument("--dtype", default="f32", choices=("f32", "f16", "bf16"))
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--cpu-fraction", type=float, default=0.1,
+    ap.add_argument("--cpu-fraction", type=float, default=1.0,
                     help="share of the frame's pixels the CPU oracle baseline resolves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="frame", choices=("frame", "serve", "copy"),
+    ap.add_argument("--mode", default="frame", choices=("frame", "serve", "copy", "traffic"),
                     help="frame: the headline single-frame step (default); serve: the continuous-batching trace; "
-                         "copy: a plain device copy of known size (calibrates the HBM byte counters)")
+                         "copy: a plain device copy of known size (calibrates the HBM byte counters); traffic: "
+                         "turn rocprofv3 FETCH_SIZE / WRITE_SIZE collections into the committed traffic summary")
+    ap.add_argument("--pmc", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="traffic mode: rocprofv3 output folders of the frame and copy runs")
+    ap.add_argument("--pmc-command", default="", help="traffic mode: the command the counters were taken with")
     ap.add_argument("--requests", type=int, default=200, help="serve mode: requests in the trace")
     ap.add_argument("--load", type=float, default=0.8, help="serve mode: arrival rate as a share of solo capacity")
     ap.add_argument("--budget-gb", type=float, default=32.0, help="serve mode: HBM admission budget")
@@ -92,6 +128,8 @@ def main():
         return run_serve(args)
     if args.mode == "copy":
         return run_copy(args)
+    if args.mode == "traffic":
+        return run_traffic(args)
 
     import torch
 
@@ -180,7 +218,8 @@ def main():
         "path_alg_bytes": b_alg,
         "path_hbm_frac": b_alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": dom_gbs, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": dom_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": dom_gbs / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(dom, args.rank, args.dtype),
                      "alg_bytes_per_launch": dom_bytes, "avg_ms": dom_ms},
     }
     if not args.no_cpu_baseline:
@@ -199,6 +238,67 @@ def run_copy(args):
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"mode": "copy", "bytes_read": n * 4, "bytes_written": n * 4, "copies": max(args.steps, 1)}))
+
+
+def _counter_means(folder):
+    """Mean counter value (KiB per dispatch) per demangled kernel name in a rocprofv3 --pmc csv folder."""
+    files = glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit("no counter_collection.csv under %s" % folder)
+    acc = {}
+    with open(files[0]) as fh:
+        for r in csv.DictReader(fh):
+            acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
+
+
+def run_traffic(args):
+    """FETCH_SIZE and WRITE_SIZE per dispatch of the path's kernels, each scaled by what the same counter reads
+    for the 1 GiB copy (bytes moved / counter KiB), written to the traffic summary with the kernel sources'
+    digest."""
+    fetch, write, cfetch, cwrite = (_counter_means(d) for d in args.pmc)
+    copy_name = [k for k in cfetch if "copyBuffer" in k][0]
+    gib = float(1 << 30)
+    f_scale = gib / (cfetch[copy_name][0] * 1024.0)
+    w_scale = gib / (cwrite[copy_name][0] * 1024.0)
+    key = "r%d_%s" % (args.rank, args.dtype)
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+        if t.get("sources_sha256") != sources_digest():
+            t = {}
+    except (OSError, ValueError):
+        t = {}
+    t["sources_sha256"] = sources_digest()
+    t["fetch_scale"], t["write_scale"] = f_scale, w_scale
+    t.setdefault("workloads", {})[key] = {}
+    t.setdefault("commands", {})[key] = args.pmc_command
+    rows = []
+    for short, prefix in KERNEL_PREFIX.items():
+        names = [k for k in fetch if k.startswith(prefix)]
+        if not names:
+            continue
+        fk, n = fetch[names[0]]
+        wk = write[names[0]][0]
+        by = fk * 1024.0 * f_scale + wk * 1024.0 * w_scale
+        t["workloads"][key][short] = by
+        rows.append("| `%s` | %d | %.0f | %.0f | %.4g |" % (names[0].split("(")[0], n, fk, wk, by / 1e9))
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(t, fh, indent=1, sort_keys=True)
+    md = TRAFFIC_FILE[:-5] + "_%s.md" % key
+    with open(md, "w") as fh:
+        fh.write("# HBM traffic per launch, smoke 1920x1080, Poisson(64 g) fragments/px, rank %d, %s coefficients\n\n"
+                 % (args.rank, args.dtype))
+        fh.write("Counters: rocprofv3 `--pmc FETCH_SIZE`, then `--pmc WRITE_SIZE`, in separate runs (KiB per dispatch, "
+                 "mean over dispatches). Scale: a 1 GiB device copy (`bench.py --mode copy`) reads FETCH_SIZE "
+                 "%.0f KiB and WRITE_SIZE %.0f KiB, so FETCH_SIZE is multiplied by %.4f and WRITE_SIZE by %.4f "
+                 "(bytes per KiB counted / 1024).\n\n" % (cfetch[copy_name][0], cwrite[copy_name][0], f_scale,
+                                                            w_scale))
+        fh.write("Command (per counter, from /tmp with TMPDIR=/tmp):\n\n    %s\n\n" % args.pmc_command)
+        fh.write("| Kernel | Dispatches | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) | HBM traffic (GB) |\n"
+                 "| --- | --- | --- | --- | --- |\n")
+        fh.write("\n".join(rows) + "\n")
+    print(json.dumps(t["workloads"][key]))
 
 
 def run_serve(args):

@@ -55,9 +55,16 @@ typedef enum {
   WT_ERR_UNSUPPORTED = -5
 } wt_status;
 
-/* Storage type of the coefficient array. Accumulation is always FP32 on chip; FP16 and BF16 round once,
- * to nearest even, when a coefficient tile is stored, and widen exactly when it is loaded. */
-typedef enum { WT_F32 = 0, WT_F16 = 1, WT_BF16 = 2 } wt_dtype;
+/* Storage type of the coefficient array. On-chip sums are FP64; FP32, FP16 and BF16 round once, to nearest
+ * even, when a coefficient tile is stored, and widen exactly when it is loaded.
+ * WT_E5B9G9R9 is the packed storage of section 2.1 for three channels: coefficient m of the three channels
+ * shares one 32-bit word, a 5-bit exponent e (bits 27-31, bias 15) and three 9-bit mantissas without an
+ * implicit one (B bits 18-26, G 9-17, R 0-8), value = mantissa * 2^(e - 24). Only magnitudes are stored: the
+ * closed forms of section 2.3.1 fix the signs (coefficient 0 is >= 0, every other one <= 0). The encoding is
+ * the shared-exponent texture format: values clamp to [0, 65408], the exponent is the smallest that holds the
+ * largest of the three in 9 bits after rounding half up, each mantissa rounds half up. Requires channels == 3
+ * and rank <= 4; the coefficient array is then P * M words ([P][M]). */
+typedef enum { WT_F32 = 0, WT_F16 = 1, WT_BF16 = 2, WT_E5B9G9R9 = 3 } wt_dtype;
 
 typedef struct {
   uint32_t width;       /* pixels per row, >= 1 */

@@ -72,6 +72,10 @@ def _load():
     lib.orc_alpha_used.argtypes = [C.c_double]
     lib.orc_round_storage.restype = C.c_double
     lib.orc_round_storage.argtypes = [C.c_double, C.c_int]
+    lib.orc_pack_e5b9g9r9.restype = C.c_uint32
+    lib.orc_pack_e5b9g9r9.argtypes = [C.c_float, C.c_float, C.c_float]
+    lib.orc_unpack_e5b9g9r9.restype = None
+    lib.orc_unpack_e5b9g9r9.argtypes = [C.c_uint32, _f64p]
     lib.orc_num_threads.restype = C.c_int
     lib.orc_num_threads.argtypes = []
     _lib = lib
@@ -97,13 +101,13 @@ def num_threads() -> int:
     return int(_load().orc_num_threads())
 
 
-STORAGE = {"exact": 0, "f32": 0, "f16": 1, "bf16": 2}
+STORAGE = {"exact": 0, "f32": 0, "f16": 1, "bf16": 2, "e5b9g9r9": 3}
 
 
 def resolve(width, height, rank, pixel, depth, alpha, rgb, bg=(0.0, 0.0, 0.0), channels=1, mask=None,
             want=("coeffs", "cells", "accum", "suma", "out", "vis"), threads=0, storage="exact"):
-    """FP64 wavelet resolve of one frame. ``storage`` ("exact", "f16", "bf16") rounds the coefficients to that
-    format before they are used. Returns a dict with the requested arrays:
+    """FP64 wavelet resolve of one frame. ``storage`` ("exact", "f16", "bf16", or "e5b9g9r9" for three channels)
+    rounds the coefficients to that format before they are used. Returns a dict with the requested arrays:
 
     ``coeffs``/``cells`` [P, C, M]; ``accum`` [P, 3]; ``suma`` [P, C]; ``out`` [P, 3]; ``vis`` [F, C]; and
     ``dropped`` (int). ``mask`` (bool [P]) restricts the computed pixels; the rest read as zeros (NaN in vis).
@@ -206,6 +210,17 @@ def psi(n, k, z):
 
 def absorbance(alpha):
     return float(_load().orc_absorbance(float(alpha)))
+
+
+def pack_e5b9g9r9(r, g, b):
+    """E5B9G9R9 word of three FP32 magnitudes (section 2.1 storage; the shared-exponent format)."""
+    return int(_load().orc_pack_e5b9g9r9(float(r), float(g), float(b)))
+
+
+def unpack_e5b9g9r9(word):
+    out = np.zeros(3)
+    _load().orc_unpack_e5b9g9r9(int(word), out)
+    return tuple(float(v) for v in out)
 
 
 def round_storage(v, storage):

@@ -112,11 +112,61 @@ static double round_format(double v, int mbits, int emin, int emax) {
   return r;
 }
 
-/* Coefficient storage precision: 0 = exact (FP64 here), 1 = FP16, 2 = BF16. */
+/* Coefficient storage precision: 0 = exact (FP64 here), 1 = FP16, 2 = BF16. (3, the shared-exponent packing
+ * below, works on coefficient triples and is applied by orc_round_triple.) */
 double orc_round_storage(double v, int storage) {
   if (storage == 1) return round_format(v, 10, -14, 15);
   if (storage == 2) return round_format(v, 7, -126, 127);
   return v;
+}
+
+/* Shared-exponent packing of three non-negative values into 32 bits, the E5B9G9R9 coefficient storage of
+ * section 2.1: a 5-bit exponent in the top bits, then three 9-bit mantissas (B, G, R from high to low bits)
+ * without an implicit leading one. The encoding is the published shared-exponent texture format (exponent
+ * bias 15, 9 mantissa bits): clamp each value to [0, 511/512 * 2^16] (NaN to 0); take the shared exponent from
+ * the largest, e' = max(-16, floor(log2 max)) + 1 + 15; if max rounds to 512 at that exponent, use e' + 1;
+ * each mantissa is floor(value / 2^(e - 24) + 1/2). Reading: the paper names the packing and defers its bit
+ * layout to a code supplement that is not available; the inputs are FP32 values (the precision in which the
+ * GPU path forms them), and every step below is exact in FP64. */
+uint32_t orc_pack_e5b9g9r9(float r, float g, float b) {
+  const double vmax = 511.0 / 512.0 * 65536.0;
+  double v[3] = {r, g, b};
+  double mx = 0.0;
+  for (int q = 0; q < 3; ++q) {
+    if (!(v[q] > 0.0)) v[q] = 0.0; /* negative and NaN */
+    if (v[q] > vmax) v[q] = vmax;
+    if (v[q] > mx) mx = v[q];
+  }
+  int lead = -16;
+  if (mx > 0.0) {
+    int e;
+    frexp(mx, &e); /* mx = f 2^e, f in [0.5, 1): floor(log2 mx) = e - 1 */
+    if (e - 1 > lead) lead = e - 1;
+  }
+  int es = lead + 1 + 15;
+  if (floor(ldexp(mx, 24 - es) + 0.5) == 512.0) es += 1;
+  uint32_t w = (uint32_t)es << 27;
+  for (int q = 0; q < 3; ++q) {
+    uint32_t m = (uint32_t)floor(ldexp(v[q], 24 - es) + 0.5);
+    w |= m << (9 * q); /* R in bits 0-8, G in 9-17, B in 18-26 */
+  }
+  return w;
+}
+
+void orc_unpack_e5b9g9r9(uint32_t w, double out[3]) {
+  const int es = (int)(w >> 27);
+  for (int q = 0; q < 3; ++q) out[q] = ldexp((double)((w >> (9 * q)) & 511u), es - 24);
+}
+
+/* Storage 3 for one coefficient of three channels: magnitudes packed and unpacked, signs restored (chi >= 0 and
+ * d <= 0 are fixed by the closed forms of section 2.3.1, so only magnitudes are stored). */
+void orc_round_triple(double* c0, double* c1, double* c2, int negative) {
+  const double sg = negative ? -1.0 : 1.0;
+  double out[3];
+  orc_unpack_e5b9g9r9(orc_pack_e5b9g9r9((float)(sg * *c0), (float)(sg * *c1), (float)(sg * *c2)), out);
+  *c0 = sg * out[0];
+  *c1 = sg * out[1];
+  *c2 = sg * out[2];
 }
 
 /* ------------------------------------------------------------------------------------------------ */
@@ -267,8 +317,9 @@ static uint64_t max_run(const uint64_t* start, uint64_t P) {
  *   suma   [P][C]     sum_i a_{i,c}                                      (may be NULL)
  *   out    [P][3]     S_q + bg_q exp(-suma_{c(q)})                        (may be NULL)
  *   vis    [F][C]     v_{i,c} = exp(-A~_c(x_i)); NaN for dropped fragments (may be NULL)
- * with c(q) = q when C = 3 and 0 when C = 1. storage != 0 rounds every coefficient to FP16 (1) or BF16 (2)
- * before the cell averages are formed (the method with coefficients kept at that precision).
+ * with c(q) = q when C = 3 and 0 when C = 1. storage != 0 rounds every coefficient to FP16 (1) or BF16 (2), or
+ * packs the three channels' coefficient m into one E5B9G9R9 word (3, C = 3 only), before the cell averages are
+ * formed (the method with coefficients kept at that precision).
  * mask (uint8 [P], may be NULL) restricts the pixels computed;
  * outputs of unmasked pixels are left untouched. threads <= 0 keeps the OpenMP default.
  */
@@ -276,7 +327,8 @@ int orc_resolve(uint32_t width, uint32_t height, uint32_t rank, uint32_t channel
                 const uint32_t* pixel, const float* depth, const float* alpha, const float* rgb, const double* bg,
                 const uint8_t* mask, int storage, double* coeffs, double* cells, double* accum, double* suma,
                 double* out, double* vis, uint64_t* dropped, int threads) {
-  if (rank > 12 || (channels != 1 && channels != 3) || (count && (!pixel || !depth || !alpha || !rgb)) || !bg)
+  if (rank > 12 || (channels != 1 && channels != 3) || (count && (!pixel || !depth || !alpha || !rgb)) || !bg ||
+      storage < 0 || storage > 3 || (storage == 3 && channels != 3))
     return ORC_EINVAL;
   orc_stream s = {width, height, rank, channels, count, pixel, depth, alpha, rgb};
   uint64_t P = (uint64_t)width * height;
@@ -302,9 +354,9 @@ int orc_resolve(uint32_t width, uint32_t height, uint32_t rank, uint32_t channel
     uint32_t* order = (uint32_t*)malloc(sizeof(uint32_t) * (kmax ? kmax : 1));
     double* xs = (double*)malloc(sizeof(double) * (kmax ? kmax : 1));
     double* as = (double*)malloc(sizeof(double) * (kmax ? kmax : 1));
-    double* cf = (double*)malloc(sizeof(double) * M);
+    double* cfa = (double*)malloc(sizeof(double) * M * 3);
     double* ce = (double*)malloc(sizeof(double) * M);
-    if (!order || !xs || !as || !cf || !ce) {
+    if (!order || !xs || !as || !cfa || !ce) {
 #pragma omp atomic write
       fail = 1;
     } else {
@@ -323,8 +375,18 @@ int orc_resolve(uint32_t width, uint32_t height, uint32_t rank, uint32_t channel
             xs[r] = clamp_depth(depth[i]);
             as[r] = orc_absorbance(alpha[(uint64_t)i * C + c]);
           }
-          orc_coeffs_one((int)rank, (int)k, xs, as, cf);
-          for (int m = 0; m < M; ++m) cf[m] = orc_round_storage(cf[m], storage);
+          orc_coeffs_one((int)rank, (int)k, xs, as, cfa + c * M);
+          for (int m = 0; m < M; ++m) cfa[c * M + m] = orc_round_storage(cfa[c * M + m], storage);
+        }
+        if (storage == 3)
+          for (int m = 0; m < M; ++m) orc_round_triple(cfa + m, cfa + M + m, cfa + 2 * M + m, m > 0);
+        for (int c = 0; c < C; ++c) {
+          for (uint64_t r = 0; r < k; ++r) {
+            uint32_t i = order[r];
+            xs[r] = clamp_depth(depth[i]);
+            as[r] = orc_absorbance(alpha[(uint64_t)i * C + c]);
+          }
+          double* cf = cfa + c * M;
           orc_cells_one((int)rank, cf, ce);
           if (coeffs) memcpy(coeffs + ((uint64_t)p * C + c) * M, cf, sizeof(double) * M);
           if (cells) memcpy(cells + ((uint64_t)p * C + c) * M, ce, sizeof(double) * M);
@@ -350,7 +412,7 @@ int orc_resolve(uint32_t width, uint32_t height, uint32_t rank, uint32_t channel
           for (int c = 0; c < C; ++c) suma[p * C + c] = sa[c];
       }
     }
-    free(order); free(xs); free(as); free(cf); free(ce);
+    free(order); free(xs); free(as); free(cfa); free(ce);
   }
   free(start);
   free(idx);

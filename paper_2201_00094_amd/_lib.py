@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(HERE, "libwt.so")
 WT_OK, WT_ERR_INVALID, WT_ERR_RANGE, WT_ERR_NOMEM, WT_ERR_HIP, WT_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 STATUS_NAMES = {0: "WT_OK", -1: "WT_ERR_INVALID", -2: "WT_ERR_RANGE", -3: "WT_ERR_NOMEM", -4: "WT_ERR_HIP",
                 -5: "WT_ERR_UNSUPPORTED"}
-WT_F32, WT_F16, WT_BF16 = 0, 1, 2
+WT_F32, WT_F16, WT_BF16, WT_E5B9G9R9 = 0, 1, 2, 3
 
 
 class FrameDesc(C.Structure):

@@ -32,7 +32,11 @@ wt_status check_desc(const wt_frame_desc* d) {
     return fail(WT_ERR_RANGE, "frame %ux%u has 2^32 or more pixels", d->width, d->height);
   if (d->rank > 10) return fail(WT_ERR_RANGE, "rank %u exceeds 10", d->rank);
   if (d->channels != 1 && d->channels != 3) return fail(WT_ERR_INVALID, "channels must be 1 or 3, got %u", d->channels);
-  if (d->coeff_dtype > WT_BF16) return fail(WT_ERR_INVALID, "unknown coefficient dtype %u", d->coeff_dtype);
+  if (d->coeff_dtype > WT_E5B9G9R9) return fail(WT_ERR_INVALID, "unknown coefficient dtype %u", d->coeff_dtype);
+  if (d->coeff_dtype == WT_E5B9G9R9 && d->channels != 3)
+    return fail(WT_ERR_INVALID, "E5B9G9R9 storage packs three channels (channels = %u)", d->channels);
+  if (d->coeff_dtype == WT_E5B9G9R9 && d->rank > 4)
+    return fail(WT_ERR_UNSUPPORTED, "E5B9G9R9 storage supports rank <= 4 (rank = %u)", d->rank);
   return WT_OK;
 }
 

@@ -116,7 +116,14 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(Binned b, Geom g, cons
     const bool in = px < g.W && py < g.H;
     const uint64_t p = in ? (uint64_t)py * g.W + px : 0;
     for (uint32_t e = 0; e < per; ++e) {
-      lc[e * TP + lp] = in ? widen<TS>(coeffs[p * per + e]) : 0.f;
+      if constexpr (is_e5<TS>::value) {
+        // packed storage (three channels): word [p][m] holds the magnitudes of coefficient m of every channel
+        const uint32_t c = e / g.M, m = e - c * g.M;
+        const float v = in ? e5_unpack(((const uint32_t*)coeffs)[p * g.M + m], c) : 0.f;
+        lc[e * TP + lp] = m ? -v : v;
+      } else {
+        lc[e * TP + lp] = in ? widen<TS>(coeffs[p * per + e]) : 0.f;
+      }
       ladj[e * TP + lp] = 0.0;
     }
     for (uint32_t q = 0; q < 3; ++q) lg[q * TP + lp] = in ? grad_out[p * 3 + q] : 0.f;
@@ -236,7 +243,9 @@ hipError_t launch_backward(const Geom& g, const Binned& b, const void* coeffs, c
   do {                                                    \
     if (g.dtype == WT_F32) WT_BWD_CELLS(CC, float);       \
     else if (g.dtype == WT_F16) WT_BWD_CELLS(CC, __half); \
-    else WT_BWD_CELLS(CC, bf16_t);                        \
+    else if (g.dtype == WT_BF16) WT_BWD_CELLS(CC, bf16_t); \
+    else if (CC == 3) WT_BWD_CELLS(CC, e5_t);             \
+    else err = hipErrorInvalidValue;                      \
   } while (0)
   if (g.C == 1)
     WT_BWD_TYPE(1);

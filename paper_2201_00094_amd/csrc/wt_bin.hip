@@ -57,6 +57,9 @@ Geom make_geom(const wt_frame_desc& d, bool backward) {
     px = tile_for(12 * g.C * g.M + 4 * (3 + g.C));
   } else {
     px = tile_for(8 * g.C * (g.M + 1) + 24);
+    // packed three-channel storage is converted on the endpoint path only: cap the tile so that every
+    // pixel/channel has a thread (rank <= 4 is checked by the API)
+    if (d.coeff_dtype == WT_E5B9G9R9) px = std::min<uint32_t>(px, floor_pow2(kTileThreads / g.C));
     if (g.M <= 32 && px * g.C <= kTileThreads) {
       g.ep = 1;
     } else {
@@ -307,12 +310,16 @@ template <int C>
 __device__ __forceinline__ void load_chunk(const wt_fragments& f, uint32_t base, uint32_t i0, uint32_t n, int vec,
                                            ChunkRegs<C>& r) {
   if (vec && i0 + kPer <= n) {
+    // pixel ids first: the tile count needs only them, and the other loads stay in flight meanwhile
+#pragma unroll
+    for (uint32_t v = 0; v < kPer / 4; ++v) {
+      const uint4 p4 = *(const uint4*)(f.pixel + (uint64_t)base + i0 + 4 * v);
+      r.p[4 * v + 0] = p4.x; r.p[4 * v + 1] = p4.y; r.p[4 * v + 2] = p4.z; r.p[4 * v + 3] = p4.w;
+    }
 #pragma unroll
     for (uint32_t v = 0; v < kPer / 4; ++v) {
       const uint64_t i = (uint64_t)base + i0 + 4 * v;
-      const uint4 p4 = *(const uint4*)(f.pixel + i);
       const float4 x4 = *(const float4*)(f.depth + i);
-      r.p[4 * v + 0] = p4.x; r.p[4 * v + 1] = p4.y; r.p[4 * v + 2] = p4.z; r.p[4 * v + 3] = p4.w;
       r.x[4 * v + 0] = x4.x; r.x[4 * v + 1] = x4.y; r.x[4 * v + 2] = x4.z; r.x[4 * v + 3] = x4.w;
 #pragma unroll
       for (int q = 0; q < C; ++q) {
@@ -397,8 +404,20 @@ __device__ __forceinline__ void block_scan_inplace(uint32_t* cnt, uint32_t nt, u
   }
 }
 
-// LDS: srec[S][D] one round of sorted records, sg[S] their global slots, cnt[nt], gb[nt]. The chunk's sorted
-// order is written in rounds of S records (S = stage, a power of two chosen by the host to fit the LDS).
+// A record as it is stored: N dwords, 4-byte aligned, so that one lane writes one record with one wide store and
+// consecutive lanes write consecutive records.
+template <uint32_t N>
+struct Words {
+  uint32_t w[N];
+};
+
+// Staged record in LDS: the head dwords followed by the record's global slot, padded to whole 16-byte units
+// (SH of them), then the tail dwords padded likewise (ST units).
+constexpr uint32_t staged_head_units(uint32_t C) { return (head_dwords(C) + 1 + 3) / 4; }
+constexpr uint32_t staged_tail_units(bool idx) { return (tail_dwords(idx) + 3) / 4; }
+
+// LDS: srec[S][SH + ST] uint4 one round of sorted records, cnt[nt], gb[nt]. The chunk's sorted order is written in
+// rounds of S records (S = stage, a power of two chosen by the host to fit the LDS).
 template <int C, bool IDX, int THREADS>
 __global__ __launch_bounds__(THREADS) void k_scatter_staged(wt_fragments f, Geom g, int vec,
                                                                     uint32_t stage,
@@ -406,11 +425,11 @@ __global__ __launch_bounds__(THREADS) void k_scatter_staged(wt_fragments f, Geom
                                                                     uint32_t* __restrict__ head,
                                                                     uint32_t* __restrict__ tail,
                                                                     unsigned long long* __restrict__ dropped) {
-  constexpr uint32_t D = record_dwords(C, IDX), DH = head_dwords(C), DT = tail_dwords(IDX);
-  extern __shared__ uint32_t sm[];
-  uint32_t* srec = sm;
-  uint32_t* sg = srec + stage * D;
-  uint32_t* cnt = sg + stage;
+  constexpr uint32_t DH = head_dwords(C), DT = tail_dwords(IDX);
+  constexpr uint32_t SH = staged_head_units(C), ST = staged_tail_units(IDX), SU = SH + ST;
+  extern __shared__ uint4 sm4[];
+  uint4* srec = sm4;
+  uint32_t* cnt = (uint32_t*)(srec + (size_t)stage * SU);
   uint32_t* gb = cnt + g.ntiles;
   __shared__ uint32_t wsum[THREADS / 64];
   __shared__ uint32_t nvalid;
@@ -453,21 +472,43 @@ __global__ __launch_bounds__(THREADS) void k_scatter_staged(wt_fragments f, Geom
 #pragma unroll
     for (uint32_t k = 0; k < kPer; ++k) {
       if (sp[k] < r0 || sp[k] >= r0 + stage) continue;  // also skips invalid slots (0xffffffff)
-      const uint32_t s = sp[k] - r0;
-      uint32_t* d = srec + s * D;
+      uint32_t hw[4 * SH], tw[4 * ST];
 #pragma unroll
-      for (uint32_t j = 0; j < D; ++j) d[j] = record_word<C>(r, k, local[k], base + i0 + k, j);
-      sg[s] = gb[tile[k]] + rank[k];
+      for (uint32_t j = 0; j < 4 * SH; ++j)
+        hw[j] = j < DH ? record_word<C>(r, k, local[k], base + i0 + k, j) : gb[tile[k]] + rank[k];
+#pragma unroll
+      for (uint32_t j = 0; j < 4 * ST; ++j) tw[j] = j < DT ? record_word<C>(r, k, local[k], base + i0 + k, DH + j) : 0u;
+      uint4* d = srec + (size_t)(sp[k] - r0) * SU;
+#pragma unroll
+      for (uint32_t u = 0; u < SH; ++u) d[u] = make_uint4(hw[4 * u], hw[4 * u + 1], hw[4 * u + 2], hw[4 * u + 3]);
+#pragma unroll
+      for (uint32_t u = 0; u < ST; ++u)
+        d[SH + u] = make_uint4(tw[4 * u], tw[4 * u + 1], tw[4 * u + 2], tw[4 * u + 3]);
     }
     __syncthreads();
     const uint32_t ns = std::min(stage, total - r0);
-    for (uint32_t j = threadIdx.x; j < ns * DH; j += blockDim.x) {
-      const uint32_t s = j / DH, w = j - s * DH;
-      head[(uint64_t)sg[s] * DH + w] = srec[s * D + w];
-    }
-    for (uint32_t j = threadIdx.x; j < ns * DT; j += blockDim.x) {
-      const uint32_t s = j / DT, w = j - s * DT;
-      tail[(uint64_t)sg[s] * DT + w] = srec[s * D + DH + w];
+    for (uint32_t sidx = threadIdx.x; sidx < ns; sidx += blockDim.x) {
+      const uint4* q = srec + (size_t)sidx * SU;
+      uint32_t hw[4 * SH], tw[4 * ST];
+#pragma unroll
+      for (uint32_t u = 0; u < SH; ++u) {
+        const uint4 v = q[u];
+        hw[4 * u] = v.x; hw[4 * u + 1] = v.y; hw[4 * u + 2] = v.z; hw[4 * u + 3] = v.w;
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < ST; ++u) {
+        const uint4 v = q[SH + u];
+        tw[4 * u] = v.x; tw[4 * u + 1] = v.y; tw[4 * u + 2] = v.z; tw[4 * u + 3] = v.w;
+      }
+      const uint64_t slot = hw[DH];
+      Words<DH> h;
+#pragma unroll
+      for (uint32_t j = 0; j < DH; ++j) h.w[j] = hw[j];
+      Words<DT> t;
+#pragma unroll
+      for (uint32_t j = 0; j < DT; ++j) t.w[j] = tw[j];
+      *(Words<DH>*)(head + slot * DH) = h;
+      *(Words<DT>*)(tail + slot * DT) = t;
     }
     __syncthreads();
   }
@@ -511,13 +552,13 @@ template <int C, bool IDX, int THREADS>
 static hipError_t launch_scatter_t(const Geom& g, const wt_fragments& f, int vec, uint32_t* cursors, uint32_t* head,
                                    uint32_t* tail, unsigned long long* dropped, uint32_t nchunks, hipStream_t s) {
   if (g.lds_bins) {
-    constexpr uint32_t D = record_dwords(C, IDX);
+    constexpr uint32_t SU = staged_head_units(C) + staged_tail_units(IDX);
     // largest power-of-two round that fits beside the tile tables (1 KB left for static LDS); with 512 threads
     // the round is capped so that two workgroups share a compute unit
     const size_t budget = (THREADS == 512 ? kLdsBytes / 2 : kLdsBytes) - 1024;
     uint32_t stage = g.chunk;
-    while (stage > 256 && (size_t)(stage * (D + 1) + 2 * g.ntiles) * 4 > budget) stage >>= 1;
-    const size_t lds = (size_t)(stage * (D + 1) + 2 * g.ntiles) * 4;
+    while (stage > 256 && (size_t)stage * SU * 16 + 8ull * g.ntiles > budget) stage >>= 1;
+    const size_t lds = (size_t)stage * SU * 16 + 8ull * g.ntiles;
     auto k = k_scatter_staged<C, IDX, THREADS>;
     if (lds > 65536) {
       hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -42,6 +42,47 @@ __device__ __forceinline__ bf16_t narrow<bf16_t>(float v) {
   return r;
 }
 
+// E5B9G9R9 coefficient storage (section 2.1): one 32-bit word per coefficient index holds the magnitudes of the
+// three channels' coefficients, a shared 5-bit exponent (bias 15) in bits 27-31 and 9-bit mantissas without an
+// implicit one, B in bits 18-26, G in 9-17, R in 0-8; value = mantissa * 2^(e - 24).
+struct e5_t {
+  uint32_t u;
+};
+template <typename T>
+struct is_e5 {
+  static constexpr bool value = false;
+};
+template <>
+struct is_e5<e5_t> {
+  static constexpr bool value = true;
+};
+
+// Shared-exponent encoding: clamp to [0, 511/512 * 2^16] (NaN and negatives to 0); exponent from the largest,
+// e = max(-16, floor(log2 max)) + 16, bumped by one if the largest rounds to 512 at e; each mantissa is
+// floor(v * 2^(24 - e) + 1/2). The scaled values are exact in FP32 (power-of-two scaling) and the rounding is
+// taken in FP64, where adding 1/2 is exact.
+__device__ __forceinline__ uint32_t e5_pack(float r, float g, float b) {
+  float v[3] = {r, g, b};
+  float mx = 0.f;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    v[q] = v[q] > 0.f ? fminf(v[q], 65408.f) : 0.f;
+    mx = fmaxf(mx, v[q]);
+  }
+  int lead = -16;
+  if (mx >= 0x1p-16f) lead = (int)((__float_as_uint(mx) >> 23) & 255u) - 127;
+  int es = lead + 16;
+  if (floor((double)ldexpf(mx, 24 - es) + 0.5) == 512.0) ++es;
+  uint32_t w = (uint32_t)es << 27;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) w |= (uint32_t)floor((double)ldexpf(v[q], 24 - es) + 0.5) << (9 * q);
+  return w;
+}
+
+__device__ __forceinline__ float e5_unpack(uint32_t w, int q) {
+  return ldexpf((float)((w >> (9 * q)) & 511u), (int)(w >> 27) - 24);
+}
+
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

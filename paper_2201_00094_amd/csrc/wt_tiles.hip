@@ -208,6 +208,7 @@ __device__ __forceinline__ void store_row(TS* dst, const TS (&s)[M]) {
 // of the same LDS region. Requires TP * C <= blockDim.x: each thread holds at most one pixel/channel.
 template <int C, typename TS, int M>
 __device__ __forceinline__ void coeffs_to_cells(const Geom& g, const TileRef& r, acc_t* lc64, TS* coeffs) {
+  if constexpr (!is_e5<TS>::value) {  // packed storage runs the endpoint path only (make_geom)
   const uint32_t TP = g.tile_px;
   const uint32_t q = threadIdx.x;
   const bool have = q < TP * C;
@@ -229,6 +230,7 @@ __device__ __forceinline__ void coeffs_to_cells(const Geom& g, const TileRef& r,
     float* lc32 = (float*)lc64;
 #pragma unroll
     for (int m = 0; m < M; ++m) lc32[(c * M + m) * TP + lp] = v[m];
+  }
   }
 }
 
@@ -272,14 +274,17 @@ __device__ __forceinline__ void build_ep_add(acc_t* le, const Geom& g, const Fra
 template <int C>
 __device__ __forceinline__ void build_ep_tile(const Binned& b, const Geom& g, const TileRef& r, acc_t* le) {
   uint32_t i = r.beg + threadIdx.x;
-  for (; i + blockDim.x < r.end; i += 2 * blockDim.x) {
-    Frag<C> f0, f1;
-    const bool ok0 = load_head<C>(b, i, f0);
-    const bool ok1 = load_head<C>(b, i + blockDim.x, f1);
-    if (ok0) build_ep_add<C>(le, g, f0);
-    if (ok1) build_ep_add<C>(le, g, f1);
+  // four 12-byte head records per thread in flight per step
+  for (; i + 3 * blockDim.x < r.end; i += 4 * blockDim.x) {
+    Frag<C> f[4];
+    bool ok[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) ok[u] = load_head<C>(b, i + u * blockDim.x, f[u]);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (ok[u]) build_ep_add<C>(le, g, f[u]);
   }
-  if (i < r.end) {
+  for (; i < r.end; i += blockDim.x) {
     Frag<C> f0;
     if (load_head<C>(b, i, f0)) build_ep_add<C>(le, g, f0);
   }
@@ -352,6 +357,129 @@ __device__ __forceinline__ void ep_render_convert(const Geom& g, const TileRef& 
     case 8: ep_render_convert<C, TS, 8>(g, r, le, coeffs); break;
     case 16: ep_render_convert<C, TS, 16>(g, r, le, coeffs); break;
     default: ep_render_convert<C, TS, 32>(g, r, le, coeffs); break;
+  }
+}
+
+// ------------------------------------------------------------------------------------------- E5B9G9R9 storage
+//
+// Three channels share one word per coefficient index (wt.h). Coefficient 0 (chi) is >= 0 and every wavelet
+// coefficient <= 0 (section 2.3.1), so the words hold magnitudes and the sign is restored from the index.
+
+__device__ __forceinline__ float e5_sign(uint32_t m) { return m ? -1.f : 1.f; }
+
+// Render: endpoint masses -> coefficients -> FP32 -> packed (stored when coeffs is not null) -> the decoded
+// values -> FP32 cells; then cells [3*M][TP] and the absorbance totals [3][TP] as floats over the endpoint region.
+template <int M>
+__device__ __forceinline__ void e5_render_convert(const Geom& g, const TileRef& r, acc_t* le, uint32_t* coeffs) {
+  constexpr uint32_t C = 3;
+  const uint32_t TP = g.tile_px;
+  const uint32_t q = threadIdx.x;
+  const bool have = q < TP * C;
+  const uint32_t c = have ? q / TP : 0, lp = have ? q - c * TP : 0;
+  float fv[M];
+  float sa = 0.f;
+  if (have) {
+    acc_t e[M + 1], cf[M], suma;
+#pragma unroll
+    for (int m = 0; m <= M; ++m) e[m] = le[(c * (M + 1) + m) * TP + lp];
+    endpoints_to_coeffs<M>(e, cf, suma);
+#pragma unroll
+    for (int m = 0; m < M; ++m) fv[m] = (float)cf[m];
+    sa = (float)suma;
+  }
+  __syncthreads();  // every endpoint mass has been read
+  float* lf = (float*)le;
+  if (have) {
+#pragma unroll
+    for (int m = 0; m < M; ++m) lf[(c * M + m) * TP + lp] = fv[m];
+  }
+  __syncthreads();
+  for (uint32_t px = threadIdx.x; px < TP; px += blockDim.x) {
+    uint32_t w[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const float sg = e5_sign(m);
+      w[m] = e5_pack(sg * lf[(0 * M + m) * TP + px], sg * lf[(1 * M + m) * TP + px], sg * lf[(2 * M + m) * TP + px]);
+#pragma unroll
+      for (uint32_t c2 = 0; c2 < C; ++c2) lf[(c2 * M + m) * TP + px] = sg * e5_unpack(w[m], c2);
+    }
+    uint64_t p;
+    if (coeffs && tile_pixel(g, r, px, p)) store_row<uint32_t, M>(coeffs + p * M, w);
+  }
+  __syncthreads();
+  if (have) {
+    float v[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) v[m] = lf[(c * M + m) * TP + lp];
+    synth_regs<M>(v);
+#pragma unroll
+    for (int m = 0; m < M; ++m) lf[(c * M + m) * TP + lp] = v[m];
+    lf[(C * M + c) * TP + lp] = sa;
+  }
+}
+
+// Build (accumulating): words += the coefficients of the endpoint masses (decoded, added in FP64, rounded to
+// FP32 and packed again).
+template <int M>
+__device__ __forceinline__ void e5_build_store(const Geom& g, const TileRef& r, acc_t* le, uint32_t* coeffs) {
+  constexpr uint32_t C = 3;
+  const uint32_t TP = g.tile_px;
+  const uint32_t q = threadIdx.x;
+  const bool have = q < TP * C;
+  const uint32_t c = have ? q / TP : 0, lp = have ? q - c * TP : 0;
+  acc_t cf[M];
+  if (have) {
+    acc_t e[M + 1], suma;
+#pragma unroll
+    for (int m = 0; m <= M; ++m) e[m] = le[(c * (M + 1) + m) * TP + lp];
+    endpoints_to_coeffs<M>(e, cf, suma);
+  }
+  __syncthreads();  // every endpoint mass has been read
+  if (have) {
+#pragma unroll
+    for (int m = 0; m < M; ++m) le[(c * M + m) * TP + lp] = cf[m];
+  }
+  __syncthreads();
+  for (uint32_t px = threadIdx.x; px < TP; px += blockDim.x) {
+    uint64_t p;
+    if (!tile_pixel(g, r, px, p)) continue;
+    uint32_t* gp = coeffs + p * M;
+    uint32_t w[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const uint32_t old = gp[m];
+      const double sg = e5_sign(m);
+      float v[C];
+#pragma unroll
+      for (uint32_t c2 = 0; c2 < C; ++c2) v[c2] = (float)(sg * le[(c2 * M + m) * TP + px] + (double)e5_unpack(old, c2));
+      w[m] = e5_pack(v[0], v[1], v[2]);
+    }
+    store_row<uint32_t, M>(gp, w);
+  }
+}
+
+template <typename F>
+__device__ __forceinline__ void with_m(const Geom& g, F&& f) {
+  switch (g.M) {
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    case 16: f(std::integral_constant<int, 16>{}); break;
+    default: f(std::integral_constant<int, 32>{}); break;
+  }
+}
+
+// Load: words -> signed values of T in LDS [3*M][TP] (zero off-frame).
+template <typename T>
+__device__ __forceinline__ void e5_load_tile(const Geom& g, const TileRef& r, T* lc, const uint32_t* coeffs) {
+  const uint32_t TP = g.tile_px, M = g.M;
+  for (uint32_t q = threadIdx.x; q < TP * M; q += blockDim.x) {
+    const uint32_t lp = q / M, m = q - lp * M;
+    uint64_t p;
+    const uint32_t w = tile_pixel(g, r, lp, p) ? coeffs[p * M + m] : 0u;
+    const float sg = e5_sign(m);
+#pragma unroll
+    for (uint32_t c = 0; c < 3; ++c) lc[(c * M + m) * TP + lp] = (T)(sg * e5_unpack(w, c));
   }
 }
 
@@ -448,6 +576,10 @@ __device__ __forceinline__ void eval_tile(const Binned& b, const Geom& g, const 
 // MODE 0: load (zero off-frame), 1: store, 2: round to TS in place and store when coeffs is not null.
 template <int C, typename TS, int MODE, typename T>
 __device__ __forceinline__ void coeff_tile_io(const Geom& g, const TileRef& r, T* lc, TS* coeffs) {
+  if constexpr (is_e5<TS>::value) {
+    // packed storage: loads only (stores run on the endpoint path, make_geom)
+    if (MODE == 0) e5_load_tile<T>(g, r, lc, (const uint32_t*)coeffs);
+  } else {
   const uint32_t TP = g.tile_px, per = C * g.M;
   const uint32_t VW = g.M < 4 ? g.M : 4;
   const uint32_t groups = per / VW;
@@ -469,6 +601,7 @@ __device__ __forceinline__ void coeff_tile_io(const Geom& g, const TileRef& r, T
       }
     }
   }
+  }
 }
 
 // ------------------------------------------------------------------------------------------- kernels
@@ -484,7 +617,10 @@ __global__ __launch_bounds__(kTileThreads) void k_build(Binned b, Geom g, TS* __
     __syncthreads();
     build_ep_tile<C>(b, g, r, lc);
     __syncthreads();
-    ep_build_store<C, TS>(g, r, lc, coeffs);
+    if constexpr (is_e5<TS>::value)
+      with_m(g, [&](auto mm) { e5_build_store<decltype(mm)::value>(g, r, lc, (uint32_t*)coeffs); });
+    else
+      ep_build_store<C, TS>(g, r, lc, coeffs);
     return;
   }
   coeff_tile_io<C, TS, 0>(g, r, lc, coeffs);
@@ -539,7 +675,10 @@ __global__ __launch_bounds__(kTileThreads) void k_render(Binned b, Geom g, TS* _
     __syncthreads();
     build_ep_tile<C>(b, g, r, le);
     __syncthreads();
-    ep_render_convert<C, TS>(g, r, le, coeffs);
+    if constexpr (is_e5<TS>::value)
+      with_m(g, [&](auto mm) { e5_render_convert<decltype(mm)::value>(g, r, le, (uint32_t*)coeffs); });
+    else
+      ep_render_convert<C, TS>(g, r, le, coeffs);
     __syncthreads();
     const float* cells = (const float*)le;
     eval_tile<C, true, float, false>(b, g, r, cells, la);
@@ -626,6 +765,10 @@ static hipError_t dispatch(const Geom& g, F&& f) {
   }
   if (g.dtype == WT_F32) return f(std::integral_constant<int, 3>{}, (float*)nullptr);
   if (g.dtype == WT_F16) return f(std::integral_constant<int, 3>{}, (__half*)nullptr);
+  if (g.dtype == WT_E5B9G9R9) {
+    if (!g.ep) return hipErrorInvalidValue;  // make_geom puts packed storage on the endpoint path
+    return f(std::integral_constant<int, 3>{}, (e5_t*)nullptr);
+  }
   return f(std::integral_constant<int, 3>{}, (bf16_t*)nullptr);
 }
 

@@ -13,8 +13,9 @@ import torch
 
 from . import _lib
 
-DTYPES = {"f32": _lib.WT_F32, "f16": _lib.WT_F16, "bf16": _lib.WT_BF16}
-TORCH_DTYPES = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}
+DTYPES = {"f32": _lib.WT_F32, "f16": _lib.WT_F16, "bf16": _lib.WT_BF16, "e5b9g9r9": _lib.WT_E5B9G9R9}
+# e5b9g9r9 (three channels): one 32-bit word per coefficient index, held in an int32 tensor [P, M]
+TORCH_DTYPES = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16, "e5b9g9r9": torch.int32}
 
 
 @dataclass
@@ -43,6 +44,8 @@ class FrameSpec:
         return _lib.desc(self.width, self.height, self.rank, self.channels, DTYPES[self.dtype])
 
     def coeff_shape(self):
+        if self.dtype == "e5b9g9r9":
+            return (self.pixels, self.M)
         return (self.pixels, self.channels, self.M)
 
     def new_coeffs(self, device="cuda"):

@@ -31,8 +31,26 @@ def gpu_render(f, dtype="f32", rank=None, want_coeffs=True):
     torch.cuda.synchronize()
     res = {"out": out.cpu().double().numpy(), "dropped": wt.dropped_count(ws)}
     if want_coeffs:
-        res["coeffs"] = coeffs.float().cpu().double().numpy()
+        res.update(_coeffs_out(coeffs, dtype))
     return res
+
+
+def _coeffs_out(coeffs, dtype):
+    if dtype == "e5b9g9r9":
+        return {"words": coeffs.cpu().numpy().view(np.uint32)}
+    return {"coeffs": coeffs.float().cpu().double().numpy()}
+
+
+def e5_decode(orc, words):
+    """Signed coefficients [P, 3, M] of E5B9G9R9 words [P, M], decoded with the oracle's unpacking (coefficient 0
+    is >= 0, the others <= 0)."""
+    P, M = words.shape
+    out = np.zeros((P, 3, M))
+    for p in range(P):
+        for m in range(M):
+            v = orc.unpack_e5b9g9r9(int(words[p, m]))
+            out[p, :, m] = v if m == 0 else tuple(-x for x in v)
+    return out
 
 
 def gpu_passes(f, dtype="f32", rank=None, chunks=1):
@@ -51,8 +69,9 @@ def gpu_passes(f, dtype="f32", rank=None, chunks=1):
         wt.evaluate(spec, p, coeffs, accum, ws)
     out = wt.resolve(spec, accum, f.bg)
     torch.cuda.synchronize()
-    return {"coeffs": coeffs.float().cpu().double().numpy(), "accum": accum.cpu().double().numpy(),
-            "out": out.cpu().double().numpy()}
+    res = {"accum": accum.cpu().double().numpy(), "out": out.cpu().double().numpy()}
+    res.update(_coeffs_out(coeffs, dtype))
+    return res
 
 
 def oracle_frame(orc, f, rank=None, storage="exact", mask=None, want=("coeffs", "accum", "suma", "out")):

@@ -74,6 +74,11 @@ def test_validation_errors_before_any_launch(lib):
     assert lib.wt_bin(C.byref(_lib.desc(0, 5, 3)), C.byref(ok), ws, 1 << 30, None) == _lib.WT_ERR_INVALID
     assert lib.wt_bin(C.byref(_lib.desc(65536, 65536, 3)), C.byref(ok), ws, 1 << 30, None) == _lib.WT_ERR_RANGE
     assert lib.wt_bin(C.byref(_lib.desc(8, 8, 3, 1, 7)), C.byref(ok), ws, 1 << 30, None) == _lib.WT_ERR_INVALID
+    # packed E5B9G9R9 storage: three channels only, rank <= 4
+    e5 = _lib.WT_E5B9G9R9
+    assert lib.wt_bin(C.byref(_lib.desc(8, 8, 3, 1, e5)), C.byref(ok), ws, 1 << 30, None) == _lib.WT_ERR_INVALID
+    assert lib.wt_bin(C.byref(_lib.desc(8, 8, 5, 3, e5)), C.byref(ok), ws, 1 << 30, None) == _lib.WT_ERR_UNSUPPORTED
+    assert lib.wt_workspace_bytes(C.byref(_lib.desc(8, 8, 4, 3, e5)), 10) > 0
     bg = _lib.bg3((0, 0, 0))
     assert lib.wt_resolve(C.byref(d), None, bg, ws, None) == _lib.WT_ERR_INVALID
     assert lib.wt_render(C.byref(d), C.byref(ok), None, None, ws, ws, 1 << 30, None) == _lib.WT_ERR_INVALID

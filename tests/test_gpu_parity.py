@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_helpers import (accum_to_oracle_layout, assert_close_abs, assert_coeffs, gpu_passes, gpu_render,
+from gpu_helpers import (accum_to_oracle_layout, assert_close_abs, assert_coeffs, e5_decode, gpu_passes, gpu_render,
                          oracle_frame, say, spec_of)
 
 pytestmark = pytest.mark.gpu
@@ -102,6 +102,40 @@ def test_reduced_precision_storage(orc, dtype, step, channels):
     say("  %s: max |out - oracle(%s)| = %.2e, max |out - oracle(exact)| = %.2e" % (dtype, dtype, err_same, err_exact))
     p = gpu_passes(f, dtype=dtype)
     np.testing.assert_allclose(p["out"], g["out"], rtol=0, atol=1e-3)
+
+
+@pytest.mark.parametrize("rank", [1, 3, 4])
+def test_e5b9g9r9_storage(orc, rank):
+    """Packed three-channel storage (section 2.1): the decoded coefficients are within one step of the shared
+    exponent (max |triple| / 255) of the oracle run at the same storage; the words equal the oracle's packing of
+    the GPU's own FP32 coefficients of the same frame, bit for bit; the composite is within 2e-3 of the oracle at
+    E5B9G9R9 storage, and its error against the exact oracle is reported."""
+    f = synth.frame_c3(seed=20 + rank, width=45, height=29, rank=rank, particles=8.0)
+    say("case e5b9g9r9 rank", rank, "F", f.count)
+    g = gpu_render(f, dtype="e5b9g9r9")
+    o = oracle_frame(orc, f, storage="e5b9g9r9", want=("coeffs", "out"))
+    ex = oracle_frame(orc, f, want=("coeffs", "out"))
+    dec = e5_decode(orc, g["words"])
+    tmax = np.abs(ex["coeffs"]).max(axis=1, keepdims=True)
+    assert np.all(np.abs(dec - o["coeffs"]) <= tmax / 255.0 * (1 + 1e-6) + 1e-30)
+    assert np.all(dec[:, :, 0] >= 0) and np.all(dec[:, :, 1:] <= 0)
+    err_same = assert_close_abs(g["out"], o["out"], 2e-3, what="e5 out vs oracle at e5 storage")
+    say("  e5b9g9r9: max |out - oracle(e5)| = %.2e, max |out - oracle(exact)| = %.2e"
+        % (err_same, float(np.abs(g["out"] - ex["out"]).max())))
+    f32 = gpu_render(f, dtype="f32")["coeffs"].reshape(-1, 3, f32_M(rank))
+    words = np.array([[orc.pack_e5b9g9r9(*(abs(f32[p, :, m]))) for m in range(f32.shape[2])]
+                      for p in range(f32.shape[0])], dtype=np.uint32)
+    mism = int((words != g["words"]).sum())
+    assert mism <= max(1, words.size // 10000), "%d of %d words differ from the oracle's packing" % (mism, words.size)
+    # the separate passes store and reload the packed words
+    p = gpu_passes(f, dtype="e5b9g9r9")
+    assert np.array_equal(p["words"], g["words"]) or \
+        np.abs(e5_decode(orc, p["words"]) - dec).max() <= tmax.max() / 255.0
+    np.testing.assert_allclose(p["out"], g["out"], rtol=0, atol=2e-3)
+
+
+def f32_M(rank):
+    return 1 << (rank + 1)
 
 
 def test_order_independence_and_chunks(orc):

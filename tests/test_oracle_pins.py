@@ -341,6 +341,57 @@ def test_storage_rounding_in_resolve(orc):
     assert 0 < np.abs(h["out"] - ex["out"]).max() < 1e-2
 
 
+def test_e5b9g9r9_hand_worked(orc):
+    """Shared-exponent words worked by hand: (1, 1/2, 1/4) has exponent field 16 and mantissas 256, 128, 64;
+    1 - 2^-11 rounds up to 512 at the first exponent, so the exponent is bumped and it decodes to 1; values
+    clamp at 511/512 * 2^16; zero, negative and NaN inputs store 0."""
+    assert orc.pack_e5b9g9r9(1.0, 0.5, 0.25) == (16 << 27) | (64 << 18) | (128 << 9) | 256
+    w = orc.pack_e5b9g9r9(1.0 - 2.0 ** -11, 0.0, 0.0)
+    assert w >> 27 == 16 and orc.unpack_e5b9g9r9(w) == (1.0, 0.0, 0.0)
+    assert orc.pack_e5b9g9r9(1e9, 0.0, 0.0) == (31 << 27) | 511
+    assert orc.unpack_e5b9g9r9((31 << 27) | 511)[0] == 65408.0
+    assert orc.pack_e5b9g9r9(0.0, 0.0, 0.0) == 0
+    assert orc.pack_e5b9g9r9(-1.0, float("nan"), 2.0 ** -30) == 0
+    assert orc.unpack_e5b9g9r9(orc.pack_e5b9g9r9(3.0, 2.0, 1.0)) == (3.0, 2.0, 1.0)
+
+
+def test_e5b9g9r9_is_nearest_at_smallest_exponent(orc):
+    """Brute force over the 32 exponents: the packed word uses the smallest exponent at which the largest
+    (clamped) value is within 9 bits after rounding half up, and every component decodes to the nearest
+    multiple of that exponent's step (ties up)."""
+    rng = np.random.default_rng(11)
+    trip = (rng.random((3000, 3)) * 10.0 ** rng.uniform(-7, 5, (3000, 1))).astype(np.float32)
+    trip[::7, 1] = 0.0
+    trip[::11] *= np.float32(2.0 ** 10)
+    vmax = 511.0 / 512.0 * 65536.0
+    for r, g, b in trip:
+        v = np.minimum(np.array([r, g, b], np.float64), vmax)
+        w = orc.pack_e5b9g9r9(r, g, b)
+        e = w >> 27
+        fits = [ex for ex in range(32) if v.max() < 511.5 * 2.0 ** (ex - 24)]
+        assert e == fits[0]
+        step = 2.0 ** (e - 24)
+        dec = np.array(orc.unpack_e5b9g9r9(w))
+        assert np.all(dec - v <= step / 2) and np.all(dec - v > -step / 2)
+        assert np.all(np.abs(dec / step - np.round(dec / step)) == 0)
+
+
+def test_e5b9g9r9_in_resolve(orc):
+    """Three channels stored as E5B9G9R9: signs are kept (chi >= 0, d <= 0, stored as magnitudes) and each
+    coefficient is within half a step of the shared exponent, i.e. within max|triple| / 511."""
+    f = synth.frame_c3(seed=4, width=12, height=9, particles=6.0)
+    ex = orc.resolve(12, 9, 3, f.pixel, f.depth, f.alpha, f.rgb, channels=3, want=("coeffs", "out"))
+    e5 = orc.resolve(12, 9, 3, f.pixel, f.depth, f.alpha, f.rgb, channels=3, want=("coeffs", "out"),
+                     storage="e5b9g9r9")
+    c, q = ex["coeffs"], e5["coeffs"]
+    assert np.all(q[:, :, 0] >= 0) and np.all(q[:, :, 1:] <= 0)
+    tmax = np.abs(c).max(axis=1, keepdims=True)
+    assert np.all(np.abs(q - c) <= tmax / 511.0 * (1 + 1e-6) + 1e-30)
+    assert 0 < np.abs(e5["out"] - ex["out"]).max() < 2e-2
+    with pytest.raises(Exception):
+        orc.resolve(4, 4, 3, f.pixel[:0], f.depth[:0], f.alpha[:0, 0], f.rgb[:0], storage="e5b9g9r9")
+
+
 # ---------------------------------------------------------------------------------------------- A-buffer
 def test_abuffer_golden_two_layers(orc):
     rows = [ln.split() for ln in open(os.path.join(GOLDEN, "two_layer_abuffer.txt")) if ln.strip() and ln[0] != "#"]
