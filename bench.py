@@ -105,10 +105,14 @@ def main():
     ap.add_argument("--cpu-fraction", type=float, default=1.0,
                     help="share of the frame's pixels the CPU oracle baseline resolves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="frame", choices=("frame", "serve", "copy", "traffic"),
+    ap.add_argument("--mode", default="frame", choices=("frame", "serve", "copy", "traffic", "precision"),
                     help="frame: the headline single-frame step (default); serve: the continuous-batching trace; "
                          "copy: a plain device copy of known size (calibrates the HBM byte counters); traffic: "
-                         "turn rocprofv3 FETCH_SIZE / WRITE_SIZE collections into the committed traffic summary")
+                         "turn rocprofv3 FETCH_SIZE / WRITE_SIZE collections into the committed traffic summary; "
+                         "precision: the glass + particles frame (3840x2160, three channels) with every coefficient "
+                         "storage, timed, with errors against the FP64 oracle and the exact A-buffer")
+    ap.add_argument("--tight", action="store_true", help="per-pixel depth bounds (WT_TIGHT_DEPTH)")
+    ap.add_argument("--sample-pixels", type=int, default=4000, help="precision mode: pixels checked by the oracle")
     ap.add_argument("--pmc", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="traffic mode: rocprofv3 output folders of the frame and copy runs")
     ap.add_argument("--pmc-command", default="", help="traffic mode: the command the counters were taken with")
@@ -130,6 +134,8 @@ def main():
         return run_copy(args)
     if args.mode == "traffic":
         return run_traffic(args)
+    if args.mode == "precision":
+        return run_precision(args)
 
     import torch
 
@@ -143,7 +149,7 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    spec = wt.FrameSpec(f.width, f.height, args.rank, 1, args.dtype)
+    spec = wt.FrameSpec(f.width, f.height, args.rank, 1, args.dtype, args.tight)
     fr = wt.Fragments.from_numpy(f.pixel, f.depth, f.alpha, f.rgb, device=dev)
     ws = wt.Workspace(spec, f.count, device=dev)
     coeffs = spec.new_coeffs(device=dev)
@@ -208,7 +214,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "smoke 1920x1080, Poisson(64 g) fragments/px (unsorted stream), rank %d, %s "
-                               "coefficient storage" % (args.rank, args.dtype),
+                               "coefficient storage%s" % (args.rank, args.dtype,
+                                                         ", per-pixel depth bounds" if args.tight else ""),
                    "width": f.width, "height": f.height, "rank": args.rank, "coeff_dtype": args.dtype,
                    "fragments": F, "seed": args.seed},
         "p50_ms": float(np.percentile(frame_ms, 50)),
@@ -224,6 +231,68 @@ def main():
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(f, args.cpu_fraction, args.seed)
+    print(json.dumps(line))
+
+
+def run_precision(args):
+    """Glass + particles (3840x2160, 2-4 glass layers with per-channel alpha plus Poisson(24) particles, three
+    visibility channels): one frame per coefficient storage (f32, f16, bf16, e5b9g9r9), timed, and checked on a
+    seeded pixel sample against the FP64 oracle at exact storage and against the exact A-buffer."""
+    import torch
+
+    import oracle
+    import paper_2201_00094_amd as wt
+    import synth
+
+    t0 = time.perf_counter()
+    f = synth.frame_c3(seed=args.seed, rank=args.rank)
+    print("precision: generated %s, %d fragments in %.1f s" % (f.name, f.count, time.perf_counter() - t0),
+          file=sys.stderr, flush=True)
+    rng = np.random.default_rng(args.seed + 5)
+    sel = np.unique(rng.choice(f.pixels, args.sample_pixels, replace=False))
+    mask = np.zeros(f.pixels, bool)
+    mask[sel] = True
+    ex = oracle.resolve(f.width, f.height, f.rank, f.pixel, f.depth, f.alpha, f.rgb, bg=f.bg, channels=3, mask=mask,
+                        want=("out",), tight=args.tight)["out"][sel]
+    ab = oracle.abuffer(f.width, f.height, f.pixel, f.depth, f.alpha, f.rgb, bg=f.bg, channels=3, mask=mask)["out"][sel]
+    fr = wt.Fragments.from_numpy(f.pixel, f.depth, f.alpha, f.rgb)
+    res = {}
+    for dt in ("f32", "f16", "bf16", "e5b9g9r9"):
+        spec = wt.FrameSpec(f.width, f.height, f.rank, 3, dt, args.tight)
+        ws = wt.Workspace(spec, f.count)
+        coeffs = spec.new_coeffs()
+        out = torch.empty((spec.pixels, 3), dtype=torch.float32, device="cuda")
+        for _ in range(2):
+            wt.render(spec, fr, f.bg, ws, out=out, coeffs=coeffs)
+        torch.cuda.synchronize()
+        K = max(1, args.steps // 4)
+        t1 = time.perf_counter()
+        for _ in range(K):
+            wt.render(spec, fr, f.bg, ws, out=out, coeffs=coeffs)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t1) * 1e3 / K
+        g = out.cpu().double().numpy()[sel]
+        e_or = np.abs(g - ex)
+        e_ab = np.abs(g - ab)
+        res[dt] = {"ms_per_frame": ms, "fragments_per_s": f.count / (ms * 1e-3),
+                   "coeff_bytes_per_px": int(coeffs.element_size() * coeffs[0].numel()),
+                   "vs_oracle_exact": {"max": float(e_or.max()), "mean": float(e_or.mean()),
+                                       "p99": float(np.percentile(e_or, 99))},
+                   "vs_abuffer": {"max": float(e_ab.max()), "mean": float(e_ab.mean()),
+                                  "p99": float(np.percentile(e_ab, 99))}}
+        print("precision: %s %.3f ms/frame" % (dt, ms), file=sys.stderr, flush=True)
+        del ws, coeffs, out
+        torch.cuda.empty_cache()
+    e_wt = np.abs(ex - ab)
+    line = {"metric": "glass + particles resolve: ms/frame and composite error per coefficient storage",
+            "mode": "precision", "n_gpus": 1, "data": "synthetic", "fragments": f.count,
+            "sample_pixels": int(sel.size), "tight": bool(args.tight),
+            "oracle_exact_vs_abuffer": {"max": float(e_wt.max()), "mean": float(e_wt.mean()),
+                                        "p99": float(np.percentile(e_wt, 99))},
+            "storage": res,
+            "config": {"workload": "glass + particles %dx%d, 2-4 glass layers (per-channel alpha) + Poisson(24) "
+                                   "particles per px, rank %d, three visibility channels" % (f.width, f.height,
+                                                                                              f.rank)}}
     print(json.dumps(line))
 
 

@@ -66,12 +66,20 @@ typedef enum {
  * and rank <= 4; the coefficient array is then P * M words ([P][M]). */
 typedef enum { WT_F32 = 0, WT_F16 = 1, WT_BF16 = 2, WT_E5B9G9R9 = 3 } wt_dtype;
 
+/* wt_frame_desc.flags.
+ * WT_TIGHT_DEPTH: per-pixel depth bounds (section 2.1, step 1). Before the build, each pixel's clamped depths are
+ * mapped onto its own range, x' = (x - zmin) / (zmax - zmin) (0 when every fragment of the pixel has the same
+ * depth), and the build, evaluate and gradient use x'. zmin and zmax are taken over the fragments one call sees,
+ * so with this flag a frame's stream is passed whole to each call (no chunked accumulation). */
+#define WT_TIGHT_DEPTH 1u
+
 typedef struct {
   uint32_t width;       /* pixels per row, >= 1 */
   uint32_t height;      /* rows, >= 1; width * height < 2^32 */
   uint32_t rank;        /* N in 0..10: levels n = 0..N, M = 2^(N+1) coefficients per channel */
   uint32_t channels;    /* 1 (one visibility for r, g, b) or 3 (per-channel transmittance) */
   uint32_t coeff_dtype; /* wt_dtype */
+  uint32_t flags;       /* 0 or WT_TIGHT_DEPTH */
 } wt_frame_desc;
 
 typedef struct {

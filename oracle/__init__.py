@@ -49,13 +49,13 @@ def _load():
     vp = C.c_void_p
     lib.orc_resolve.restype = C.c_int
     lib.orc_resolve.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64, vp, vp, vp, vp, vp, vp,
-                                C.c_int, vp, vp, vp, vp, vp, vp, vp, C.c_int]
+                                C.c_int, C.c_int, vp, vp, vp, vp, vp, vp, vp, C.c_int]
     lib.orc_abuffer.restype = C.c_int
     lib.orc_abuffer.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64, vp, vp, vp, vp, vp, vp, C.c_int, vp, vp,
                                 vp, C.c_int]
     lib.orc_backward.restype = C.c_int
     lib.orc_backward.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64, vp, vp, vp, vp, vp, vp, vp,
-                                 vp, vp, C.c_int]
+                                 C.c_int, vp, vp, C.c_int]
     lib.orc_coeffs_one.restype = None
     lib.orc_coeffs_one.argtypes = [C.c_int, C.c_int, _f64p, _f64p, _f64p]
     lib.orc_cells_one.restype = None
@@ -105,9 +105,10 @@ STORAGE = {"exact": 0, "f32": 0, "f16": 1, "bf16": 2, "e5b9g9r9": 3}
 
 
 def resolve(width, height, rank, pixel, depth, alpha, rgb, bg=(0.0, 0.0, 0.0), channels=1, mask=None,
-            want=("coeffs", "cells", "accum", "suma", "out", "vis"), threads=0, storage="exact"):
+            want=("coeffs", "cells", "accum", "suma", "out", "vis"), threads=0, storage="exact", tight=False):
     """FP64 wavelet resolve of one frame. ``storage`` ("exact", "f16", "bf16", or "e5b9g9r9" for three channels)
-    rounds the coefficients to that format before they are used. Returns a dict with the requested arrays:
+    rounds the coefficients to that format before they are used; ``tight`` maps each pixel's depths onto its own
+    [zmin, zmax] (section 2.1, step 1). Returns a dict with the requested arrays:
 
     ``coeffs``/``cells`` [P, C, M]; ``accum`` [P, 3]; ``suma`` [P, C]; ``out`` [P, 3]; ``vis`` [F, C]; and
     ``dropped`` (int). ``mask`` (bool [P]) restricts the computed pixels; the rest read as zeros (NaN in vis).
@@ -127,7 +128,8 @@ def resolve(width, height, rank, pixel, depth, alpha, rgb, bg=(0.0, 0.0, 0.0), c
     bgv = np.ascontiguousarray(bg, dtype=np.float64)
     dropped = C.c_uint64(0)
     rc = lib.orc_resolve(width, height, rank, channels, F, _ptr(pixel), _ptr(depth), _ptr(alpha), _ptr(rgb), _ptr(bgv),
-                         _ptr(m), STORAGE[storage], _ptr(res["coeffs"]), _ptr(res["cells"]), _ptr(res["accum"]),
+                         _ptr(m), STORAGE[storage], int(bool(tight)), _ptr(res["coeffs"]), _ptr(res["cells"]),
+                         _ptr(res["accum"]),
                          _ptr(res["suma"]), _ptr(res["out"]), _ptr(res["vis"]), C.byref(dropped), int(threads))
     if rc != 0:
         raise RuntimeError("orc_resolve failed with %d" % rc)
@@ -158,7 +160,7 @@ def abuffer(width, height, pixel, depth, alpha, rgb, bg=(0.0, 0.0, 0.0), channel
 
 
 def backward(width, height, rank, pixel, depth, alpha, rgb, grad_out, bg=(0.0, 0.0, 0.0), channels=1, mask=None,
-             threads=0):
+             threads=0, tight=False):
     """Gradient of sum(grad_out * out) w.r.t. alpha [F, C] and rgb [F, 3], FP64."""
     lib = _load()
     pixel, depth, alpha, rgb, F = _stream(pixel, depth, alpha, rgb, channels)
@@ -171,7 +173,7 @@ def backward(width, height, rank, pixel, depth, alpha, rgb, grad_out, bg=(0.0, 0
     m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
     bgv = np.ascontiguousarray(bg, dtype=np.float64)
     rc = lib.orc_backward(width, height, rank, channels, F, _ptr(pixel), _ptr(depth), _ptr(alpha), _ptr(rgb),
-                          _ptr(bgv), _ptr(g), _ptr(m), _ptr(ga), _ptr(gr), int(threads))
+                          _ptr(bgv), _ptr(g), _ptr(m), int(bool(tight)), _ptr(ga), _ptr(gr), int(threads))
     if rc != 0:
         raise RuntimeError("orc_backward failed with %d" % rc)
     return ga, gr

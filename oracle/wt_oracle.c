@@ -68,6 +68,23 @@ static double clamp_depth(double x) {
   return x;
 }
 
+/* Depths of one pixel's fragments as the method uses them. With tight bounds (section 2.1, step 1: a depth
+ * buffer pass records each pixel's nearest and farthest transparent depth before the coefficients are built),
+ * the clamped depths are mapped affinely so that the pixel's range [zmin, zmax] becomes [0, 1]:
+ * x' = (x - zmin) / (zmax - zmin). Reading: the paper names the bounds but not the mapping; linear depth
+ * (section 2.3's choice) makes the affine map the natural one, and a pixel whose fragments share one depth
+ * maps them to 0. */
+static void pixel_depths(const float* depth, const uint32_t* order, uint64_t k, int tight, double* xs) {
+  double lo = 1.0, hi = 0.0;
+  for (uint64_t r = 0; r < k; ++r) {
+    xs[r] = clamp_depth(depth[order[r]]);
+    if (xs[r] < lo) lo = xs[r];
+    if (xs[r] > hi) hi = xs[r];
+  }
+  if (!tight) return;
+  for (uint64_t r = 0; r < k; ++r) xs[r] = hi > lo ? (xs[r] - lo) / (hi - lo) : 0.0;
+}
+
 /* 2^(e/2) for integer e, the level normalisation of the orthonormal Haar basis (2^(n/2) psi(2^n x - k)). */
 static double half_pow2(int e) {
   double r = ldexp(1.0, e / 2 - (e < 0 && (e & 1) ? 1 : 0)); /* 2^floor(e/2) */
@@ -319,13 +336,14 @@ static uint64_t max_run(const uint64_t* start, uint64_t P) {
  *   vis    [F][C]     v_{i,c} = exp(-A~_c(x_i)); NaN for dropped fragments (may be NULL)
  * with c(q) = q when C = 3 and 0 when C = 1. storage != 0 rounds every coefficient to FP16 (1) or BF16 (2), or
  * packs the three channels' coefficient m into one E5B9G9R9 word (3, C = 3 only), before the cell averages are
- * formed (the method with coefficients kept at that precision).
+ * formed (the method with coefficients kept at that precision). tight != 0 maps every pixel's depths onto its
+ * own [zmin, zmax] first (pixel_depths).
  * mask (uint8 [P], may be NULL) restricts the pixels computed;
  * outputs of unmasked pixels are left untouched. threads <= 0 keeps the OpenMP default.
  */
 int orc_resolve(uint32_t width, uint32_t height, uint32_t rank, uint32_t channels, uint64_t count,
                 const uint32_t* pixel, const float* depth, const float* alpha, const float* rgb, const double* bg,
-                const uint8_t* mask, int storage, double* coeffs, double* cells, double* accum, double* suma,
+                const uint8_t* mask, int storage, int tight, double* coeffs, double* cells, double* accum, double* suma,
                 double* out, double* vis, uint64_t* dropped, int threads) {
   if (rank > 12 || (channels != 1 && channels != 3) || (count && (!pixel || !depth || !alpha || !rgb)) || !bg ||
       storage < 0 || storage > 3 || (storage == 3 && channels != 3))
@@ -369,23 +387,16 @@ int orc_resolve(uint32_t width, uint32_t height, uint32_t rank, uint32_t channel
         qsort(order, k, sizeof(uint32_t), cmp_frag);
         double S[3] = {0.0, 0.0, 0.0};
         double sa[3] = {0.0, 0.0, 0.0};
+        pixel_depths(depth, order, k, tight, xs);
         for (int c = 0; c < C; ++c) {
-          for (uint64_t r = 0; r < k; ++r) {
-            uint32_t i = order[r];
-            xs[r] = clamp_depth(depth[i]);
-            as[r] = orc_absorbance(alpha[(uint64_t)i * C + c]);
-          }
+          for (uint64_t r = 0; r < k; ++r) as[r] = orc_absorbance(alpha[(uint64_t)order[r] * C + c]);
           orc_coeffs_one((int)rank, (int)k, xs, as, cfa + c * M);
           for (int m = 0; m < M; ++m) cfa[c * M + m] = orc_round_storage(cfa[c * M + m], storage);
         }
         if (storage == 3)
           for (int m = 0; m < M; ++m) orc_round_triple(cfa + m, cfa + M + m, cfa + 2 * M + m, m > 0);
         for (int c = 0; c < C; ++c) {
-          for (uint64_t r = 0; r < k; ++r) {
-            uint32_t i = order[r];
-            xs[r] = clamp_depth(depth[i]);
-            as[r] = orc_absorbance(alpha[(uint64_t)i * C + c]);
-          }
+          for (uint64_t r = 0; r < k; ++r) as[r] = orc_absorbance(alpha[(uint64_t)order[r] * C + c]);
           double* cf = cfa + c * M;
           orc_cells_one((int)rank, cf, ce);
           if (coeffs) memcpy(coeffs + ((uint64_t)p * C + c) * M, cf, sizeof(double) * M);
@@ -534,7 +545,8 @@ int orc_abuffer(uint32_t width, uint32_t height, uint32_t channels, uint64_t cou
  */
 int orc_backward(uint32_t width, uint32_t height, uint32_t rank, uint32_t channels, uint64_t count,
                  const uint32_t* pixel, const float* depth, const float* alpha, const float* rgb, const double* bg,
-                 const double* grad_out, const uint8_t* mask, double* grad_alpha, double* grad_rgb, int threads) {
+                 const double* grad_out, const uint8_t* mask, int tight, double* grad_alpha, double* grad_rgb,
+                 int threads) {
   if (rank > 12 || (channels != 1 && channels != 3) || (count && (!pixel || !depth || !alpha || !rgb)) || !bg ||
       !grad_out || !grad_alpha || !grad_rgb)
     return ORC_EINVAL;
@@ -579,12 +591,11 @@ int orc_backward(uint32_t width, uint32_t height, uint32_t rank, uint32_t channe
         memcpy(order, idx + start[p], sizeof(uint32_t) * k);
         qsort(order, k, sizeof(uint32_t), cmp_frag);
         const double* g = grad_out + p * 3;
+        pixel_depths(depth, order, k, tight, xs);
         for (int c = 0; c < C; ++c) {
           double suma = 0.0;
           for (uint64_t r = 0; r < k; ++r) {
-            uint32_t i = order[r];
-            xs[r] = clamp_depth(depth[i]);
-            as[r] = orc_absorbance(alpha[(uint64_t)i * C + c]);
+            as[r] = orc_absorbance(alpha[(uint64_t)order[r] * C + c]);
             suma += as[r];
           }
           orc_coeffs_one((int)rank, (int)k, xs, as, cf);

@@ -11,11 +11,12 @@ WT_OK, WT_ERR_INVALID, WT_ERR_RANGE, WT_ERR_NOMEM, WT_ERR_HIP, WT_ERR_UNSUPPORTE
 STATUS_NAMES = {0: "WT_OK", -1: "WT_ERR_INVALID", -2: "WT_ERR_RANGE", -3: "WT_ERR_NOMEM", -4: "WT_ERR_HIP",
                 -5: "WT_ERR_UNSUPPORTED"}
 WT_F32, WT_F16, WT_BF16, WT_E5B9G9R9 = 0, 1, 2, 3
+WT_TIGHT_DEPTH = 1
 
 
 class FrameDesc(C.Structure):
     _fields_ = [("width", C.c_uint32), ("height", C.c_uint32), ("rank", C.c_uint32), ("channels", C.c_uint32),
-                ("coeff_dtype", C.c_uint32)]
+                ("coeff_dtype", C.c_uint32), ("flags", C.c_uint32)]
 
 
 class Fragments(C.Structure):
@@ -77,8 +78,8 @@ def check(status: int, where: str):
         raise WTError(status, where, load().wt_last_error().decode(errors="replace"))
 
 
-def desc(width, height, rank, channels=1, dtype=WT_F32) -> FrameDesc:
-    return FrameDesc(int(width), int(height), int(rank), int(channels), int(dtype))
+def desc(width, height, rank, channels=1, dtype=WT_F32, flags=0) -> FrameDesc:
+    return FrameDesc(int(width), int(height), int(rank), int(channels), int(dtype), int(flags))
 
 
 def bg3(bg):

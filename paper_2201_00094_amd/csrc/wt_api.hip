@@ -37,6 +37,7 @@ wt_status check_desc(const wt_frame_desc* d) {
     return fail(WT_ERR_INVALID, "E5B9G9R9 storage packs three channels (channels = %u)", d->channels);
   if (d->coeff_dtype == WT_E5B9G9R9 && d->rank > 4)
     return fail(WT_ERR_UNSUPPORTED, "E5B9G9R9 storage supports rank <= 4 (rank = %u)", d->rank);
+  if (d->flags & ~WT_TIGHT_DEPTH) return fail(WT_ERR_INVALID, "unknown flags 0x%x", d->flags);
   return WT_OK;
 }
 
@@ -75,7 +76,7 @@ wt_status check_lds(const wt::Geom& g) {
 
 extern "C" {
 
-int wt_abi_version(void) { return 1; }
+int wt_abi_version(void) { return 2; }
 
 const char* wt_last_error(void) { return g_last_error.c_str(); }
 

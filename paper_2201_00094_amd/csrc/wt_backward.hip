@@ -109,10 +109,11 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(Binned b, Geom g, cons
   float* lc = (float*)(ladj + per * TP);
   float* lg = lc + per * TP;
   float* lT = lg + 3 * TP;
+  uint32_t* lb = g.tight ? (uint32_t*)(lT + C * TP) : nullptr;  // per-pixel depth bounds
   const uint32_t t = b.order[blockIdx.x];
   const uint32_t x0 = (t % g.tilesX) * g.TW, y0 = (t / g.tilesX) * g.TH;
   for (uint32_t lp = threadIdx.x; lp < TP; lp += blockDim.x) {
-    const uint32_t px = x0 + (lp & (g.TW - 1)), py = y0 + lp / g.TW;
+    const uint32_t px = x0 + (lp & (g.TW - 1)), py = y0 + (lp >> g.lTW);
     const bool in = px < g.W && py < g.H;
     const uint64_t p = in ? (uint64_t)py * g.W + px : 0;
     for (uint32_t e = 0; e < per; ++e) {
@@ -138,11 +139,27 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(Binned b, Geom g, cons
     }
   __syncthreads();
   const uint32_t beg = b.offsets[t * g.NX], end = b.offsets[(t + 1) * g.NX];
+  if (lb) {
+    // depth bounds over the tile's valid fragments (section 2.1, step 1)
+    for (uint32_t lp = threadIdx.x; lp < TP; lp += blockDim.x) {
+      lb[lp] = __float_as_uint(1.f);
+      lb[TP + lp] = 0u;
+    }
+    __syncthreads();
+    for (uint32_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
+      BFrag<C> f;
+      if (!load_bfrag<C>(b, i, f)) continue;
+      const uint32_t xb = __float_as_uint(clamp01_b(f.x));
+      atomicMin(lb + f.lp, xb);
+      atomicMax(lb + TP + f.lp, xb);
+    }
+    __syncthreads();
+  }
   // pass 1: cell adjoints
   for (uint32_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
     BFrag<C> f;
     if (!load_bfrag<C>(b, i, f)) continue;
-    const float x = clamp01_b(f.x);
+    const float x = unit_depth(f.x, lb, TP, f.lp);
     const float u = x * (float)g.M;
     const uint32_t j = min((uint32_t)u, g.M - 1);
     const float tt = u - (float)j;
@@ -179,7 +196,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(Binned b, Geom g, cons
     BFrag<C> f;
     if (!load_bfrag<C>(b, i, f)) continue;
     const uint64_t src = f.src;
-    const float x = clamp01_b(f.x);
+    const float x = unit_depth(f.x, lb, TP, f.lp);
     const float u = x * (float)g.M;
     const uint32_t j = min((uint32_t)u, g.M - 1);
     const float tt = u - (float)j;
@@ -210,7 +227,9 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(Binned b, Geom g, cons
   }
 }
 
-size_t lds_backward_bytes(const Geom& g) { return (size_t)g.tile_px * (12 * g.C * g.M + 4 * (3 + g.C)); }
+size_t lds_backward_bytes(const Geom& g) {
+  return (size_t)g.tile_px * (12 * g.C * g.M + 4 * (3 + g.C) + (g.tight ? 8 : 0));
+}
 
 hipError_t launch_backward(const Geom& g, const Binned& b, const void* coeffs, const float* accum, const float* bg,
                            const float* grad_out, float* grad_alpha, float* grad_rgb, uint64_t count,

@@ -53,23 +53,28 @@ Geom make_geom(const wt_frame_desc& d, bool backward) {
   };
   uint32_t px;
   g.ep = 0;
+  g.tight = (d.flags & WT_TIGHT_DEPTH) ? 1 : 0;
+  const uint32_t bpx = g.tight ? 8 : 0;  // per-pixel depth bounds (two u32) in LDS
   if (backward) {
-    px = tile_for(12 * g.C * g.M + 4 * (3 + g.C));
+    px = tile_for(12 * g.C * g.M + 4 * (3 + g.C) + bpx);
   } else {
-    px = tile_for(8 * g.C * (g.M + 1) + 24);
+    px = tile_for(8 * g.C * (g.M + 1) + 24 + bpx);
     // packed three-channel storage is converted on the endpoint path only: cap the tile so that every
     // pixel/channel has a thread (rank <= 4 is checked by the API)
     if (d.coeff_dtype == WT_E5B9G9R9) px = std::min<uint32_t>(px, floor_pow2(kTileThreads / g.C));
     if (g.M <= 32 && px * g.C <= kTileThreads) {
       g.ep = 1;
     } else {
-      px = tile_for(8 * (g.C * g.M + g.AL));
+      px = tile_for(8 * (g.C * g.M + g.AL) + bpx);
     }
   }
   uint32_t e = 0;
   while ((1u << e) < px) ++e;
-  g.TW = 1u << ((e + 1) / 2);
-  g.TH = 1u << (e / 2);
+  g.lTW = (e + 1) / 2;
+  g.lTH = e / 2;
+  g.TW = 1u << g.lTW;
+  g.TH = 1u << g.lTH;
+  g.divW = make_fastdiv(g.W);
   g.tile_px = g.TW * g.TH;
   g.tilesX = (g.W + g.TW - 1) / g.TW;
   g.tilesY = (g.H + g.TH - 1) / g.TH;
@@ -458,11 +463,26 @@ __global__ __launch_bounds__(THREADS) void k_scatter_staged(wt_fragments f, Geom
   mine = wave_sum(mine);
   if ((threadIdx.x & 63) == 0 && mine) atomicAdd(&nvalid, mine);
   __syncthreads();
-  for (uint32_t t = threadIdx.x; t < g.ntiles; t += blockDim.x) {
+  // Reserve this chunk's run in every touched tile. The first kResv tiles of each thread keep their returned
+  // slots in registers until after the block scan, so the round trip of the atomics overlaps the scan.
+  constexpr uint32_t kResv = 4;
+  uint32_t resv[kResv];
+#pragma unroll
+  for (uint32_t j = 0; j < kResv; ++j) {
+    const uint32_t t = threadIdx.x + j * THREADS;
+    const uint32_t v = t < g.ntiles ? cnt[t] : 0u;
+    resv[j] = v ? atomicAdd(&cursors[cls * g.ntiles + t], v) : 0u;
+  }
+  for (uint32_t t = threadIdx.x + kResv * THREADS; t < g.ntiles; t += THREADS) {
     const uint32_t v = cnt[t];
     gb[t] = v ? atomicAdd(&cursors[cls * g.ntiles + t], v) : 0u;
   }
   block_scan_inplace<THREADS>(cnt, g.ntiles, wsum);
+#pragma unroll
+  for (uint32_t j = 0; j < kResv; ++j) {
+    const uint32_t t = threadIdx.x + j * THREADS;
+    if (t < g.ntiles) gb[t] = resv[j];
+  }
   __syncthreads();
   uint32_t sp[kPer];
 #pragma unroll

@@ -91,16 +91,28 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 
 // Tile of pixel p and its index inside the tile (row-major within the tile).
 __device__ __forceinline__ void tile_locate(const Geom& g, uint32_t p, uint32_t& tile, uint32_t& local) {
-  const uint32_t y = p / g.W;
+  const uint32_t y = fastdiv(p, g.divW);
   const uint32_t x = p - y * g.W;
-  tile = (y / g.TH) * g.tilesX + x / g.TW;
-  local = (y & (g.TH - 1)) * g.TW + (x & (g.TW - 1));
+  tile = (y >> g.lTH) * g.tilesX + (x >> g.lTW);
+  local = ((y & (g.TH - 1)) << g.lTW) + (x & (g.TW - 1));
 }
 
 __device__ __forceinline__ uint32_t tile_of(const Geom& g, uint32_t p) {
-  const uint32_t y = p / g.W;
+  const uint32_t y = fastdiv(p, g.divW);
   const uint32_t x = p - y * g.W;
-  return (y / g.TH) * g.tilesX + x / g.TW;
+  return (y >> g.lTH) * g.tilesX + (x >> g.lTW);
+}
+
+// Depth of a fragment as the method uses it: clamped to [0, 1], then, with per-pixel bounds (lb: lo bits [TP], hi
+// bits [TP] of tile-local pixels), mapped onto the pixel's own range, (x - lo) / (hi - lo), 0 when lo == hi
+// (section 2.1, step 1). The differences are of FP32 values and the quotient is correctly rounded, so x' <= 1.
+__device__ __forceinline__ float unit_depth(float x, const uint32_t* lb, uint32_t TP, uint32_t lp) {
+  x = fminf(fmaxf(x, 0.f), 1.f);
+  if (lb) {
+    const float lo = __uint_as_float(lb[lp]), hi = __uint_as_float(lb[TP + lp]);
+    x = hi > lo ? (x - lo) / (hi - lo) : 0.f;
+  }
+  return x;
 }
 
 // Absorbance step a = -ln(1 - alpha) of a (non-NaN) coverage value, with alpha clamped to [0, 1 - 2^-24].

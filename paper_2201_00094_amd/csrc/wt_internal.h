@@ -20,11 +20,40 @@ constexpr uint32_t kMaxTilePx = 2048;
 constexpr uint32_t kTileThreads = 1024;    // workgroup size of the per-tile kernels
 constexpr float kAlphaMax = 0.99999994f;   // 1 - 2^-24
 
+// Division of 32-bit values by a divisor fixed per frame, without a hardware divide (Granlund and Montgomery,
+// "Division by invariant integers using multiplication", 1994, the round-up form for unsigned 32-bit operands):
+// with l = ceil(log2 d) and m = floor(2^32 (2^l - d) / d) + 1, q = (t + ((n - t) >> min(l, 1))) >> max(l - 1, 0),
+// t = mulhi(m, n), equals floor(n / d) for every n < 2^32 and 1 <= d < 2^32.
+struct FastDiv {
+  uint32_t m, s1, s2;
+};
+
+inline FastDiv make_fastdiv(uint32_t d) {
+  uint32_t l = 0;
+  while (l < 32 && (1ull << l) < d) ++l;
+  FastDiv f;
+  f.m = (uint32_t)((((1ull << l) - d) << 32) / d + 1);
+  f.s1 = l < 1 ? l : 1;
+  f.s2 = l > 1 ? l - 1 : 0;
+  return f;
+}
+
+__host__ __device__ inline uint32_t fastdiv(uint32_t n, const FastDiv& f) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const uint32_t t = __umulhi(f.m, n);
+#else
+  const uint32_t t = (uint32_t)(((uint64_t)f.m * n) >> 32);
+#endif
+  return (t + ((n - t) >> f.s1)) >> f.s2;
+}
+
 // Frame geometry as the kernels see it.
 struct Geom {
   uint32_t W, H, P;      // frame
   uint32_t C, rank, M, L;// channels, rank, coefficients per channel (2^L), L = rank + 1
   uint32_t TW, TH;       // tile extent in pixels (powers of two)
+  uint32_t lTW, lTH;     // log2 of TW, TH
+  FastDiv divW;          // division by W
   uint32_t tilesX, tilesY, ntiles, tile_px;
   uint32_t NX;           // write-frontier classes (kClasses, or 1 when the tile count is large)
   uint32_t lds_bins;     // 1: LDS-staged scatter; 0: one global atomic per fragment
@@ -32,6 +61,7 @@ struct Geom {
   uint32_t AL;           // accumulation floats per pixel in LDS: 4 (C = 1) or 6 (C = 3)
   uint32_t dtype;        // wt_dtype of the coefficient storage
   uint32_t ep;           // 1: the build accumulates endpoint masses (M <= 32, one pixel/channel per thread)
+  uint32_t tight;        // 1: per-pixel depth bounds (WT_TIGHT_DEPTH); the tile kernels keep them in LDS
   uint32_t sthreads;     // scatter workgroup size (512 or 1024)
   uint32_t chunk;        // fragments per scatter workgroup = sthreads * kPer (also the class granularity)
 };

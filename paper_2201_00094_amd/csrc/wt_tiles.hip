@@ -43,7 +43,7 @@ __device__ __forceinline__ TileRef tile_ref(const Geom& g, const Binned& b, uint
 __device__ __forceinline__ bool tile_pixel(const Geom& g, const TileRef& r, uint32_t lp, uint64_t& p) {
   p = 0;
   const uint32_t px = r.x0 + (lp & (g.TW - 1));
-  const uint32_t py = r.y0 + lp / g.TW;
+  const uint32_t py = r.y0 + (lp >> g.lTW);
   if (px >= g.W || py >= g.H) return false;
   p = (uint64_t)py * g.W + px;
   return true;
@@ -84,6 +84,29 @@ __device__ __forceinline__ bool load_full(const Binned& b, uint32_t i, Frag<C>& 
   return load_head<C>(b, i, f);
 }
 
+// ------------------------------------------------------------------------------------------- depth bounds
+
+// Per-pixel depth bounds of the tile (section 2.1, step 1): lb[lp] = lo, lb[TP + lp] = hi as FP32 bits, over the
+// clamped depths of the tile's valid fragments (non-negative floats order like their bit patterns). Ends with a
+// barrier.
+template <int C>
+__device__ __forceinline__ void bounds_tile(const Binned& b, const Geom& g, const TileRef& r, uint32_t* lb) {
+  const uint32_t TP = g.tile_px;
+  for (uint32_t lp = threadIdx.x; lp < TP; lp += blockDim.x) {
+    lb[lp] = __float_as_uint(1.f);
+    lb[TP + lp] = 0u;
+  }
+  __syncthreads();
+  for (uint32_t i = r.beg + threadIdx.x; i < r.end; i += blockDim.x) {
+    Frag<C> f;
+    if (!load_head<C>(b, i, f)) continue;
+    const uint32_t xb = __float_as_uint(fminf(fmaxf(f.x, 0.f), 1.f));
+    atomicMin(lb + f.lp, xb);
+    atomicMax(lb + TP + f.lp, xb);
+  }
+  __syncthreads();
+}
+
 // ------------------------------------------------------------------------------------------- build
 
 // On-chip sums are FP64: on gfx950 an LDS FP64 atomic add sustains about nine times the rate of an FP32 one,
@@ -92,9 +115,9 @@ using acc_t = double;
 
 // The N + 2 coefficient updates of one fragment, per channel. lc is [C*M][TP] of acc_t.
 template <int C>
-__device__ __forceinline__ void build_add(acc_t* lc, const Geom& g, const Frag<C>& f) {
+__device__ __forceinline__ void build_add(acc_t* lc, const Geom& g, const Frag<C>& f, const uint32_t* lb) {
   const uint32_t TP = g.tile_px;
-  const float x = clamp01(f.x);
+  const float x = unit_depth(f.x, lb, TP, f.lp);
   float a[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) {
@@ -113,19 +136,20 @@ __device__ __forceinline__ void build_add(acc_t* lc, const Geom& g, const Frag<C
 }
 
 template <int C>
-__device__ __forceinline__ void build_tile(const Binned& b, const Geom& g, const TileRef& r, acc_t* lc) {
+__device__ __forceinline__ void build_tile(const Binned& b, const Geom& g, const TileRef& r, acc_t* lc,
+                                           const uint32_t* lb) {
   uint32_t i = r.beg + threadIdx.x;
   // two records per thread per step keep more loads in flight
   for (; i + blockDim.x < r.end; i += 2 * blockDim.x) {
     Frag<C> f0, f1;
     const bool ok0 = load_head<C>(b, i, f0);
     const bool ok1 = load_head<C>(b, i + blockDim.x, f1);
-    if (ok0) build_add<C>(lc, g, f0);
-    if (ok1) build_add<C>(lc, g, f1);
+    if (ok0) build_add<C>(lc, g, f0, lb);
+    if (ok1) build_add<C>(lc, g, f1, lb);
   }
   if (i < r.end) {
     Frag<C> f0;
-    if (load_head<C>(b, i, f0)) build_add<C>(lc, g, f0);
+    if (load_head<C>(b, i, f0)) build_add<C>(lc, g, f0, lb);
   }
 }
 
@@ -256,9 +280,9 @@ __device__ __forceinline__ void coeffs_to_cells(const Geom& g, const TileRef& r,
 // of N + 2, and the absorbance total comes for free.
 
 template <int C>
-__device__ __forceinline__ void build_ep_add(acc_t* le, const Geom& g, const Frag<C>& f) {
+__device__ __forceinline__ void build_ep_add(acc_t* le, const Geom& g, const Frag<C>& f, const uint32_t* lb) {
   const uint32_t TP = g.tile_px, M1 = g.M + 1;
-  const float x = clamp01(f.x);
+  const float x = unit_depth(f.x, lb, TP, f.lp);
   const float u = x * (float)g.M;
   const uint32_t j = min((uint32_t)u, g.M - 1);
   const float t = u - (float)j;
@@ -272,7 +296,8 @@ __device__ __forceinline__ void build_ep_add(acc_t* le, const Geom& g, const Fra
 }
 
 template <int C>
-__device__ __forceinline__ void build_ep_tile(const Binned& b, const Geom& g, const TileRef& r, acc_t* le) {
+__device__ __forceinline__ void build_ep_tile(const Binned& b, const Geom& g, const TileRef& r, acc_t* le,
+                                              const uint32_t* lb) {
   uint32_t i = r.beg + threadIdx.x;
   // four 12-byte head records per thread in flight per step
   for (; i + 3 * blockDim.x < r.end; i += 4 * blockDim.x) {
@@ -282,11 +307,11 @@ __device__ __forceinline__ void build_ep_tile(const Binned& b, const Geom& g, co
     for (int u = 0; u < 4; ++u) ok[u] = load_head<C>(b, i + u * blockDim.x, f[u]);
 #pragma unroll
     for (int u = 0; u < 4; ++u)
-      if (ok[u]) build_ep_add<C>(le, g, f[u]);
+      if (ok[u]) build_ep_add<C>(le, g, f[u], lb);
   }
   for (; i < r.end; i += blockDim.x) {
     Frag<C> f0;
-    if (load_head<C>(b, i, f0)) build_ep_add<C>(le, g, f0);
+    if (load_head<C>(b, i, f0)) build_ep_add<C>(le, g, f0, lb);
   }
 }
 
@@ -519,9 +544,10 @@ __device__ __forceinline__ void ep_build_store(const Geom& g, const TileRef& r, 
 // la is [AL][TP] of acc_t: rows 0..2 colour, then sum a (C = 1) or sum a_r, a_g, a_b (C = 3).
 // lc holds FP32 cells (CELLS) or coefficients of type T (otherwise), [C*M][TP].
 template <int C, bool CELLS, typename T, bool SUMA = true>
-__device__ __forceinline__ void eval_add(const T* lc, acc_t* la, const Geom& g, const Frag<C>& f) {
+__device__ __forceinline__ void eval_add(const T* lc, acc_t* la, const Geom& g, const Frag<C>& f,
+                                         const uint32_t* lb) {
   const uint32_t TP = g.tile_px;
-  const float x = clamp01(f.x);
+  const float x = unit_depth(f.x, lb, TP, f.lp);
   const float u = x * (float)g.M;
   const uint32_t j = min((uint32_t)u, g.M - 1);
   const float t = u - (float)j;
@@ -554,18 +580,18 @@ __device__ __forceinline__ void eval_add(const T* lc, acc_t* la, const Geom& g, 
 
 template <int C, bool CELLS, typename T, bool SUMA = true>
 __device__ __forceinline__ void eval_tile(const Binned& b, const Geom& g, const TileRef& r, const T* lc,
-                                          acc_t* la) {
+                                          acc_t* la, const uint32_t* lb) {
   uint32_t i = r.beg + threadIdx.x;
   for (; i + blockDim.x < r.end; i += 2 * blockDim.x) {
     Frag<C> f0, f1;
     const bool ok0 = load_full<C>(b, i, f0);
     const bool ok1 = load_full<C>(b, i + blockDim.x, f1);
-    if (ok0) eval_add<C, CELLS, T, SUMA>(lc, la, g, f0);
-    if (ok1) eval_add<C, CELLS, T, SUMA>(lc, la, g, f1);
+    if (ok0) eval_add<C, CELLS, T, SUMA>(lc, la, g, f0, lb);
+    if (ok1) eval_add<C, CELLS, T, SUMA>(lc, la, g, f1, lb);
   }
   if (i < r.end) {
     Frag<C> f0;
-    if (load_full<C>(b, i, f0)) eval_add<C, CELLS, T, SUMA>(lc, la, g, f0);
+    if (load_full<C>(b, i, f0)) eval_add<C, CELLS, T, SUMA>(lc, la, g, f0, lb);
   }
 }
 
@@ -612,10 +638,13 @@ __global__ __launch_bounds__(kTileThreads) void k_build(Binned b, Geom g, TS* __
   extern __shared__ acc_t smem_d[];
   acc_t* lc = smem_d;
   const TileRef r = tile_ref(g, b, b.order[blockIdx.x]);
+  // per-pixel depth bounds after the coefficient region
+  uint32_t* lb = g.tight ? (uint32_t*)(smem_d + (g.ep ? C * (g.M + 1) : C * g.M) * g.tile_px) : nullptr;
+  if (lb) bounds_tile<C>(b, g, r, lb);
   if (g.ep) {
     for (uint32_t e = threadIdx.x; e < C * (g.M + 1) * g.tile_px; e += blockDim.x) lc[e] = 0.0;
     __syncthreads();
-    build_ep_tile<C>(b, g, r, lc);
+    build_ep_tile<C>(b, g, r, lc, lb);
     __syncthreads();
     if constexpr (is_e5<TS>::value)
       with_m(g, [&](auto mm) { e5_build_store<decltype(mm)::value>(g, r, lc, (uint32_t*)coeffs); });
@@ -625,7 +654,7 @@ __global__ __launch_bounds__(kTileThreads) void k_build(Binned b, Geom g, TS* __
   }
   coeff_tile_io<C, TS, 0>(g, r, lc, coeffs);
   __syncthreads();
-  build_tile<C>(b, g, r, lc);
+  build_tile<C>(b, g, r, lc, lb);
   __syncthreads();
   coeff_tile_io<C, TS, 1>(g, r, lc, coeffs);
 }
@@ -637,7 +666,9 @@ __global__ __launch_bounds__(kTileThreads) void k_evaluate(Binned b, Geom g, con
   const uint32_t TP = g.tile_px;
   acc_t* la = smem_d;                              // [AL][TP] FP64
   float* lc = (float*)(smem_d + g.AL * TP);        // [C*M][TP] FP32
+  uint32_t* lb = g.tight ? (uint32_t*)(lc + C * g.M * TP) : nullptr;  // per-pixel depth bounds
   const TileRef r = tile_ref(g, b, b.order[blockIdx.x]);
+  if (lb) bounds_tile<C>(b, g, r, lb);
   coeff_tile_io<C, TS, 0>(g, r, lc, const_cast<TS*>(coeffs));
   for (uint32_t lp = threadIdx.x; lp < TP; lp += blockDim.x) {
     uint64_t p;
@@ -649,7 +680,7 @@ __global__ __launch_bounds__(kTileThreads) void k_evaluate(Binned b, Geom g, con
   __syncthreads();
   if (CELLS) synth_tile_f32<C>(lc, g);
   __syncthreads();
-  eval_tile<C, CELLS, float>(b, g, r, lc, la);
+  eval_tile<C, CELLS, float>(b, g, r, lc, la, lb);
   __syncthreads();
   for (uint32_t lp = threadIdx.x; lp < TP; lp += blockDim.x) {
     uint64_t p;
@@ -671,9 +702,11 @@ __global__ __launch_bounds__(kTileThreads) void k_render(Binned b, Geom g, TS* _
     // place), colour sums [3][TP] FP64
     acc_t* le = smem_d;
     acc_t* la = smem_d + C * (g.M + 1) * TP;
+    uint32_t* lb = g.tight ? (uint32_t*)(la + 3 * TP) : nullptr;  // per-pixel depth bounds
+    if (lb) bounds_tile<C>(b, g, r, lb);
     for (uint32_t e = threadIdx.x; e < (C * (g.M + 1) + 3) * TP; e += blockDim.x) smem_d[e] = 0.0;
     __syncthreads();
-    build_ep_tile<C>(b, g, r, le);
+    build_ep_tile<C>(b, g, r, le, lb);
     __syncthreads();
     if constexpr (is_e5<TS>::value)
       with_m(g, [&](auto mm) { e5_render_convert<decltype(mm)::value>(g, r, le, (uint32_t*)coeffs); });
@@ -681,7 +714,7 @@ __global__ __launch_bounds__(kTileThreads) void k_render(Binned b, Geom g, TS* _
       ep_render_convert<C, TS>(g, r, le, coeffs);
     __syncthreads();
     const float* cells = (const float*)le;
-    eval_tile<C, true, float, false>(b, g, r, cells, la);
+    eval_tile<C, true, float, false>(b, g, r, cells, la, lb);
     __syncthreads();
     const float* sa = cells + C * g.M * TP;
     for (uint32_t lp = threadIdx.x; lp < TP; lp += blockDim.x) {
@@ -695,19 +728,21 @@ __global__ __launch_bounds__(kTileThreads) void k_render(Binned b, Geom g, TS* _
   }
   acc_t* lc = smem_d;                    // [C*M][TP] FP64, then FP32 cells in its first half (CELLS)
   acc_t* la = smem_d + C * g.M * TP;     // [AL][TP] FP64
+  uint32_t* lb = g.tight ? (uint32_t*)(la + g.AL * TP) : nullptr;  // per-pixel depth bounds
+  if (lb) bounds_tile<C>(b, g, r, lb);
   for (uint32_t e = threadIdx.x; e < (C * g.M + g.AL) * TP; e += blockDim.x) smem_d[e] = 0.0;
   __syncthreads();
-  build_tile<C>(b, g, r, lc);
+  build_tile<C>(b, g, r, lc, lb);
   __syncthreads();
   // coefficients at storage precision: stored (optionally) and used for the evaluation
   if (CELLS) {
     coeffs_to_cells<C, TS>(g, r, lc, coeffs);
     __syncthreads();
-    eval_tile<C, true, float>(b, g, r, (const float*)lc, la);
+    eval_tile<C, true, float>(b, g, r, (const float*)lc, la, lb);
   } else {
     coeff_tile_io<C, TS, 2>(g, r, lc, coeffs);
     __syncthreads();
-    eval_tile<C, false, acc_t>(b, g, r, lc, la);
+    eval_tile<C, false, acc_t>(b, g, r, lc, la, lb);
   }
   __syncthreads();
   for (uint32_t lp = threadIdx.x; lp < TP; lp += blockDim.x) {
@@ -739,11 +774,14 @@ __global__ __launch_bounds__(256) void k_resolve(const float* __restrict__ accum
 // LDS of the render (with_accum) and build kernels: endpoint masses (+ three colour sums), or coefficient
 // sums (+ AL accumulations).
 size_t lds_tile_bytes(const Geom& g, bool with_accum) {
-  if (g.ep) return (size_t)g.tile_px * (g.C * (g.M + 1) + (with_accum ? 3 : 0)) * sizeof(acc_t);
-  return (size_t)g.tile_px * (g.C * g.M + (with_accum ? g.AL : 0)) * sizeof(acc_t);
+  const size_t bounds = g.tight ? 8ull * g.tile_px : 0;
+  if (g.ep) return (size_t)g.tile_px * (g.C * (g.M + 1) + (with_accum ? 3 : 0)) * sizeof(acc_t) + bounds;
+  return (size_t)g.tile_px * (g.C * g.M + (with_accum ? g.AL : 0)) * sizeof(acc_t) + bounds;
 }
 
-static size_t lds_eval_bytes(const Geom& g) { return (size_t)g.tile_px * (4 * g.C * g.M + 8 * g.AL); }
+static size_t lds_eval_bytes(const Geom& g) {
+  return (size_t)g.tile_px * (4 * g.C * g.M + 8 * g.AL + (g.tight ? 8 : 0));
+}
 
 // The render kernel expands cells in registers, one pixel/channel per thread.
 static bool render_cells(const Geom& g) { return g.M <= 32 && g.tile_px * g.C <= (uint32_t)kTileThreads; }

@@ -25,6 +25,7 @@ class FrameSpec:
     rank: int
     channels: int = 1
     dtype: str = "f32"
+    tight: bool = False   # per-pixel depth bounds (WT_TIGHT_DEPTH): pass each frame's stream whole
 
     @property
     def pixels(self) -> int:
@@ -41,7 +42,8 @@ class FrameSpec:
     def c_desc(self) -> _lib.FrameDesc:
         if self.dtype not in DTYPES:
             raise ValueError("unknown coefficient storage %r" % self.dtype)
-        return _lib.desc(self.width, self.height, self.rank, self.channels, DTYPES[self.dtype])
+        return _lib.desc(self.width, self.height, self.rank, self.channels, DTYPES[self.dtype],
+                         _lib.WT_TIGHT_DEPTH if self.tight else 0)
 
     def coeff_shape(self):
         if self.dtype == "e5b9g9r9":

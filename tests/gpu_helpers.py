@@ -15,15 +15,15 @@ def device_frags(f, device="cuda"):
     return wt.Fragments.from_numpy(f.pixel, f.depth, f.alpha, f.rgb, device=device)
 
 
-def spec_of(f, dtype="f32", rank=None):
+def spec_of(f, dtype="f32", rank=None, tight=False):
     import paper_2201_00094_amd as wt
-    return wt.FrameSpec(f.width, f.height, f.rank if rank is None else rank, f.channels, dtype)
+    return wt.FrameSpec(f.width, f.height, f.rank if rank is None else rank, f.channels, dtype, tight)
 
 
-def gpu_render(f, dtype="f32", rank=None, want_coeffs=True):
+def gpu_render(f, dtype="f32", rank=None, want_coeffs=True, tight=False):
     import torch
     import paper_2201_00094_amd as wt
-    spec = spec_of(f, dtype, rank)
+    spec = spec_of(f, dtype, rank, tight)
     fr = device_frags(f)
     ws = wt.Workspace(spec, f.count)
     coeffs = spec.new_coeffs() if want_coeffs else None
@@ -53,11 +53,11 @@ def e5_decode(orc, words):
     return out
 
 
-def gpu_passes(f, dtype="f32", rank=None, chunks=1):
+def gpu_passes(f, dtype="f32", rank=None, chunks=1, tight=False):
     """Separate build / evaluate / resolve calls, each taking the raw stream (optionally in chunks)."""
     import torch
     import paper_2201_00094_amd as wt
-    spec = spec_of(f, dtype, rank)
+    spec = spec_of(f, dtype, rank, tight)
     coeffs = spec.new_coeffs()
     accum = spec.new_accum()
     bounds = np.linspace(0, f.count, chunks + 1).astype(np.int64)
@@ -74,9 +74,9 @@ def gpu_passes(f, dtype="f32", rank=None, chunks=1):
     return res
 
 
-def oracle_frame(orc, f, rank=None, storage="exact", mask=None, want=("coeffs", "accum", "suma", "out")):
+def oracle_frame(orc, f, rank=None, storage="exact", mask=None, want=("coeffs", "accum", "suma", "out"), tight=False):
     return orc.resolve(f.width, f.height, f.rank if rank is None else rank, f.pixel, f.depth, f.alpha, f.rgb,
-                       bg=f.bg, channels=f.channels, mask=mask, want=want, storage=storage)
+                       bg=f.bg, channels=f.channels, mask=mask, want=want, storage=storage, tight=tight)
 
 
 def assert_coeffs(g, o, rel=1e-5, sel=None, what="coeffs"):

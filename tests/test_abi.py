@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_abi_version(lib):
-    assert lib.wt_abi_version() == 1
+    assert lib.wt_abi_version() == 2
 
 
 def test_workspace_bytes(lib):
@@ -79,6 +79,9 @@ def test_validation_errors_before_any_launch(lib):
     assert lib.wt_bin(C.byref(_lib.desc(8, 8, 3, 1, e5)), C.byref(ok), ws, 1 << 30, None) == _lib.WT_ERR_INVALID
     assert lib.wt_bin(C.byref(_lib.desc(8, 8, 5, 3, e5)), C.byref(ok), ws, 1 << 30, None) == _lib.WT_ERR_UNSUPPORTED
     assert lib.wt_workspace_bytes(C.byref(_lib.desc(8, 8, 4, 3, e5)), 10) > 0
+    # flags: only WT_TIGHT_DEPTH is defined
+    assert lib.wt_bin(C.byref(_lib.desc(8, 8, 3, 1, 0, 2)), C.byref(ok), ws, 1 << 30, None) == _lib.WT_ERR_INVALID
+    assert lib.wt_workspace_bytes(C.byref(_lib.desc(8, 8, 3, 1, 0, _lib.WT_TIGHT_DEPTH)), 10) > 0
     bg = _lib.bg3((0, 0, 0))
     assert lib.wt_resolve(C.byref(d), None, bg, ws, None) == _lib.WT_ERR_INVALID
     assert lib.wt_render(C.byref(d), C.byref(ok), None, None, ws, ws, 1 << 30, None) == _lib.WT_ERR_INVALID

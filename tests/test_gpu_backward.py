@@ -16,10 +16,10 @@ def _gpu():
         pytest.skip("no GPU")
 
 
-def _gpu_grads(f, rank, target, dtype="f32"):
+def _gpu_grads(f, rank, target, dtype="f32", tight=False):
     import torch
     import paper_2201_00094_amd as wt
-    spec = wt.FrameSpec(f.width, f.height, rank, f.channels, dtype)
+    spec = wt.FrameSpec(f.width, f.height, rank, f.channels, dtype, tight)
     fr = wt.Fragments.from_numpy(f.pixel, f.depth, f.alpha, f.rgb)
     alpha = fr.alpha.clone().requires_grad_(True)
     rgb = fr.rgb.clone().requires_grad_(True)
@@ -32,20 +32,21 @@ def _gpu_grads(f, rank, target, dtype="f32"):
             rgb.grad.cpu().double().numpy())
 
 
-@pytest.mark.parametrize("channels,rank", [(1, 3), (1, 4), (1, 6), (3, 3)])
-def test_backward_matches_oracle_gradient(orc, channels, rank):
+@pytest.mark.parametrize("channels,rank,tight", [(1, 3, False), (1, 4, False), (1, 6, False), (3, 3, False),
+                                                (1, 3, True), (3, 4, True)])
+def test_backward_matches_oracle_gradient(orc, channels, rank, tight):
     if channels == 1:
         f = synth.frame_c5(seed=rank, width=45, height=38, rank=rank, mean=12.0)
     else:
         f = synth.frame_c3(seed=rank, width=45, height=38, rank=rank, particles=8.0)
-    say("case backward channels", channels, "rank", rank, "F", f.count)
+    say("case backward channels", channels, "rank", rank, "tight", tight, "F", f.count)
     target = synth.target_image(rank, f.width, f.height)
-    out, ga, gr = _gpu_grads(f, rank, target)
+    out, ga, gr = _gpu_grads(f, rank, target, tight=tight)
     o = orc.resolve(f.width, f.height, rank, f.pixel, f.depth, f.alpha, f.rgb, bg=f.bg, channels=channels,
-                    want=("out",))
+                    want=("out",), tight=tight)
     np.testing.assert_allclose(out, o["out"], atol=1e-4, rtol=0)
     oa, orgb = orc.backward(f.width, f.height, rank, f.pixel, f.depth, f.alpha, f.rgb, 2.0 * (out - target), bg=f.bg,
-                            channels=channels)
+                            channels=channels, tight=tight)
     sa, sr = np.abs(oa).max(), np.abs(orgb).max()
     np.testing.assert_allclose(ga, oa, rtol=1e-4, atol=2e-6 * sa)
     np.testing.assert_allclose(gr, orgb, rtol=1e-5, atol=1e-7 * sr)

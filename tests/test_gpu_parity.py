@@ -138,6 +138,49 @@ def f32_M(rank):
     return 1 << (rank + 1)
 
 
+@pytest.mark.parametrize("channels,rank", [(1, 0), (1, 3), (1, 4), (1, 6), (3, 3)])
+def test_tight_depth_bounds(orc, channels, rank):
+    """Per-pixel depth bounds (section 2.1, step 1) against the oracle with the same bounds: fused render and the
+    separate passes, on a ragged frame; the plain and tight results differ."""
+    f = (synth.frame_c1(seed=50 + rank, width=53, height=38, rank=rank, mean=9.0) if channels == 1 else
+         synth.frame_c3(seed=50 + rank, width=53, height=38, rank=rank, particles=6.0))
+    say("case tight depth channels", channels, "rank", rank)
+    g = gpu_render(f, tight=True)
+    o = oracle_frame(orc, f, tight=True)
+    assert_coeffs(g["coeffs"], o["coeffs"])
+    assert_close_abs(g["out"], o["out"], 1e-4)
+    p = gpu_passes(f, tight=True)
+    assert_coeffs(p["coeffs"], o["coeffs"])
+    S, sa = accum_to_oracle_layout(p["accum"], channels)
+    np.testing.assert_allclose(S, o["accum"], rtol=2e-5, atol=1e-7)
+    assert_close_abs(p["out"], o["out"], 1e-4)
+    plain = oracle_frame(orc, f, want=("out",))
+    assert np.abs(plain["out"] - o["out"]).max() > 1e-3
+
+
+def test_tight_depth_smoke_1080p_sampled(orc):
+    """The smoke frame (depths concentrated around 0.5) with per-pixel bounds, on sampled pixels."""
+    import torch
+    import paper_2201_00094_amd as wt
+    f = synth.frame_c2(seed=3, rank=3)
+    say("case tight smoke 1080p F", f.count)
+    spec = spec_of(f, tight=True)
+    fr = wt.Fragments.from_numpy(f.pixel, f.depth, f.alpha, f.rgb)
+    ws = wt.Workspace(spec, f.count)
+    coeffs = spec.new_coeffs()
+    out = wt.render(spec, fr, f.bg, ws, coeffs=coeffs)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(3)
+    sel = np.unique(rng.choice(f.pixels, 1500, replace=False))
+    mask = np.zeros(f.pixels, bool)
+    mask[sel] = True
+    o = oracle_frame(orc, f, mask=mask, want=("coeffs", "out"), tight=True)
+    assert_coeffs(coeffs.cpu().double().numpy(), o["coeffs"], sel=sel)
+    assert_close_abs(out.cpu().double().numpy(), o["out"], 1e-4, sel=sel)
+    del fr, ws, coeffs, out
+    torch.cuda.empty_cache()
+
+
 def test_order_independence_and_chunks(orc):
     """Permuted and chunked streams give the same result within the parity tolerance (P6, P10)."""
     f = synth.frame_c1(seed=11, width=90, height=70, mean=20.0)

@@ -425,7 +425,7 @@ def test_abuffer_sorted_equals_brute_force(orc):
 
 # ---------------------------------------------------------------------------------------------- P14 (oracle side)
 @pytest.mark.parametrize("channels", [1, 3])
-def test_p14_backward_matches_finite_differences(orc, channels):
+def test_p14_backward_matches_finite_differences(orc, channels, tight=False):
     rng = np.random.default_rng(31 + channels)
     W, H, rank = 6, 5, 3
     f = synth.frame_c5(seed=channels, width=W, height=H, rank=rank, mean=9)
@@ -435,11 +435,14 @@ def test_p14_backward_matches_finite_differences(orc, channels):
     bg = (0.2, 0.5, 0.8)
 
     def loss(al, rgb):
-        out = orc.resolve(W, H, rank, f.pixel, f.depth, al, rgb, bg=bg, channels=channels, want=("out",))["out"]
+        out = orc.resolve(W, H, rank, f.pixel, f.depth, al, rgb, bg=bg, channels=channels, want=("out",),
+                          tight=tight)["out"]
         return ((out - target) ** 2).sum()
 
-    out = orc.resolve(W, H, rank, f.pixel, f.depth, alpha, f.rgb, bg=bg, channels=channels, want=("out",))["out"]
-    ga, gr = orc.backward(W, H, rank, f.pixel, f.depth, alpha, f.rgb, 2.0 * (out - target), bg=bg, channels=channels)
+    out = orc.resolve(W, H, rank, f.pixel, f.depth, alpha, f.rgb, bg=bg, channels=channels, want=("out",),
+                      tight=tight)["out"]
+    ga, gr = orc.backward(W, H, rank, f.pixel, f.depth, alpha, f.rgb, 2.0 * (out - target), bg=bg, channels=channels,
+                          tight=tight)
     # FD in FP64 needs FP64 inputs: perturb through float64 copies by evaluating the oracle's steps on the
     # perturbed value directly (the FP32 stream is promoted exactly, so a float32 perturbation would round).
     eps = 1e-3
@@ -462,6 +465,85 @@ def test_p14_backward_matches_finite_differences(orc, channels):
             rm[i, q] -= eps
             fd = (loss(alpha, rp) - loss(alpha, rm)) / (float(rp[i, q]) - float(rm[i, q]))
             assert gr[i, q] == pytest.approx(fd, rel=1e-6, abs=1e-9)
+
+
+def test_p14_backward_with_tight_depth_bounds(orc):
+    test_p14_backward_matches_finite_differences(orc, 1, tight=True)
+
+
+# ---------------------------------------------------------------------------------------------- tight depth bounds
+def _two_depth_frame(rng, W, H, channels=1):
+    """Every pixel holds 1-5 fragments at exactly two distinct depths (ties included)."""
+    pix, dep = [], []
+    for p in range(W * H):
+        z = np.sort(rng.choice(np.arange(1, 255), 2, replace=False) / 256.0)
+        k = rng.integers(2, 6)
+        d = np.concatenate([z, rng.choice(z, k - 2)])
+        pix += [p] * k
+        dep += list(d)
+    F = len(pix)
+    alpha = rng.uniform(0.05, 0.8, (F, channels) if channels == 3 else F).astype(np.float32)
+    return (np.array(pix, np.uint32), np.array(dep, np.float32), alpha, rng.random((F, 3), dtype=np.float32))
+
+
+@pytest.mark.parametrize("channels", [1, 3])
+def test_tight_depth_two_layers_are_exact(orc, channels):
+    """With per-pixel bounds two distinct depths land on 0 and 1: the near group sees v = 1 (the knot at 0) and the
+    far group sees the full near absorbance (the last cell average), which is exactly the sorted A-buffer."""
+    rng = np.random.default_rng(40 + channels)
+    W, H = 7, 5
+    pix, dep, al, rgb = _two_depth_frame(rng, W, H, channels)
+    t = orc.resolve(W, H, 3, pix, dep, al, rgb, bg=(0.3, 0.2, 0.1), channels=channels, want=("out", "vis"), tight=True)
+    a = orc.abuffer(W, H, pix, dep, al, rgb, bg=(0.3, 0.2, 0.1), channels=channels, want_vis=True)
+    np.testing.assert_allclose(t["vis"], a["vis"], rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(t["out"], a["out"], rtol=1e-12, atol=1e-15)
+    plain = orc.resolve(W, H, 3, pix, dep, al, rgb, bg=(0.3, 0.2, 0.1), channels=channels, want=("out",))
+    assert np.abs(plain["out"] - a["out"]).max() > 1e-4  # off-grid depths are approximated without the bounds
+
+
+def test_tight_depth_affine_invariance(orc):
+    """The tight result depends on depth only through each pixel's relative position: x -> 1/8 + x/2 (exact on a
+    dyadic grid) leaves every output bit-identical, while the plain result changes."""
+    rng = np.random.default_rng(44)
+    f = synth.frame_c1(seed=44, width=9, height=8, mean=7.0)
+    dep = (np.floor(f.depth * 256.0) / 256.0).astype(np.float32)
+    dep2 = (0.125 + dep / 2.0).astype(np.float32)
+    a = orc.resolve(9, 8, 3, f.pixel, dep, f.alpha, f.rgb, bg=f.bg, want=("coeffs", "out"), tight=True)
+    b = orc.resolve(9, 8, 3, f.pixel, dep2, f.alpha, f.rgb, bg=f.bg, want=("coeffs", "out"), tight=True)
+    np.testing.assert_array_equal(a["coeffs"], b["coeffs"])
+    np.testing.assert_array_equal(a["out"], b["out"])
+    pa = orc.resolve(9, 8, 3, f.pixel, dep, f.alpha, f.rgb, bg=f.bg, want=("out",))
+    pb = orc.resolve(9, 8, 3, f.pixel, dep2, f.alpha, f.rgb, bg=f.bg, want=("out",))
+    assert np.abs(pa["out"] - pb["out"]).max() > 1e-4
+    del rng
+
+
+def test_tight_depth_full_range_is_plain(orc):
+    """A pixel whose fragments already span [0, 1] is unchanged by the bounds (x' = x), bit for bit."""
+    f = synth.frame_c1(seed=45, width=6, height=6, mean=5.0)
+    P = f.pixels
+    pix = np.concatenate([f.pixel, np.arange(P, dtype=np.uint32), np.arange(P, dtype=np.uint32)])
+    dep = np.concatenate([f.depth, np.zeros(P, np.float32), np.ones(P, np.float32)])
+    al = np.concatenate([f.alpha, np.full(P, 0.3, np.float32), np.full(P, 0.4, np.float32)])
+    rgb = np.concatenate([f.rgb, np.full((P, 3), 0.5, np.float32), np.full((P, 3), 0.25, np.float32)])
+    a = orc.resolve(6, 6, 3, pix, dep, al, rgb, bg=f.bg, want=("coeffs", "out"), tight=True)
+    b = orc.resolve(6, 6, 3, pix, dep, al, rgb, bg=f.bg, want=("coeffs", "out"))
+    np.testing.assert_array_equal(a["coeffs"], b["coeffs"])
+    np.testing.assert_array_equal(a["out"], b["out"])
+
+
+def test_tight_depth_single_fragment(orc):
+    """One fragment per pixel maps to depth 0: nothing is in front of it, out = alpha c + bg (1 - alpha)."""
+    rng = np.random.default_rng(46)
+    P = 20
+    pix = np.arange(P, dtype=np.uint32)
+    dep = rng.uniform(0.1, 0.9, P).astype(np.float32)
+    al = rng.uniform(0.1, 0.9, P).astype(np.float32)
+    rgb = rng.random((P, 3), dtype=np.float32)
+    bg = (0.3, 0.6, 0.9)
+    t = orc.resolve(5, 4, 3, pix, dep, al, rgb, bg=bg, want=("out",), tight=True)
+    ref = al[:, None].astype(np.float64) * rgb + np.array(bg)[None, :] * (1.0 - al[:, None].astype(np.float64))
+    np.testing.assert_allclose(t["out"], ref, rtol=1e-12, atol=1e-15)
 
 
 # ---------------------------------------------------------------------------------------------- generators
