@@ -116,8 +116,9 @@ def main():
     ap.add_argument("--pmc", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="traffic mode: rocprofv3 output folders of the frame and copy runs")
     ap.add_argument("--pmc-command", default="", help="traffic mode: the command the counters were taken with")
-    ap.add_argument("--requests", type=int, default=200, help="serve mode: requests in the trace")
-    ap.add_argument("--load", type=float, default=0.8, help="serve mode: arrival rate as a share of solo capacity")
+    ap.add_argument("--requests", type=int, default=500, help="serve mode: requests per trace")
+    ap.add_argument("--load", default="0.5,0.8,0.95",
+                    help="serve mode: arrival rates as shares of the solo capacity (comma-separated sweep)")
     ap.add_argument("--budget-gb", type=float, default=32.0, help="serve mode: HBM admission budget")
     ap.add_argument("--slots", type=int, default=4, help="serve mode: concurrent requests (HIP streams)")
     args = ap.parse_args()
@@ -373,7 +374,9 @@ def run_traffic(args):
 def run_serve(args):
     """Poisson arrivals of frames whose size is drawn from 640x360 .. 3840x2160, rank from {3, 4} and storage from
     {f32, f16}, 24 fragments/px; admitted by HBM footprint into a fixed number of slots; p50/p99 latency from
-    arrival to completion and whole-trace fragments/s. A sample of requests is re-rendered alone and compared."""
+    arrival to completion, arrival-to-admission waits and whole-trace fragments/s, for a sweep of arrival rates
+    (shares of the solo capacity). Every request is re-rendered alone afterwards and compared with its served
+    result."""
     import torch
 
     import paper_2201_00094_amd as wt
@@ -408,37 +411,53 @@ def run_serve(args):
                 del ws
     torch.cuda.empty_cache()
     mean_service = float(np.mean(list(solo.values())))
-    rate = args.load / mean_service
-    trace = synth.poisson_arrivals(args.seed, args.requests, rate)
-    ex = GpuExecutor(slots=args.slots, device=dev)
-    srv = Server(ex, slots=args.slots, budget_bytes=int(args.budget_gb * (1 << 30)))
-    futs = []
-    t0 = time.perf_counter()
-    for i, r in enumerate(trace):
-        now = time.perf_counter() - t0
-        if r["t"] > now:
-            time.sleep(r["t"] - now)
-        fr = pool[(r["width"], r["height"], r["seed"] % 2)]
-        futs.append(srv.submit(FrameRequest(r["width"], r["height"], r["rank"], fr, dtype=r["dtype"],
-                                            bg=(0.2, 0.2, 0.2), tag=i)))
-    results = [f.result(timeout=600) for f in futs]
-    srv.close()
-    stats = srv.stats.summary()
-    # solo vs mix on a sample
-    worst = 0.0
-    for i in np.random.default_rng(args.seed).choice(len(trace), min(16, len(trace)), replace=False):
-        r = trace[i]
-        fr = pool[(r["width"], r["height"], r["seed"] % 2)]
-        spec = wt.FrameSpec(r["width"], r["height"], r["rank"], 1, r["dtype"])
-        alone = wt.render(spec, fr, (0.2, 0.2, 0.2), wt.Workspace(spec, fr.count, device=dev))
-        torch.cuda.synchronize()
-        worst = max(worst, float((alone - results[i].out).abs().max()))
+    sweep = []
+    for k, load in enumerate(float(v) for v in str(args.load).split(",")):
+        rate = load / mean_service
+        trace = synth.poisson_arrivals(args.seed + k, args.requests, rate)
+        ex = GpuExecutor(slots=args.slots, device=dev)
+        srv = Server(ex, slots=args.slots, budget_bytes=int(args.budget_gb * (1 << 30)))
+        futs = []
+        t0 = time.perf_counter()
+        for i, r in enumerate(trace):
+            now = time.perf_counter() - t0
+            if r["t"] > now:
+                time.sleep(r["t"] - now)
+            fr = pool[(r["width"], r["height"], r["seed"] % 2)]
+            futs.append(srv.submit(FrameRequest(r["width"], r["height"], r["rank"], fr, dtype=r["dtype"],
+                                                bg=(0.2, 0.2, 0.2), tag=i)))
+        results = [fu.result(timeout=600) for fu in futs]
+        srv.close()
+        stats = srv.stats.summary()
+        # every request against the same frame rendered alone
+        worst = 0.0
+        alone_ws = {}
+        for i, r in enumerate(trace):
+            fr = pool[(r["width"], r["height"], r["seed"] % 2)]
+            spec = wt.FrameSpec(r["width"], r["height"], r["rank"], 1, r["dtype"])
+            key = (r["width"], r["height"], r["rank"], r["dtype"])
+            if key not in alone_ws:
+                most = max(q.count for kk, q in pool.items() if kk[:2] == (r["width"], r["height"]))
+                alone_ws[key] = wt.Workspace(spec, most, device=dev)
+            alone = wt.render(spec, fr, (0.2, 0.2, 0.2), alone_ws[key])
+            worst = max(worst, float((alone - results[i].out).abs().max()))
+        del alone_ws, results, ex
+        torch.cuda.empty_cache()
+        sweep.append({"load": load, "rate_hz": rate, "requests": len(trace), "fragments_per_s": stats["fragments_per_s"],
+                      "p50_ms": stats["p50_ms"], "p99_ms": stats["p99_ms"], "mean_ms": stats["mean_ms"],
+                      "queued": stats["queued"], "wait_p50_ms": stats["wait_p50_ms"],
+                      "wait_p99_ms": stats["wait_p99_ms"], "admitted": stats["completed"],
+                      "rejected": stats["rejected"], "max_inflight": stats["max_inflight"],
+                      "max_gb_inflight": stats["max_bytes_inflight"] / (1 << 30), "solo_vs_mix_max_abs": worst})
+        print("serve: load %.2f p50 %.2f ms p99 %.2f ms %.3g fragments/s" % (load, stats["p50_ms"], stats["p99_ms"],
+                                                                          stats["fragments_per_s"]),
+              file=sys.stderr, flush=True)
+    head = sweep[min(1, len(sweep) - 1)]
     line = {"metric": "served frames: p50/p99 latency (arrival to completion) and fragments/s", "mode": "serve",
-            "value": stats["fragments_per_s"], "unit": "fragments/s", "n_gpus": 1, "requests": len(trace),
-            "rate_hz": rate, "load": args.load, "mean_solo_ms": mean_service * 1e3, "p50_ms": stats["p50_ms"],
-            "p99_ms": stats["p99_ms"], "mean_ms": stats["mean_ms"], "slots": args.slots,
-            "budget_gb": args.budget_gb, "max_inflight": stats["max_inflight"],
-            "max_gb_inflight": stats["max_bytes_inflight"] / (1 << 30), "solo_vs_mix_max_abs": worst,
+            "value": head["fragments_per_s"], "unit": "fragments/s", "n_gpus": 1, "load": head["load"],
+            "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"], "mean_solo_ms": mean_service * 1e3,
+            "slots": args.slots, "budget_gb": args.budget_gb, "sweep": sweep,
+            "solo_vs_mix_max_abs": max(x["solo_vs_mix_max_abs"] for x in sweep),
             "data": "synthetic", "dtype": "f32/f16 storage mix",
             "config": {"workload": "Poisson arrivals; 640x360..3840x2160, rank 3/4, f32/f16 storage, "
                                    "Poisson(24) fragments/px"}}

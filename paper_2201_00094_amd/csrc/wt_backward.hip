@@ -140,7 +140,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(Binned b, Geom g, cons
   __syncthreads();
   const uint32_t beg = b.offsets[t * g.NX], end = b.offsets[(t + 1) * g.NX];
   if (lb) {
-    // depth bounds over the tile's valid fragments (section 2.1, step 1)
+    // depth bounds over the tile's valid fragments (section 2.1, step 1): u32 extremes of the FP32 bit patterns
     for (uint32_t lp = threadIdx.x; lp < TP; lp += blockDim.x) {
       lb[lp] = __float_as_uint(1.f);
       lb[TP + lp] = 0u;
@@ -159,22 +159,21 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(Binned b, Geom g, cons
   for (uint32_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
     BFrag<C> f;
     if (!load_bfrag<C>(b, i, f)) continue;
-    const float x = unit_depth(f.x, lb, TP, f.lp);
-    const float u = x * (float)g.M;
-    const uint32_t j = min((uint32_t)u, g.M - 1);
-    const float tt = u - (float)j;
+    uint32_t j;
+    float tt, omt;
+    cell_coord(f.x, lb, TP, f.lp, g.M, j, tt, omt);
     const float gq[3] = {lg[f.lp], lg[TP + f.lp], lg[2 * TP + f.lp]};
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const float* cf = lc + (c * g.M) * TP + f.lp;
       const float hi = cell_value(cf, TP, g, j, CELLS);
       const float lo = j ? cell_value(cf, TP, g, j - 1, CELLS) : 0.f;
-      const float v = __expf(-fmaf(tt, hi, (1.f - tt) * lo));
+      const float v = __expf(-fmaf(tt, hi, omt * lo));
       const float alc = alpha_clamped(f.al[c]);
       const float gc = (C == 1) ? (gq[0] * f.rgb[0] + gq[1] * f.rgb[1] + gq[2] * f.rgb[2]) : gq[c] * f.rgb[c];
       const float s = alc * v * gc;
       double* adj = ladj + (c * g.M) * TP + f.lp;
-      if (j) atomicAdd(adj + (j - 1) * TP, (double)(-s * (1.f - tt)));
+      if (j) atomicAdd(adj + (j - 1) * TP, (double)(-s * omt));
       atomicAdd(adj + j * TP, (double)(-s * tt));
     }
   }
@@ -196,22 +195,21 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(Binned b, Geom g, cons
     BFrag<C> f;
     if (!load_bfrag<C>(b, i, f)) continue;
     const uint64_t src = f.src;
-    const float x = unit_depth(f.x, lb, TP, f.lp);
-    const float u = x * (float)g.M;
-    const uint32_t j = min((uint32_t)u, g.M - 1);
-    const float tt = u - (float)j;
+    uint32_t j;
+    float tt, omt;
+    cell_coord(f.x, lb, TP, f.lp, g.M, j, tt, omt);
     const float gq[3] = {lg[f.lp], lg[TP + f.lp], lg[2 * TP + f.lp]};
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const float* cf = lc + (c * g.M) * TP + f.lp;
       const float hi = cell_value(cf, TP, g, j, CELLS);
       const float lo = j ? cell_value(cf, TP, g, j - 1, CELLS) : 0.f;
-      const float v = __expf(-fmaf(tt, hi, (1.f - tt) * lo));
+      const float v = __expf(-fmaf(tt, hi, omt * lo));
       const float alc = alpha_clamped(f.al[c]);
       const double* S = ladj + (c * g.M) * TP + f.lp;
       const double Sj = S[j * TP];
       const double Sj1 = (j + 1 < g.M) ? S[(j + 1) * TP] : 0.0;
-      const float through_cells = (float)(((double)(j + 1) - (double)u) * (Sj - Sj1) + Sj1);
+      const float through_cells = (float)((double)omt * (Sj - Sj1) + Sj1);
       const float gbg = (C == 1) ? (gq[0] * bg[0] + gq[1] * bg[1] + gq[2] * bg[2]) : gq[c] * bg[c];
       const float dLda = through_cells - gbg * lT[c * TP + f.lp];
       const float gc = (C == 1) ? (gq[0] * f.rgb[0] + gq[1] * f.rgb[1] + gq[2] * f.rgb[2]) : gq[c] * f.rgb[c];

@@ -54,7 +54,7 @@ Geom make_geom(const wt_frame_desc& d, bool backward) {
   uint32_t px;
   g.ep = 0;
   g.tight = (d.flags & WT_TIGHT_DEPTH) ? 1 : 0;
-  const uint32_t bpx = g.tight ? 8 : 0;  // per-pixel depth bounds (two u32) in LDS
+  const uint32_t bpx = g.tight ? 8 : 0;  // per-pixel depth bounds (two FP32) in LDS
   if (backward) {
     px = tile_for(12 * g.C * g.M + 4 * (3 + g.C) + bpx);
   } else {

@@ -103,16 +103,34 @@ __device__ __forceinline__ uint32_t tile_of(const Geom& g, uint32_t p) {
   return (y >> g.lTH) * g.tilesX + (x >> g.lTW);
 }
 
-// Depth of a fragment as the method uses it: clamped to [0, 1], then, with per-pixel bounds (lb: lo bits [TP], hi
-// bits [TP] of tile-local pixels), mapped onto the pixel's own range, (x - lo) / (hi - lo), 0 when lo == hi
-// (section 2.1, step 1). The differences are of FP32 values and the quotient is correctly rounded, so x' <= 1.
-__device__ __forceinline__ float unit_depth(float x, const uint32_t* lb, uint32_t TP, uint32_t lp) {
-  x = fminf(fmaxf(x, 0.f), 1.f);
+// Depth of a fragment as the method uses it: clamped to [0, 1]; with per-pixel bounds (lb: lo [TP], then hi [TP],
+// as FP32 bit patterns) mapped onto the pixel's own range, x' = (x - lo) / (hi - lo), 0 when hi == lo
+// (section 2.1, step 1). The map is taken in FP64, where both differences are exact and the division rounds
+// once (correctly), so x' is the correctly rounded FP64 value of the exact quotient: x = lo and x = hi map to
+// exactly 0 and 1, and the cell offsets below keep the accuracy of a plain FP32 depth.
+__device__ __forceinline__ double unit_depth_d(float x, const uint32_t* lb, uint32_t TP, uint32_t lp) {
+  const float xc = fminf(fmaxf(x, 0.f), 1.f);
+  if (!lb) return (double)xc;
+  const float lo = __uint_as_float(lb[lp]), hi = __uint_as_float(lb[TP + lp]);
+  return hi > lo ? ((double)xc - (double)lo) / ((double)hi - (double)lo) : 0.0;
+}
+
+// Finest cell j of a fragment and the weights of its two endpoints: u = M x', j = min(floor(u), M - 1),
+// t = u - j and omt = 1 - t. Both weights are rounded once from exact or FP64 values (1 - t formed from an
+// already rounded t would lose its relative accuracy as t -> 1). For a plain FP32 depth every step is exact.
+__device__ __forceinline__ void cell_coord(float x, const uint32_t* lb, uint32_t TP, uint32_t lp, uint32_t M,
+                                           uint32_t& j, float& t, float& omt) {
   if (lb) {
-    const float lo = __uint_as_float(lb[lp]), hi = __uint_as_float(lb[TP + lp]);
-    x = hi > lo ? (x - lo) / (hi - lo) : 0.f;
+    const double u = unit_depth_d(x, lb, TP, lp) * (double)M;
+    j = min((uint32_t)u, M - 1);
+    t = (float)(u - (double)j);
+    omt = (float)((double)(j + 1) - u);
+  } else {
+    const float u = fminf(fmaxf(x, 0.f), 1.f) * (float)M;
+    j = min((uint32_t)u, M - 1);
+    t = u - (float)j;
+    omt = 1.f - t;
   }
-  return x;
 }
 
 // Absorbance step a = -ln(1 - alpha) of a (non-NaN) coverage value, with alpha clamped to [0, 1 - 2^-24].

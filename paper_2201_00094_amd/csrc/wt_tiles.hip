@@ -86,9 +86,9 @@ __device__ __forceinline__ bool load_full(const Binned& b, uint32_t i, Frag<C>& 
 
 // ------------------------------------------------------------------------------------------- depth bounds
 
-// Per-pixel depth bounds of the tile (section 2.1, step 1): lb[lp] = lo, lb[TP + lp] = hi as FP32 bits, over the
-// clamped depths of the tile's valid fragments (non-negative floats order like their bit patterns). Ends with a
-// barrier.
+// Per-pixel depth bounds of the tile (section 2.1, step 1): lb[lp] = lo, lb[TP + lp] = hi as FP32 bit patterns,
+// over the clamped depths of the tile's valid fragments (non-negative floats order like their bit patterns, so
+// LDS u32 min/max atomics take them). Ends with a barrier.
 template <int C>
 __device__ __forceinline__ void bounds_tile(const Binned& b, const Geom& g, const TileRef& r, uint32_t* lb) {
   const uint32_t TP = g.tile_px;
@@ -117,19 +117,19 @@ using acc_t = double;
 template <int C>
 __device__ __forceinline__ void build_add(acc_t* lc, const Geom& g, const Frag<C>& f, const uint32_t* lb) {
   const uint32_t TP = g.tile_px;
-  const float x = unit_depth(f.x, lb, TP, f.lp);
+  const double xd = unit_depth_d(f.x, lb, TP, f.lp);
   float a[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     a[c] = absorbance(alpha_clamped(f.al[c]));
-    atomicAdd(lc + (c * g.M) * TP + f.lp, (acc_t)(a[c] * (1.f - x)));
+    atomicAdd(lc + (c * g.M) * TP + f.lp, (acc_t)(a[c] * (float)(1.0 - xd)));
   }
   for (uint32_t n = 0; n <= g.rank; ++n) {
     const uint32_t s = 1u << n;
-    const float u = x * (float)s;
+    const double u = xd * (double)s;
     const uint32_t k = min((uint32_t)u, s - 1);
-    const float t = u - (float)k;
-    const float tau = t < 0.5f ? t : 1.f - t;
+    const double t = u - (double)k;
+    const float tau = (float)(t < 0.5 ? t : 1.0 - t);
 #pragma unroll
     for (int c = 0; c < C; ++c) atomicAdd(lc + (c * g.M + s + k) * TP + f.lp, (acc_t)(-a[c] * tau));
   }
@@ -282,15 +282,14 @@ __device__ __forceinline__ void coeffs_to_cells(const Geom& g, const TileRef& r,
 template <int C>
 __device__ __forceinline__ void build_ep_add(acc_t* le, const Geom& g, const Frag<C>& f, const uint32_t* lb) {
   const uint32_t TP = g.tile_px, M1 = g.M + 1;
-  const float x = unit_depth(f.x, lb, TP, f.lp);
-  const float u = x * (float)g.M;
-  const uint32_t j = min((uint32_t)u, g.M - 1);
-  const float t = u - (float)j;
+  uint32_t j;
+  float t, omt;
+  cell_coord(f.x, lb, TP, f.lp, g.M, j, t, omt);
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     const float a = absorbance(alpha_clamped(f.al[c]));
     acc_t* e = le + (c * M1 + j) * TP + f.lp;
-    atomicAdd(e, (acc_t)(a * (1.f - t)));
+    atomicAdd(e, (acc_t)(a * omt));
     atomicAdd(e + TP, (acc_t)(a * t));
   }
 }
@@ -547,10 +546,9 @@ template <int C, bool CELLS, typename T, bool SUMA = true>
 __device__ __forceinline__ void eval_add(const T* lc, acc_t* la, const Geom& g, const Frag<C>& f,
                                          const uint32_t* lb) {
   const uint32_t TP = g.tile_px;
-  const float x = unit_depth(f.x, lb, TP, f.lp);
-  const float u = x * (float)g.M;
-  const uint32_t j = min((uint32_t)u, g.M - 1);
-  const float t = u - (float)j;
+  uint32_t j;
+  float t, omt;
+  cell_coord(f.x, lb, TP, f.lp, g.M, j, t, omt);
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     const T* cf = lc + (c * g.M) * TP + f.lp;
@@ -562,7 +560,7 @@ __device__ __forceinline__ void eval_add(const T* lc, acc_t* la, const Geom& g, 
       hi = cell_from_coeffs<T>(cf, TP, g, j);
       lo = j ? cell_from_coeffs<T>(cf, TP, g, j - 1) : 0.f;
     }
-    const float At = fmaf(t, hi, (1.f - t) * lo);
+    const float At = fmaf(t, hi, omt * lo);
     const float v = __expf(-At);
     const float alc = alpha_clamped(f.al[c]);
     if (C == 1) {

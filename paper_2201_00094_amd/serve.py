@@ -84,6 +84,7 @@ class ServerStats:
     rejected: int = 0
     fragments: int = 0
     latencies: list = field(default_factory=list)
+    waits: list = field(default_factory=list)   # arrival to admission
     max_inflight: int = 0
     max_bytes_inflight: int = 0
     first_submit: float = float("inf")
@@ -92,9 +93,12 @@ class ServerStats:
     def summary(self) -> dict:
         lat = np.array(self.latencies) * 1e3 if self.latencies else np.zeros(1)
         span = max(self.last_done - self.first_submit, 1e-12)
+        wait = np.array(self.waits) * 1e3 if self.waits else np.zeros(1)
         return {"completed": self.completed, "rejected": self.rejected, "fragments": self.fragments,
                 "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                 "mean_ms": float(lat.mean()), "fragments_per_s": self.fragments / span,
+                "queued": int((wait > 1.0).sum()), "wait_p50_ms": float(np.percentile(wait, 50)),
+                "wait_p99_ms": float(np.percentile(wait, 99)),
                 "max_inflight": self.max_inflight, "max_bytes_inflight": self.max_bytes_inflight}
 
 
@@ -195,6 +199,7 @@ class Server:
                 self.stats.completed += 1
                 self.stats.fragments += r.pend.req.count
                 self.stats.latencies.append(res.latency)
+                self.stats.waits.append(r.t_admit - r.pend.t_submit)
                 self.stats.last_done = max(self.stats.last_done, t)
                 r.pend.fut.set_result(res)
             else:
