@@ -17,7 +17,6 @@
 // A chunk's class is chunk % NX in both k_hist and the scatter; with one chunk per scatter workgroup the class
 // is also the XCD the workgroup runs on, so each (tile, class) run is written from a single L2.
 // NaN fragments are counted as dropped and still binned; the tile kernels skip them.
-#include <stdlib.h>
 
 #include <algorithm>
 
@@ -83,9 +82,11 @@ Geom make_geom(const wt_frame_desc& d, bool backward) {
   g.NX = g.lds_bins ? kClasses : 1;
   // scatter workgroup: 1024 threads (one per CU, larger chunks) by default; WT_SCATTER_WG=512 selects two
   // 512-thread workgroups per CU (tuning override) where their tile tables fit half the LDS
-  const char* wg = getenv("WT_SCATTER_WG");
-  g.sthreads = (wg && atoi(wg) == 512 && g.ntiles <= 4096) ? 512 : 1024;
-  g.chunk = g.sthreads * kPer;
+  // Scatter: 1024 threads, 8 fragments per thread (one workgroup per compute unit), or 4 per thread where the
+  // tile tables and a 1024-record round fit half the LDS, so that two workgroups share a compute unit.
+  g.sthreads = 1024;
+  g.kper = (g.lds_bins && 8ull * g.ntiles + 1024ull * 48 <= kLdsBytes / 2 - 1024) ? 4 : kPer;
+  g.chunk = g.sthreads * g.kper;
   return g;
 }
 
@@ -299,21 +300,22 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t* __restric
 
 // ------------------------------------------------------------------------------------------------ scatter
 
-static_assert(kPer % 4 == 0, "vector loads take fragments four at a time");
 
 // One chunk's fragments, held in registers by the thread that loaded them.
-template <int C>
+template <int C, int PER>
 struct ChunkRegs {
-  uint32_t p[kPer];
-  float x[kPer];
-  float a[C * kPer];
-  float c[3 * kPer];
+  static_assert(PER % 4 == 0, "vector loads take fragments four at a time");
+  uint32_t p[PER];
+  float x[PER];
+  float a[C * PER];
+  float c[3 * PER];
 };
 
-// Loads fragments [i0, i0 + kPer) of the chunk at base; out-of-range slots get pixel id 0xffffffff.
-template <int C>
+// Loads fragments [i0, i0 + PER) of the chunk at base; out-of-range slots get pixel id 0xffffffff.
+template <int C, int PER>
 __device__ __forceinline__ void load_chunk(const wt_fragments& f, uint32_t base, uint32_t i0, uint32_t n, int vec,
-                                           ChunkRegs<C>& r) {
+                                           ChunkRegs<C, PER>& r) {
+  constexpr uint32_t kPer = PER;
   if (vec && i0 + kPer <= n) {
     // pixel ids first: the tile count needs only them, and the other loads stay in flight meanwhile
 #pragma unroll
@@ -357,8 +359,8 @@ __device__ __forceinline__ void load_chunk(const wt_fragments& f, uint32_t base,
   }
 }
 
-template <int C>
-__device__ __forceinline__ bool has_nan(const ChunkRegs<C>& r, uint32_t k) {
+template <int C, int PER>
+__device__ __forceinline__ bool has_nan(const ChunkRegs<C, PER>& r, uint32_t k) {
   bool bad = isnan(r.x[k]);
 #pragma unroll
   for (int q = 0; q < C; ++q) bad |= isnan(r.a[C * k + q]);
@@ -366,8 +368,8 @@ __device__ __forceinline__ bool has_nan(const ChunkRegs<C>& r, uint32_t k) {
 }
 
 // Record dword j of fragment k (tile-local pixel `local`, stream index `src`).
-template <int C>
-__device__ __forceinline__ uint32_t record_word(const ChunkRegs<C>& r, uint32_t k, uint32_t local, uint32_t src,
+template <int C, int PER>
+__device__ __forceinline__ uint32_t record_word(const ChunkRegs<C, PER>& r, uint32_t k, uint32_t local, uint32_t src,
                                                 uint32_t j) {
   if (j == 0) return local;
   if (j == 1) return __float_as_uint(r.x[k]);
@@ -423,8 +425,10 @@ constexpr uint32_t staged_tail_units(bool idx) { return (tail_dwords(idx) + 3) /
 
 // LDS: srec[S][SH + ST] uint4 one round of sorted records, cnt[nt], gb[nt]. The chunk's sorted order is written in
 // rounds of S records (S = stage, a power of two chosen by the host to fit the LDS).
-template <int C, bool IDX, int THREADS>
-__global__ __launch_bounds__(THREADS) void k_scatter_staged(wt_fragments f, Geom g, int vec,
+// PER = 4 is meant for two workgroups per compute unit (LDS <= 80 KB, <= 64 VGPRs at eight waves per SIMD):
+// one workgroup's loads and stores overlap the other's ranking and staging.
+template <int C, bool IDX, int THREADS, int PER>
+__global__ __launch_bounds__(THREADS, PER == 4 ? 8 : 1) void k_scatter_staged(wt_fragments f, Geom g, int vec,
                                                                     uint32_t stage,
                                                                     uint32_t* __restrict__ cursors,
                                                                     uint32_t* __restrict__ head,
@@ -444,19 +448,19 @@ __global__ __launch_bounds__(THREADS) void k_scatter_staged(wt_fragments f, Geom
   const uint32_t n = std::min<uint32_t>(g.chunk, F - base);
   for (uint32_t t = threadIdx.x; t < g.ntiles; t += blockDim.x) cnt[t] = 0;
   if (threadIdx.x == 0) nvalid = 0;
-  ChunkRegs<C> r;
-  const uint32_t i0 = threadIdx.x * kPer;
-  load_chunk<C>(f, base, i0, n, vec, r);
+  ChunkRegs<C, PER> r;
+  const uint32_t i0 = threadIdx.x * PER;
+  load_chunk<C, PER>(f, base, i0, n, vec, r);
   __syncthreads();
-  uint32_t tile[kPer], rank[kPer], local[kPer];
+  uint32_t tile[PER], rank[PER], local[PER];
   uint32_t nan_count = 0, mine = 0;
 #pragma unroll
-  for (uint32_t k = 0; k < kPer; ++k) {
+  for (uint32_t k = 0; k < PER; ++k) {
     tile[k] = 0xffffffffu;
     if (r.p[k] < g.P) {
       tile_locate(g, r.p[k], tile[k], local[k]);
       rank[k] = atomicAdd(&cnt[tile[k]], 1u);
-      nan_count += has_nan<C>(r, k) ? 1u : 0u;
+      nan_count += has_nan<C, PER>(r, k) ? 1u : 0u;
       ++mine;
     }
   }
@@ -484,20 +488,20 @@ __global__ __launch_bounds__(THREADS) void k_scatter_staged(wt_fragments f, Geom
     if (t < g.ntiles) gb[t] = resv[j];
   }
   __syncthreads();
-  uint32_t sp[kPer];
+  uint32_t sp[PER];
 #pragma unroll
-  for (uint32_t k = 0; k < kPer; ++k) sp[k] = (tile[k] == 0xffffffffu) ? 0xffffffffu : cnt[tile[k]] + rank[k];
+  for (uint32_t k = 0; k < PER; ++k) sp[k] = (tile[k] == 0xffffffffu) ? 0xffffffffu : cnt[tile[k]] + rank[k];
   const uint32_t total = nvalid;
   for (uint32_t r0 = 0; r0 < total; r0 += stage) {
 #pragma unroll
-    for (uint32_t k = 0; k < kPer; ++k) {
+    for (uint32_t k = 0; k < PER; ++k) {
       if (sp[k] < r0 || sp[k] >= r0 + stage) continue;  // also skips invalid slots (0xffffffff)
       uint32_t hw[4 * SH], tw[4 * ST];
 #pragma unroll
       for (uint32_t j = 0; j < 4 * SH; ++j)
-        hw[j] = j < DH ? record_word<C>(r, k, local[k], base + i0 + k, j) : gb[tile[k]] + rank[k];
+        hw[j] = j < DH ? record_word<C, PER>(r, k, local[k], base + i0 + k, j) : gb[tile[k]] + rank[k];
 #pragma unroll
-      for (uint32_t j = 0; j < 4 * ST; ++j) tw[j] = j < DT ? record_word<C>(r, k, local[k], base + i0 + k, DH + j) : 0u;
+      for (uint32_t j = 0; j < 4 * ST; ++j) tw[j] = j < DT ? record_word<C, PER>(r, k, local[k], base + i0 + k, DH + j) : 0u;
       uint4* d = srec + (size_t)(sp[k] - r0) * SU;
 #pragma unroll
       for (uint32_t u = 0; u < SH; ++u) d[u] = make_uint4(hw[4 * u], hw[4 * u + 1], hw[4 * u + 2], hw[4 * u + 3]);
@@ -546,21 +550,21 @@ __global__ __launch_bounds__(THREADS) void k_scatter_global(wt_fragments f, Geom
   const uint32_t F = (uint32_t)f.count;
   const uint32_t base = blockIdx.x * g.chunk;
   const uint32_t n = std::min<uint32_t>(g.chunk, F - base);
-  ChunkRegs<C> r;
+  ChunkRegs<C, kPer> r;
   const uint32_t i0 = threadIdx.x * kPer;
-  load_chunk<C>(f, base, i0, n, vec, r);
+  load_chunk<C, kPer>(f, base, i0, n, vec, r);
   uint32_t nan_count = 0;
 #pragma unroll
   for (uint32_t k = 0; k < kPer; ++k) {
     if (r.p[k] >= g.P) continue;
     uint32_t tile, local;
     tile_locate(g, r.p[k], tile, local);
-    nan_count += has_nan<C>(r, k) ? 1u : 0u;
+    nan_count += has_nan<C, kPer>(r, k) ? 1u : 0u;
     const uint64_t pos = atomicAdd(&cursors[tile], 1u);
 #pragma unroll
-    for (uint32_t j = 0; j < DH; ++j) head[pos * DH + j] = record_word<C>(r, k, local, base + i0 + k, j);
+    for (uint32_t j = 0; j < DH; ++j) head[pos * DH + j] = record_word<C, kPer>(r, k, local, base + i0 + k, j);
 #pragma unroll
-    for (uint32_t j = 0; j < DT; ++j) tail[pos * DT + j] = record_word<C>(r, k, local, base + i0 + k, DH + j);
+    for (uint32_t j = 0; j < DT; ++j) tail[pos * DT + j] = record_word<C, kPer>(r, k, local, base + i0 + k, DH + j);
   }
   nan_count = wave_sum(nan_count);
   if ((threadIdx.x & 63) == 0 && nan_count) atomicAdd(dropped, (unsigned long long)nan_count);
@@ -568,18 +572,19 @@ __global__ __launch_bounds__(THREADS) void k_scatter_global(wt_fragments f, Geom
 
 static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
-template <int C, bool IDX, int THREADS>
+template <int C, bool IDX, int PER>
 static hipError_t launch_scatter_t(const Geom& g, const wt_fragments& f, int vec, uint32_t* cursors, uint32_t* head,
                                    uint32_t* tail, unsigned long long* dropped, uint32_t nchunks, hipStream_t s) {
+  constexpr int THREADS = 1024;
   if (g.lds_bins) {
     constexpr uint32_t SU = staged_head_units(C) + staged_tail_units(IDX);
-    // largest power-of-two round that fits beside the tile tables (1 KB left for static LDS); with 512 threads
-    // the round is capped so that two workgroups share a compute unit
-    const size_t budget = (THREADS == 512 ? kLdsBytes / 2 : kLdsBytes) - 1024;
+    // largest power-of-two round beside the tile tables (1 KB left for static LDS), within half the LDS when two
+    // workgroups share a compute unit
+    const size_t budget = (PER == 4 ? kLdsBytes / 2 : kLdsBytes) - 1024;
     uint32_t stage = g.chunk;
     while (stage > 256 && (size_t)stage * SU * 16 + 8ull * g.ntiles > budget) stage >>= 1;
     const size_t lds = (size_t)stage * SU * 16 + 8ull * g.ntiles;
-    auto k = k_scatter_staged<C, IDX, THREADS>;
+    auto k = k_scatter_staged<C, IDX, THREADS, PER>;
     if (lds > 65536) {
       hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return e;
@@ -595,8 +600,8 @@ static hipError_t launch_scatter_t(const Geom& g, const wt_fragments& f, int vec
 template <int C, bool IDX>
 static hipError_t launch_scatter(const Geom& g, const wt_fragments& f, int vec, uint32_t* cursors, uint32_t* head,
                                  uint32_t* tail, unsigned long long* dropped, uint32_t nchunks, hipStream_t s) {
-  if (g.sthreads == 512) return launch_scatter_t<C, IDX, 512>(g, f, vec, cursors, head, tail, dropped, nchunks, s);
-  return launch_scatter_t<C, IDX, 1024>(g, f, vec, cursors, head, tail, dropped, nchunks, s);
+  if (g.kper == 4) return launch_scatter_t<C, IDX, 4>(g, f, vec, cursors, head, tail, dropped, nchunks, s);
+  return launch_scatter_t<C, IDX, 8>(g, f, vec, cursors, head, tail, dropped, nchunks, s);
 }
 
 hipError_t launch_bin_count(const Geom& g, const wt_fragments& f, void* ws, const Layout& l, hipStream_t s) {

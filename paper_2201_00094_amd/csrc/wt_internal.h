@@ -62,7 +62,8 @@ struct Geom {
   uint32_t dtype;        // wt_dtype of the coefficient storage
   uint32_t ep;           // 1: the build accumulates endpoint masses (M <= 32, one pixel/channel per thread)
   uint32_t tight;        // 1: per-pixel depth bounds (WT_TIGHT_DEPTH); the tile kernels keep them in LDS
-  uint32_t sthreads;     // scatter workgroup size (512 or 1024)
+  uint32_t sthreads;     // scatter workgroup size
+  uint32_t kper;         // fragments per scatter thread (4 or kPer)
   uint32_t chunk;        // fragments per scatter workgroup = sthreads * kPer (also the class granularity)
 };
 

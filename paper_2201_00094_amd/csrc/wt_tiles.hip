@@ -113,6 +113,11 @@ __device__ __forceinline__ void bounds_tile(const Binned& b, const Geom& g, cons
 // and every FP32 term then rounds once while the sum rounds nowhere.
 using acc_t = double;
 
+// Binned records each thread keeps in flight in the build and evaluate loops (memory-level parallelism of one
+// workgroup per compute unit).
+constexpr int kBuildUnroll = 8;
+constexpr int kEvalUnroll = 4;
+
 // The N + 2 coefficient updates of one fragment, per channel. lc is [C*M][TP] of acc_t.
 template <int C>
 __device__ __forceinline__ void build_add(acc_t* lc, const Geom& g, const Frag<C>& f, const uint32_t* lb) {
@@ -298,14 +303,14 @@ template <int C>
 __device__ __forceinline__ void build_ep_tile(const Binned& b, const Geom& g, const TileRef& r, acc_t* le,
                                               const uint32_t* lb) {
   uint32_t i = r.beg + threadIdx.x;
-  // four 12-byte head records per thread in flight per step
-  for (; i + 3 * blockDim.x < r.end; i += 4 * blockDim.x) {
-    Frag<C> f[4];
-    bool ok[4];
+  // kBuildUnroll 12-byte head records per thread in flight per step
+  for (; i + (kBuildUnroll - 1) * blockDim.x < r.end; i += kBuildUnroll * blockDim.x) {
+    Frag<C> f[kBuildUnroll];
+    bool ok[kBuildUnroll];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) ok[u] = load_head<C>(b, i + u * blockDim.x, f[u]);
+    for (int u = 0; u < kBuildUnroll; ++u) ok[u] = load_head<C>(b, i + u * blockDim.x, f[u]);
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < kBuildUnroll; ++u)
       if (ok[u]) build_ep_add<C>(le, g, f[u], lb);
   }
   for (; i < r.end; i += blockDim.x) {
@@ -580,14 +585,17 @@ template <int C, bool CELLS, typename T, bool SUMA = true>
 __device__ __forceinline__ void eval_tile(const Binned& b, const Geom& g, const TileRef& r, const T* lc,
                                           acc_t* la, const uint32_t* lb) {
   uint32_t i = r.beg + threadIdx.x;
-  for (; i + blockDim.x < r.end; i += 2 * blockDim.x) {
-    Frag<C> f0, f1;
-    const bool ok0 = load_full<C>(b, i, f0);
-    const bool ok1 = load_full<C>(b, i + blockDim.x, f1);
-    if (ok0) eval_add<C, CELLS, T, SUMA>(lc, la, g, f0, lb);
-    if (ok1) eval_add<C, CELLS, T, SUMA>(lc, la, g, f1, lb);
+  // kEvalUnroll 24-byte records per thread in flight per step
+  for (; i + (kEvalUnroll - 1) * blockDim.x < r.end; i += kEvalUnroll * blockDim.x) {
+    Frag<C> f[kEvalUnroll];
+    bool ok[kEvalUnroll];
+#pragma unroll
+    for (int u = 0; u < kEvalUnroll; ++u) ok[u] = load_full<C>(b, i + u * blockDim.x, f[u]);
+#pragma unroll
+    for (int u = 0; u < kEvalUnroll; ++u)
+      if (ok[u]) eval_add<C, CELLS, T, SUMA>(lc, la, g, f[u], lb);
   }
-  if (i < r.end) {
+  for (; i < r.end; i += blockDim.x) {
     Frag<C> f0;
     if (load_full<C>(b, i, f0)) eval_add<C, CELLS, T, SUMA>(lc, la, g, f0, lb);
   }
