@@ -78,14 +78,17 @@ Geom make_geom(const wt_frame_desc& d, bool backward) {
   g.tilesX = (g.W + g.TW - 1) / g.TW;
   g.tilesY = (g.H + g.TH - 1) / g.TH;
   g.ntiles = g.tilesX * g.tilesY;
-  g.lds_bins = g.ntiles <= kMaxLdsBins ? 1 : 0;
+  // LDS tile tables of at most kMaxLdsBins tiles: one range, or several passes of balanced ranges
+  const uint32_t nr = (g.ntiles + kMaxLdsBins - 1) / kMaxLdsBins;
+  g.lds_bins = nr <= kMaxRanges ? 1 : 0;
+  g.rb = (g.ntiles + nr - 1) / nr;
   g.NX = g.lds_bins ? kClasses : 1;
   // scatter workgroup: 1024 threads (one per CU, larger chunks) by default; WT_SCATTER_WG=512 selects two
   // 512-thread workgroups per CU (tuning override) where their tile tables fit half the LDS
   // Scatter: 1024 threads, 8 fragments per thread (one workgroup per compute unit), or 4 per thread where the
   // tile tables and a 1024-record round fit half the LDS, so that two workgroups share a compute unit.
   g.sthreads = 1024;
-  g.kper = (g.lds_bins && 8ull * g.ntiles + 1024ull * 48 <= kLdsBytes / 2 - 1024) ? 4 : kPer;
+  g.kper = (g.lds_bins && 8ull * g.rb + 1024ull * 48 <= kLdsBytes / 2 - 1024) ? 4 : kPer;
   g.chunk = g.sthreads * g.kper;
   return g;
 }
@@ -148,11 +151,15 @@ __global__ __launch_bounds__(kHistThreads) void k_hist_lds(const uint32_t* __res
                                                            int vec, uint32_t* __restrict__ counts,
                                                            unsigned long long* __restrict__ dropped) {
   extern __shared__ uint32_t lh[];
-  for (uint32_t t = threadIdx.x; t < g.ntiles; t += blockDim.x) lh[t] = 0;
-  __syncthreads();
   const uint32_t cls = blockIdx.x % g.NX;
   const uint32_t nchunks = (uint32_t)(((uint64_t)F + g.chunk - 1) / g.chunk);
   uint32_t nd = 0;
+  // one pass per range of g.rb tiles (a single pass unless the frame has more tiles than the table holds)
+  for (uint32_t t0 = 0; t0 < g.ntiles; t0 += g.rb) {
+  const uint32_t nt = std::min(g.rb, g.ntiles - t0);
+  const bool first = t0 == 0;
+  for (uint32_t t = threadIdx.x; t < nt; t += blockDim.x) lh[t] = 0;
+  __syncthreads();
   for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
     const uint32_t base = c * g.chunk;
     const uint32_t n = std::min<uint32_t>(g.chunk, F - base);
@@ -168,27 +175,33 @@ __global__ __launch_bounds__(kHistThreads) void k_hist_lds(const uint32_t* __res
           const uint32_t ps[4] = {q[v].x, q[v].y, q[v].z, q[v].w};
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
-            if (ps[k] < g.P)
-              atomicAdd(&lh[tile_of(g, ps[k])], 1u);
-            else
+            if (ps[k] < g.P) {
+              const uint32_t t = tile_of(g, ps[k]) - t0;
+              if (t < nt) atomicAdd(&lh[t], 1u);
+            } else if (first) {
               ++nd;
+            }
           }
         }
       }
     } else {
       for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
         const uint32_t p = pixel[base + i];
-        if (p < g.P)
-          atomicAdd(&lh[tile_of(g, p)], 1u);
-        else
+        if (p < g.P) {
+          const uint32_t t = tile_of(g, p) - t0;
+          if (t < nt) atomicAdd(&lh[t], 1u);
+        } else if (first) {
           ++nd;
+        }
       }
     }
   }
   __syncthreads();
-  for (uint32_t t = threadIdx.x; t < g.ntiles; t += blockDim.x) {
+  for (uint32_t t = threadIdx.x; t < nt; t += blockDim.x) {
     const uint32_t v = lh[t];
-    if (v) atomicAdd(&counts[cls * g.ntiles + t], v);
+    if (v) atomicAdd(&counts[cls * g.ntiles + t0 + t], v);
+  }
+  __syncthreads();
   }
   nd = wave_sum(nd);
   if ((threadIdx.x & 63) == 0 && nd) atomicAdd(dropped, (unsigned long long)nd);
@@ -540,6 +553,134 @@ __global__ __launch_bounds__(THREADS, PER == 4 ? 8 : 1) void k_scatter_staged(wt
   if ((threadIdx.x & 63) == 0 && nan_count) atomicAdd(dropped, (unsigned long long)nan_count);
 }
 
+// The same for frames with more tiles than one LDS table holds: the chunk stays in registers and is placed in one
+// pass per range of g.rb tiles.
+template <int C, bool IDX, int THREADS, int PER>
+__global__ __launch_bounds__(THREADS, PER == 4 ? 8 : 1) void k_scatter_ranged(wt_fragments f, Geom g, int vec,
+                                                                    uint32_t stage,
+                                                                    uint32_t* __restrict__ cursors,
+                                                                    uint32_t* __restrict__ head,
+                                                                    uint32_t* __restrict__ tail,
+                                                                    unsigned long long* __restrict__ dropped) {
+  constexpr uint32_t DH = head_dwords(C), DT = tail_dwords(IDX);
+  constexpr uint32_t SH = staged_head_units(C), ST = staged_tail_units(IDX), SU = SH + ST;
+  extern __shared__ uint4 sm4[];
+  uint4* srec = sm4;
+  uint32_t* cnt = (uint32_t*)(srec + (size_t)stage * SU);
+  uint32_t* gb = cnt + g.rb;
+  __shared__ uint32_t wsum[THREADS / 64];
+  __shared__ uint32_t nvalid;
+  const uint32_t F = (uint32_t)f.count;
+  const uint32_t cls = blockIdx.x % g.NX;
+  const uint32_t base = blockIdx.x * g.chunk;
+  const uint32_t n = std::min<uint32_t>(g.chunk, F - base);
+  ChunkRegs<C, PER> r;
+  const uint32_t i0 = threadIdx.x * PER;
+  load_chunk<C, PER>(f, base, i0, n, vec, r);
+  uint32_t tile[PER], local[PER];
+  uint32_t nan_count = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < PER; ++k) {
+    tile[k] = 0xffffffffu;
+    if (r.p[k] < g.P) {
+      tile_locate(g, r.p[k], tile[k], local[k]);
+      nan_count += has_nan<C, PER>(r, k) ? 1u : 0u;
+    }
+  }
+  // The tile tables cover g.rb tiles at a time: one pass per range of tiles [t0, t0 + nt) (one pass unless the
+  // frame has more tiles than a table holds); every fragment is placed in the pass of its tile's range.
+  for (uint32_t t0 = 0; t0 < g.ntiles; t0 += g.rb) {
+  const uint32_t nt = std::min(g.rb, g.ntiles - t0);
+  for (uint32_t t = threadIdx.x; t < nt; t += blockDim.x) cnt[t] = 0;
+  if (threadIdx.x == 0) nvalid = 0;
+  __syncthreads();
+  uint32_t rank[PER];
+  uint32_t mine = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < PER; ++k) {
+    if (tile[k] - t0 < nt) {  // unsigned: also false for invalid slots
+      rank[k] = atomicAdd(&cnt[tile[k] - t0], 1u);
+      ++mine;
+    }
+  }
+  mine = wave_sum(mine);
+  if ((threadIdx.x & 63) == 0 && mine) atomicAdd(&nvalid, mine);
+  __syncthreads();
+  // Reserve this chunk's run in every touched tile. The first kResv tiles of each thread keep their returned
+  // slots in registers until after the block scan, so the round trip of the atomics overlaps the scan.
+  constexpr uint32_t kResv = 4;
+  uint32_t* cur = cursors + cls * g.ntiles + t0;
+  uint32_t resv[kResv];
+#pragma unroll
+  for (uint32_t j = 0; j < kResv; ++j) {
+    const uint32_t t = threadIdx.x + j * THREADS;
+    const uint32_t v = t < nt ? cnt[t] : 0u;
+    resv[j] = v ? atomicAdd(&cur[t], v) : 0u;
+  }
+  for (uint32_t t = threadIdx.x + kResv * THREADS; t < nt; t += THREADS) {
+    const uint32_t v = cnt[t];
+    gb[t] = v ? atomicAdd(&cur[t], v) : 0u;
+  }
+  block_scan_inplace<THREADS>(cnt, nt, wsum);
+#pragma unroll
+  for (uint32_t j = 0; j < kResv; ++j) {
+    const uint32_t t = threadIdx.x + j * THREADS;
+    if (t < nt) gb[t] = resv[j];
+  }
+  __syncthreads();
+  uint32_t sp[PER];
+#pragma unroll
+  for (uint32_t k = 0; k < PER; ++k) sp[k] = (tile[k] - t0 < nt) ? cnt[tile[k] - t0] + rank[k] : 0xffffffffu;
+  const uint32_t total = nvalid;
+  for (uint32_t r0 = 0; r0 < total; r0 += stage) {
+#pragma unroll
+    for (uint32_t k = 0; k < PER; ++k) {
+      if (sp[k] < r0 || sp[k] >= r0 + stage) continue;  // also skips invalid slots (0xffffffff)
+      uint32_t hw[4 * SH], tw[4 * ST];
+#pragma unroll
+      for (uint32_t j = 0; j < 4 * SH; ++j)
+        hw[j] = j < DH ? record_word<C, PER>(r, k, local[k], base + i0 + k, j) : gb[tile[k] - t0] + rank[k];
+#pragma unroll
+      for (uint32_t j = 0; j < 4 * ST; ++j) tw[j] = j < DT ? record_word<C, PER>(r, k, local[k], base + i0 + k, DH + j) : 0u;
+      uint4* d = srec + (size_t)(sp[k] - r0) * SU;
+#pragma unroll
+      for (uint32_t u = 0; u < SH; ++u) d[u] = make_uint4(hw[4 * u], hw[4 * u + 1], hw[4 * u + 2], hw[4 * u + 3]);
+#pragma unroll
+      for (uint32_t u = 0; u < ST; ++u)
+        d[SH + u] = make_uint4(tw[4 * u], tw[4 * u + 1], tw[4 * u + 2], tw[4 * u + 3]);
+    }
+    __syncthreads();
+    const uint32_t ns = std::min(stage, total - r0);
+    for (uint32_t sidx = threadIdx.x; sidx < ns; sidx += blockDim.x) {
+      const uint4* q = srec + (size_t)sidx * SU;
+      uint32_t hw[4 * SH], tw[4 * ST];
+#pragma unroll
+      for (uint32_t u = 0; u < SH; ++u) {
+        const uint4 v = q[u];
+        hw[4 * u] = v.x; hw[4 * u + 1] = v.y; hw[4 * u + 2] = v.z; hw[4 * u + 3] = v.w;
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < ST; ++u) {
+        const uint4 v = q[SH + u];
+        tw[4 * u] = v.x; tw[4 * u + 1] = v.y; tw[4 * u + 2] = v.z; tw[4 * u + 3] = v.w;
+      }
+      const uint64_t slot = hw[DH];
+      Words<DH> h;
+#pragma unroll
+      for (uint32_t j = 0; j < DH; ++j) h.w[j] = hw[j];
+      Words<DT> t;
+#pragma unroll
+      for (uint32_t j = 0; j < DT; ++j) t.w[j] = tw[j];
+      *(Words<DH>*)(head + slot * DH) = h;
+      *(Words<DT>*)(tail + slot * DT) = t;
+    }
+    __syncthreads();
+  }
+  }
+  nan_count = wave_sum(nan_count);
+  if ((threadIdx.x & 63) == 0 && nan_count) atomicAdd(dropped, (unsigned long long)nan_count);
+}
+
 template <int C, bool IDX, int THREADS>
 __global__ __launch_bounds__(THREADS) void k_scatter_global(wt_fragments f, Geom g, int vec,
                                                                     uint32_t* __restrict__ cursors,
@@ -582,9 +723,9 @@ static hipError_t launch_scatter_t(const Geom& g, const wt_fragments& f, int vec
     // workgroups share a compute unit
     const size_t budget = (PER == 4 ? kLdsBytes / 2 : kLdsBytes) - 1024;
     uint32_t stage = g.chunk;
-    while (stage > 256 && (size_t)stage * SU * 16 + 8ull * g.ntiles > budget) stage >>= 1;
-    const size_t lds = (size_t)stage * SU * 16 + 8ull * g.ntiles;
-    auto k = k_scatter_staged<C, IDX, THREADS, PER>;
+    while (stage > 256 && (size_t)stage * SU * 16 + 8ull * g.rb > budget) stage >>= 1;
+    const size_t lds = (size_t)stage * SU * 16 + 8ull * g.rb;
+    auto k = g.rb < g.ntiles ? k_scatter_ranged<C, IDX, THREADS, PER> : k_scatter_staged<C, IDX, THREADS, PER>;
     if (lds > 65536) {
       hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return e;
@@ -621,7 +762,7 @@ hipError_t launch_bin_count(const Geom& g, const wt_fragments& f, void* ws, cons
   if (F > 0) {
     if (g.lds_bins) {
       const uint32_t grid = std::min<uint32_t>(((nchunks + g.NX - 1) / g.NX) * g.NX, 2048);
-      hipLaunchKernelGGL(k_hist_lds, dim3(grid), dim3(kHistThreads), g.ntiles * 4, s, f.pixel, F, g, vec, counts,
+      hipLaunchKernelGGL(k_hist_lds, dim3(grid), dim3(kHistThreads), g.rb * 4, s, f.pixel, F, g, vec, counts,
                          dropped);
     } else {
       hipLaunchKernelGGL(k_hist_global, dim3(2048), dim3(256), 0, s, f.pixel, F, g, counts, dropped);

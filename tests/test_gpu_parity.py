@@ -259,10 +259,10 @@ def test_smoke_1080p_64_sampled(orc, rank):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("width,height", [(1200, 1100), (2000, 1100)])
+@pytest.mark.parametrize("width,height", [(1200, 1100), (2000, 1100), (3840, 2160)])
 def test_many_tiles(orc, width, height):
-    """Three channels at rank 4 use 16 x 8 tiles: about 10,000 tiles (LDS-staged binning with large tile tables)
-    and about 17,000 tiles (one cursor atomic per fragment)."""
+    """Three channels at rank 4 use 16 x 8 tiles: about 10,000 tiles (one LDS tile table), about 17,000 (two
+    passes of tile ranges) and 64,800 at 3840 x 2160 (four passes)."""
     f = synth.frame_c3(seed=width, width=width, height=height, rank=4, particles=1.0)
     say("case many tiles", width, height, "F", f.count)
     g = gpu_render(f)
