@@ -61,24 +61,27 @@ def measured_traffic(kernel, rank, dtype):
     return t.get("workloads", {}).get("r%d_%s" % (rank, dtype), {}).get(kernel)
 
 
-def algorithmic_bytes(F, P, M, coeff_bytes):
-    """Bytes the two-pass method must move for an unsorted stream (one visibility channel): the build reads
-    pixel, depth, alpha (12 B/fragment); the evaluate reads pixel, depth, alpha, rgb (24 B/fragment); the
-    coefficients are written and read once (2 s M B/pixel), the accumulation written and read (32 B/pixel) and
-    the composite written (12 B/pixel)."""
-    return F * (12 + 24) + P * (2 * coeff_bytes * M + 16 + 16 + 12)
+def algorithmic_bytes(F, P, C, coeff_px):
+    """Bytes the two-pass method must move for an unsorted stream with C visibility channels: the build reads
+    pixel, depth, alpha (8 + 4C B/fragment); the evaluate reads them and rgb (20 + 4C B/fragment); the
+    coefficients are written and read once (2 x coeff_px B/pixel: s C M, or 4 M for E5B9G9R9), the accumulation
+    written and read (16 B/pixel at C = 1, 32 at C = 3, each way) and the composite written (12 B/pixel).
+    One channel: F 36 + P (2 s M + 44)."""
+    acc = 16 if C == 1 else 32
+    return F * ((8 + 4 * C) + (20 + 4 * C)) + P * (2 * coeff_px + 2 * acc + 12)
 
 
-def render_kernel_bytes(F, P, M, coeff_bytes):
+def render_kernel_bytes(F, P, C, coeff_px):
     """Algorithmic bytes of the fused per-tile kernel: the build and evaluate reads of each binned fragment
-    (tile-local pixel, depth, alpha: 12 B; plus rgb: 24 B), the coefficient store (s M B/pixel) and the
-    composite store (12 B/pixel); the accumulation never leaves LDS."""
-    return F * (12 + 24) + P * (coeff_bytes * M + 12)
+    (tile-local pixel, depth, alpha: 8 + 4C B; plus rgb: 20 + 4C B), the coefficient store and the composite
+    store (12 B/pixel); the accumulation never leaves LDS."""
+    return F * ((8 + 4 * C) + (20 + 4 * C)) + P * (coeff_px + 12)
 
 
-def scatter_kernel_bytes(F):
-    """Algorithmic bytes of the binning scatter: read the fragment (24 B) and write its binned copy (24 B)."""
-    return F * 48
+def scatter_kernel_bytes(F, C):
+    """Algorithmic bytes of the binning scatter: read the fragment (20 + 4C B) and write its binned record
+    (tile-local pixel, depth, alpha, rgb: 20 + 4C B); 48 B at C = 1."""
+    return F * 2 * (20 + 4 * C)
 
 
 def cpu_baseline(f, fraction, seed, min_seconds=10.0, max_reps=8):
@@ -106,7 +109,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--rank", type=int, default=3)
-    ap.add_argument("--dtype", default="f32", choices=("f32", "f16", "bf16"))
+    ap.add_argument("--dtype", default="f32", choices=("f32", "f16", "bf16", "e5b9g9r9"))
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-fraction", type=float, default=1.0,
                     help="share of the frame's pixels the CPU oracle baseline resolves")
@@ -118,6 +121,9 @@ def main():
                          "precision: the glass + particles frame (3840x2160, three channels) with every coefficient "
                          "storage, timed, with errors against the FP64 oracle and the exact A-buffer")
     ap.add_argument("--tight", action="store_true", help="per-pixel depth bounds (WT_TIGHT_DEPTH)")
+    ap.add_argument("--workload", default="smoke", choices=("smoke", "glass"),
+                    help="frame mode: smoke (1920x1080, one visibility channel; the headline) or glass "
+                         "(3840x2160 glass + particles, three visibility channels)")
     ap.add_argument("--sample-pixels", type=int, default=4000, help="precision mode: pixels checked by the oracle")
     ap.add_argument("--pmc", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="traffic mode: rocprofv3 output folders of the frame and copy runs")
@@ -150,13 +156,14 @@ def main():
     import synth
 
     t_gen = time.perf_counter()
-    f = synth.frame_c2(seed=args.seed, rank=args.rank)
+    glass = args.workload == "glass"
+    f = synth.frame_c3(seed=args.seed, rank=args.rank) if glass else synth.frame_c2(seed=args.seed, rank=args.rank)
     gen_s = time.perf_counter() - t_gen
     print("bench: generated %s, %d fragments in %.1f s" % (f.name, f.count, gen_s), file=sys.stderr, flush=True)
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    spec = wt.FrameSpec(f.width, f.height, args.rank, 1, args.dtype, args.tight)
+    spec = wt.FrameSpec(f.width, f.height, args.rank, f.channels, args.dtype, args.tight)
     fr = wt.Fragments.from_numpy(f.pixel, f.depth, f.alpha, f.rgb, device=dev)
     ws = wt.Workspace(spec, f.count, device=dev)
     coeffs = spec.new_coeffs(device=dev)
@@ -196,12 +203,12 @@ def main():
     scatter_ms = np.array([ev[k][1].elapsed_time(ev[k][2]) for k in range(K)])
     render_ms = np.array([ev[k][2].elapsed_time(ev[k][3]) for k in range(K)])
     ms_per_step = wall * 1e3 / K
-    F, P, M = f.count, f.pixels, spec.M
-    sbytes = {"f32": 4, "f16": 2, "bf16": 2}[args.dtype]
-    b_alg = algorithmic_bytes(F, P, M, sbytes)
+    F, P, M, C = f.count, f.pixels, spec.M, f.channels
+    coeff_px = 4 * M if args.dtype == "e5b9g9r9" else {"f32": 4, "f16": 2, "bf16": 2}[args.dtype] * C * M
+    b_alg = algorithmic_bytes(F, P, C, coeff_px)
     kernels = {
-        "k_render": (render_kernel_bytes(F, P, M, sbytes), float(render_ms.mean())),
-        "k_scatter_staged": (scatter_kernel_bytes(F), float(scatter_ms.mean())),
+        "k_render": (render_kernel_bytes(F, P, C, coeff_px), float(render_ms.mean())),
+        "k_scatter_staged": (scatter_kernel_bytes(F, C), float(scatter_ms.mean())),
     }
     dom = max(kernels, key=lambda k: kernels[k][1])
     dom_bytes, dom_ms = kernels[dom]
@@ -220,9 +227,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "smoke 1920x1080, Poisson(64 g) fragments/px (unsorted stream), rank %d, %s "
-                               "coefficient storage%s" % (args.rank, args.dtype,
-                                                         ", per-pixel depth bounds" if args.tight else ""),
+        "config": {"workload": ("glass + particles 3840x2160, 2-4 glass layers + Poisson(24) particles/px, three "
+                                "visibility channels" if glass else
+                                "smoke 1920x1080, Poisson(64 g) fragments/px") +
+                               " (unsorted stream), rank %d, %s coefficient storage%s" % (
+                                   args.rank, args.dtype, ", per-pixel depth bounds" if args.tight else ""),
                    "width": f.width, "height": f.height, "rank": args.rank, "coeff_dtype": args.dtype,
                    "fragments": F, "seed": args.seed},
         "p50_ms": float(np.percentile(frame_ms, 50)),

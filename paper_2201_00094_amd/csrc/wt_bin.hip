@@ -82,6 +82,8 @@ Geom make_geom(const wt_frame_desc& d, bool backward) {
   const uint32_t nr = (g.ntiles + kMaxLdsBins - 1) / kMaxLdsBins;
   g.lds_bins = nr <= kMaxRanges ? 1 : 0;
   g.rb = (g.ntiles + nr - 1) / nr;
+  const uint32_t hnr = (g.ntiles + kMaxHistBins - 1) / kMaxHistBins;
+  g.hrb = (g.ntiles + hnr - 1) / hnr;
   g.NX = g.lds_bins ? kClasses : 1;
   // scatter workgroup: 1024 threads (one per CU, larger chunks) by default; WT_SCATTER_WG=512 selects two
   // 512-thread workgroups per CU (tuning override) where their tile tables fit half the LDS
@@ -145,8 +147,10 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint64_t n, uint32_t v) {
 
 // ------------------------------------------------------------------------------------------------ histogram
 
-constexpr int kHistThreads = 256;
+// Workgroups of 256 threads, or of 1024 when the tile table is large (up to 144 KB of LDS leaves one workgroup per
+// compute unit, which then still has sixteen waves of loads in flight).
 
+template <int kHistThreads>
 __global__ __launch_bounds__(kHistThreads) void k_hist_lds(const uint32_t* __restrict__ pixel, uint32_t F, Geom g,
                                                            int vec, uint32_t* __restrict__ counts,
                                                            unsigned long long* __restrict__ dropped) {
@@ -154,9 +158,9 @@ __global__ __launch_bounds__(kHistThreads) void k_hist_lds(const uint32_t* __res
   const uint32_t cls = blockIdx.x % g.NX;
   const uint32_t nchunks = (uint32_t)(((uint64_t)F + g.chunk - 1) / g.chunk);
   uint32_t nd = 0;
-  // one pass per range of g.rb tiles (a single pass unless the frame has more tiles than the table holds)
-  for (uint32_t t0 = 0; t0 < g.ntiles; t0 += g.rb) {
-  const uint32_t nt = std::min(g.rb, g.ntiles - t0);
+  // one pass per range of g.hrb tiles (a single pass unless the frame has more tiles than the table holds)
+  for (uint32_t t0 = 0; t0 < g.ntiles; t0 += g.hrb) {
+  const uint32_t nt = std::min(g.hrb, g.ntiles - t0);
   const bool first = t0 == 0;
   for (uint32_t t = threadIdx.x; t < nt; t += blockDim.x) lh[t] = 0;
   __syncthreads();
@@ -164,14 +168,19 @@ __global__ __launch_bounds__(kHistThreads) void k_hist_lds(const uint32_t* __res
     const uint32_t base = c * g.chunk;
     const uint32_t n = std::min<uint32_t>(g.chunk, F - base);
     if (vec && n == g.chunk) {
-      // chunk / 4 uint4 per chunk; four per thread in flight at a time
+      // chunk / 4 uint4 per chunk; up to four per thread in flight at a time
       const uint4* q4 = (const uint4*)(pixel + base);
-      for (uint32_t v0 = 0; v0 < g.chunk / 4; v0 += 4 * kHistThreads) {
+      const uint32_t nv = g.chunk / 4;
+      for (uint32_t v0 = 0; v0 < nv; v0 += 4 * kHistThreads) {
         uint4 q[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) q[v] = q4[v0 + v * kHistThreads + threadIdx.x];
+        for (int v = 0; v < 4; ++v) {
+          const uint32_t iv = v0 + v * kHistThreads + threadIdx.x;
+          q[v] = iv < nv ? q4[iv] : make_uint4(0u, 0u, 0u, 0u);
+        }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
+          if (v0 + v * kHistThreads + threadIdx.x >= nv) continue;
           const uint32_t ps[4] = {q[v].x, q[v].y, q[v].z, q[v].w};
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
@@ -762,8 +771,17 @@ hipError_t launch_bin_count(const Geom& g, const wt_fragments& f, void* ws, cons
   if (F > 0) {
     if (g.lds_bins) {
       const uint32_t grid = std::min<uint32_t>(((nchunks + g.NX - 1) / g.NX) * g.NX, 2048);
-      hipLaunchKernelGGL(k_hist_lds, dim3(grid), dim3(kHistThreads), g.rb * 4, s, f.pixel, F, g, vec, counts,
-                         dropped);
+      const size_t lds = 4ull * g.hrb;
+      if (lds <= 32768) {
+        hipLaunchKernelGGL(k_hist_lds<256>, dim3(grid), dim3(256), lds, s, f.pixel, F, g, vec, counts, dropped);
+      } else {
+        auto k = k_hist_lds<1024>;
+        if (lds > 65536) {
+          hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+          if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(k, dim3(grid), dim3(1024), lds, s, f.pixel, F, g, vec, counts, dropped);
+      }
     } else {
       hipLaunchKernelGGL(k_hist_global, dim3(2048), dim3(256), 0, s, f.pixel, F, g, counts, dropped);
     }

@@ -14,8 +14,9 @@ namespace wt {
 // partial cache lines of a frontier are filled inside a single L2 before they are written back.
 constexpr uint32_t kClasses = 8;
 constexpr uint32_t kPer = 8;               // fragments per scatter thread (held in registers)
-constexpr uint32_t kMaxLdsBins = 16384;    // tiles one LDS tile table holds (per pass of the staged binning)
-constexpr uint32_t kMaxRanges = 4;         // passes of tile ranges; beyond kMaxRanges * kMaxLdsBins: global path
+constexpr uint32_t kMaxLdsBins = 8192;     // tiles one scatter tile table holds (per pass of the staged binning)
+constexpr uint32_t kMaxRanges = 8;         // passes of tile ranges; beyond kMaxRanges * kMaxLdsBins: global path
+constexpr uint32_t kMaxHistBins = 36864;   // tiles one histogram table holds (144 KB of LDS)
 constexpr uint32_t kLdsBytes = 160 * 1024; // LDS of one CDNA4 compute unit (also the per-workgroup limit)
 constexpr uint32_t kMaxTilePx = 2048;
 constexpr uint32_t kTileThreads = 1024;    // workgroup size of the per-tile kernels
@@ -58,7 +59,8 @@ struct Geom {
   uint32_t tilesX, tilesY, ntiles, tile_px;
   uint32_t NX;           // write-frontier classes (kClasses, or 1 when the tile count is large)
   uint32_t lds_bins;     // 1: LDS-staged scatter; 0: one global atomic per fragment
-  uint32_t rb;           // tiles per LDS table (range); ceil(ntiles / ranges)
+  uint32_t rb;           // tiles per scatter table (range): ceil(ntiles / ranges)
+  uint32_t hrb;          // tiles per histogram table (range)
   uint32_t AW;           // accum floats per pixel in global memory: 4 (C = 1) or 8 (C = 3)
   uint32_t AL;           // accumulation floats per pixel in LDS: 4 (C = 1) or 6 (C = 3)
   uint32_t dtype;        // wt_dtype of the coefficient storage
