@@ -7,15 +7,21 @@
 // per-pixel update of the build and evaluate passes happens in the LDS of the compute unit that owns the tile.
 //
 // Kernels:
-//   k_hist            pixel ids (4 B/fragment) -> per-(class, tile) counts; range drops counted.
-//   k_scan            exclusive scan of the counts, tile-major, into segment offsets and write cursors.
-//   k_scatter_staged  one chunk (kPer fragments per thread) per workgroup: vector loads into registers, LDS count
-//                     per tile, one cursor reservation per touched tile, records placed in LDS in tile order,
-//                     then written as flat runs of dwords (head array, then tail array) so that consecutive
-//                     lanes store consecutive addresses inside each tile's run.
-//   k_scatter_global  one cursor atomic per fragment (very many tiles).
-// A chunk's class is chunk % NX in both k_hist and the scatter; with one chunk per scatter workgroup the class
-// is also the XCD the workgroup runs on, so each (tile, class) run is written from a single L2.
+//   k_hist_lds        pixel ids (4 B/fragment) -> per-(class, tile) counts in an LDS table (in passes of tile
+//                     ranges for very large frames); range drops counted.
+//   k_scan            exclusive scan of the counts, tile-major over (tile, class), into segment offsets and write
+//                     cursors; tile order for the tile kernels (heaviest first).
+//   k_scatter_staged  one chunk (4 or 8 fragments per thread) per workgroup: vector loads into registers, LDS
+//                     rank per tile, one cursor reservation per touched tile, records placed in LDS in tile order,
+//                     then written record by record with consecutive lanes on consecutive records (head array,
+//                     then tail array), so each tile's run is written coalesced.
+//   Frames with more than kTwoLevelTiles tiles: a chunk would touch most tiles about once, so the stream is
+//   binned into super-tiles of SW x SH tiles first (k_super_counts, k_scan and k_scatter_staged over the
+//   super-tile geometry), then k_split moves each super-tile's records into its tiles without atomics.
+//   k_hist_global,    one global atomic per fragment (beyond kMaxLdsBins super-tiles).
+//   k_scatter_global
+// A chunk's class is chunk % NX in both the histogram and the scatter; with one chunk per scatter workgroup the
+// class is also the XCD the workgroup runs on, so each (bin, class) run is written from a single L2.
 // NaN fragments are counted as dropped and still binned; the tile kernels skip them.
 
 #include <algorithm>
@@ -78,21 +84,65 @@ Geom make_geom(const wt_frame_desc& d, bool backward) {
   g.tilesX = (g.W + g.TW - 1) / g.TW;
   g.tilesY = (g.H + g.TH - 1) / g.TH;
   g.ntiles = g.tilesX * g.tilesY;
-  // LDS tile tables of at most kMaxLdsBins tiles: one range, or several passes of balanced ranges
-  const uint32_t nr = (g.ntiles + kMaxLdsBins - 1) / kMaxLdsBins;
-  g.lds_bins = nr <= kMaxRanges ? 1 : 0;
-  g.rb = (g.ntiles + nr - 1) / nr;
+  // One LDS tile table for the scatter (up to kTwoLevelTiles tiles; beyond, two levels below)
+  g.lds_bins = g.ntiles <= kTwoLevelTiles ? 1 : 0;
+  g.rb = g.ntiles;
   const uint32_t hnr = (g.ntiles + kMaxHistBins - 1) / kMaxHistBins;
   g.hrb = (g.ntiles + hnr - 1) / hnr;
+  // Many tiles: a chunk of the stream touches each tile about chunk / ntiles times, too few for whole runs. Bin
+  // into at most kMaxSupers super-tiles of SW x SH tiles first (runs as long as for a small frame), then split
+  // each super-tile's records into its tiles (runs of hundreds of records, no atomics).
+  g.two = 0;
+  g.SW = g.SH = 1;
+  if (g.ntiles > kTwoLevelTiles) {
+    auto supers = [&](uint32_t sw, uint32_t sh) {
+      return ((g.tilesX + sw - 1) / sw) * ((g.tilesY + sh - 1) / sh);
+    };
+    while (supers(g.SW, g.SH) > kMaxSupers && g.SW * g.SH < kMaxSub) {
+      if (g.SW <= g.SH) g.SW *= 2;
+      else g.SH *= 2;
+    }
+    // super-tile tables must fit the scatter's LDS; beyond that (about half a million tiles) the stream is
+    // binned with one global atomic per fragment
+    g.two = supers(g.SW, g.SH) <= kMaxLdsBins ? 1 : 0;
+    g.lds_bins = g.two;
+  }
+  g.lSW = 0;
+  while ((1u << g.lSW) < g.SW) ++g.lSW;
+  g.lSH = 0;
+  while ((1u << g.lSH) < g.SH) ++g.lSH;
+  g.sX = (g.tilesX + g.SW - 1) / g.SW;
+  g.sY = (g.tilesY + g.SH - 1) / g.SH;
+  g.nsuper = g.sX * g.sY;
   g.NX = g.lds_bins ? kClasses : 1;
-  // scatter workgroup: 1024 threads (one per CU, larger chunks) by default; WT_SCATTER_WG=512 selects two
-  // 512-thread workgroups per CU (tuning override) where their tile tables fit half the LDS
   // Scatter: 1024 threads, 8 fragments per thread (one workgroup per compute unit), or 4 per thread where the
-  // tile tables and a 1024-record round fit half the LDS, so that two workgroups share a compute unit.
+  // tile tables (of the binning level that scatters) and a 1024-record round fit half the LDS, so that two
+  // workgroups share a compute unit.
   g.sthreads = 1024;
-  g.kper = (g.lds_bins && 8ull * g.rb + 1024ull * 48 <= kLdsBytes / 2 - 1024) ? 4 : kPer;
+  const uint32_t bins = g.two ? g.nsuper : g.rb;
+  // (one channel only: the three-channel fragment does not fit the 64 registers of eight waves per SIMD)
+  g.kper = (g.C == 1 && g.lds_bins && 8ull * bins + 1024ull * 48 <= kLdsBytes / 2 - 1024) ? 4 : kPer;
   g.chunk = g.sthreads * g.kper;
   return g;
+}
+
+Geom super_geom(const Geom& g) {
+  Geom s = g;
+  s.lTW = g.lTW + g.lSW;
+  s.lTH = g.lTH + g.lSH;
+  s.TW = 1u << s.lTW;
+  s.TH = 1u << s.lTH;
+  s.tile_px = s.TW * s.TH;
+  s.tilesX = g.sX;
+  s.tilesY = g.sY;
+  s.ntiles = g.nsuper;
+  s.rb = s.hrb = g.nsuper;
+  s.two = 0;
+  s.SW = s.SH = 1;
+  s.lSW = s.lSH = 0;
+  s.sX = s.tilesX;
+  s.sY = s.tilesY;
+  return s;  // NX, kper and chunk stay those of g: the first level uses the classes the histogram counted
 }
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -114,6 +164,21 @@ Layout make_layout(const Geom& g, uint64_t cap) {
   o = align256(o + 4ull * head_dwords(g.C) * cap);
   l.tails = o;
   o = align256(o + 4ull * tail_dwords(true) * cap);
+  l.counts1 = l.offsets1 = l.cursors1 = l.order1 = l.heads1 = l.tails1 = o;
+  if (g.two) {
+    l.counts1 = o;
+    o = align256(o + 4ull * g.NX * g.nsuper);
+    l.offsets1 = o;
+    o = align256(o + 4ull * (g.NX * (uint64_t)g.nsuper + 1));
+    l.cursors1 = o;
+    o = align256(o + 4ull * g.NX * g.nsuper);
+    l.order1 = o;
+    o = align256(o + 4ull * g.nsuper);
+    l.heads1 = o;
+    o = align256(o + 4ull * head_dwords(g.C) * cap);
+    l.tails1 = o;
+    o = align256(o + 4ull * tail_dwords(true) * cap);
+  }
   l.total = o;
   l.cap = cap;
   return l;
@@ -122,7 +187,7 @@ Layout make_layout(const Geom& g, uint64_t cap) {
 uint64_t capacity_for(const Geom& g, size_t ws_bytes) {
   const size_t fixed = make_layout(g, 0).total;
   if (ws_bytes < fixed) return 0;
-  const uint64_t per = 4ull * record_dwords(g.C, true);
+  const uint64_t per = 4ull * record_dwords(g.C, true) * (g.two ? 2 : 1);
   uint64_t cap = (ws_bytes - fixed) / per;
   while (cap > 0 && make_layout(g, cap).total > ws_bytes) --cap;
   return cap;
@@ -243,7 +308,7 @@ constexpr uint32_t kOrderMax = 4096;  // tile counts up to this are ordered by s
 __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t* __restrict__ counts, Geom g,
                                                        uint32_t* __restrict__ offsets,
                                                        uint32_t* __restrict__ cursors,
-                                                       uint32_t* __restrict__ order) {
+                                                       uint32_t* __restrict__ order, int with_order) {
   __shared__ uint32_t sums[kScanThreads];
   __shared__ unsigned long long keys[kOrderMax];
   const uint64_t n = (uint64_t)g.ntiles * g.NX;
@@ -285,6 +350,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t* __restric
     __syncthreads();
   }
   if (tid == 0) offsets[n] = carry;
+  if (!with_order) return;
   if (g.ntiles > kOrderMax) {
     for (uint32_t t = tid; t < g.ntiles; t += kScanThreads) order[t] = t;
     return;
@@ -318,6 +384,21 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t* __restric
     }
   }
   for (uint32_t t = tid; t < g.ntiles; t += kScanThreads) order[t] = (uint32_t)(keys[t] & 0xffffffffu);
+}
+
+// Per-class counts of the super-tiles (first level of two-level binning) from the per-class tile counts.
+__global__ __launch_bounds__(256) void k_super_counts(const uint32_t* __restrict__ counts, Geom g,
+                                                      uint32_t* __restrict__ counts1) {
+  const uint32_t id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= g.NX * g.nsuper) return;
+  const uint32_t x = id / g.nsuper, sidx = id - x * g.nsuper;
+  const uint32_t sx = sidx % g.sX, sy = sidx / g.sX;
+  uint32_t sum = 0;
+  for (uint32_t j = 0; j < g.SW * g.SH; ++j) {
+    const uint32_t tx = (sx << g.lSW) + (j & (g.SW - 1)), ty = (sy << g.lSH) + (j >> g.lSW);
+    if (tx < g.tilesX && ty < g.tilesY) sum += counts[x * g.ntiles + ty * g.tilesX + tx];
+  }
+  counts1[id] = sum;
 }
 
 // ------------------------------------------------------------------------------------------------ scatter
@@ -562,134 +643,6 @@ __global__ __launch_bounds__(THREADS, PER == 4 ? 8 : 1) void k_scatter_staged(wt
   if ((threadIdx.x & 63) == 0 && nan_count) atomicAdd(dropped, (unsigned long long)nan_count);
 }
 
-// The same for frames with more tiles than one LDS table holds: the chunk stays in registers and is placed in one
-// pass per range of g.rb tiles.
-template <int C, bool IDX, int THREADS, int PER>
-__global__ __launch_bounds__(THREADS, PER == 4 ? 8 : 1) void k_scatter_ranged(wt_fragments f, Geom g, int vec,
-                                                                    uint32_t stage,
-                                                                    uint32_t* __restrict__ cursors,
-                                                                    uint32_t* __restrict__ head,
-                                                                    uint32_t* __restrict__ tail,
-                                                                    unsigned long long* __restrict__ dropped) {
-  constexpr uint32_t DH = head_dwords(C), DT = tail_dwords(IDX);
-  constexpr uint32_t SH = staged_head_units(C), ST = staged_tail_units(IDX), SU = SH + ST;
-  extern __shared__ uint4 sm4[];
-  uint4* srec = sm4;
-  uint32_t* cnt = (uint32_t*)(srec + (size_t)stage * SU);
-  uint32_t* gb = cnt + g.rb;
-  __shared__ uint32_t wsum[THREADS / 64];
-  __shared__ uint32_t nvalid;
-  const uint32_t F = (uint32_t)f.count;
-  const uint32_t cls = blockIdx.x % g.NX;
-  const uint32_t base = blockIdx.x * g.chunk;
-  const uint32_t n = std::min<uint32_t>(g.chunk, F - base);
-  ChunkRegs<C, PER> r;
-  const uint32_t i0 = threadIdx.x * PER;
-  load_chunk<C, PER>(f, base, i0, n, vec, r);
-  uint32_t tile[PER], local[PER];
-  uint32_t nan_count = 0;
-#pragma unroll
-  for (uint32_t k = 0; k < PER; ++k) {
-    tile[k] = 0xffffffffu;
-    if (r.p[k] < g.P) {
-      tile_locate(g, r.p[k], tile[k], local[k]);
-      nan_count += has_nan<C, PER>(r, k) ? 1u : 0u;
-    }
-  }
-  // The tile tables cover g.rb tiles at a time: one pass per range of tiles [t0, t0 + nt) (one pass unless the
-  // frame has more tiles than a table holds); every fragment is placed in the pass of its tile's range.
-  for (uint32_t t0 = 0; t0 < g.ntiles; t0 += g.rb) {
-  const uint32_t nt = std::min(g.rb, g.ntiles - t0);
-  for (uint32_t t = threadIdx.x; t < nt; t += blockDim.x) cnt[t] = 0;
-  if (threadIdx.x == 0) nvalid = 0;
-  __syncthreads();
-  uint32_t rank[PER];
-  uint32_t mine = 0;
-#pragma unroll
-  for (uint32_t k = 0; k < PER; ++k) {
-    if (tile[k] - t0 < nt) {  // unsigned: also false for invalid slots
-      rank[k] = atomicAdd(&cnt[tile[k] - t0], 1u);
-      ++mine;
-    }
-  }
-  mine = wave_sum(mine);
-  if ((threadIdx.x & 63) == 0 && mine) atomicAdd(&nvalid, mine);
-  __syncthreads();
-  // Reserve this chunk's run in every touched tile. The first kResv tiles of each thread keep their returned
-  // slots in registers until after the block scan, so the round trip of the atomics overlaps the scan.
-  constexpr uint32_t kResv = 4;
-  uint32_t* cur = cursors + cls * g.ntiles + t0;
-  uint32_t resv[kResv];
-#pragma unroll
-  for (uint32_t j = 0; j < kResv; ++j) {
-    const uint32_t t = threadIdx.x + j * THREADS;
-    const uint32_t v = t < nt ? cnt[t] : 0u;
-    resv[j] = v ? atomicAdd(&cur[t], v) : 0u;
-  }
-  for (uint32_t t = threadIdx.x + kResv * THREADS; t < nt; t += THREADS) {
-    const uint32_t v = cnt[t];
-    gb[t] = v ? atomicAdd(&cur[t], v) : 0u;
-  }
-  block_scan_inplace<THREADS>(cnt, nt, wsum);
-#pragma unroll
-  for (uint32_t j = 0; j < kResv; ++j) {
-    const uint32_t t = threadIdx.x + j * THREADS;
-    if (t < nt) gb[t] = resv[j];
-  }
-  __syncthreads();
-  uint32_t sp[PER];
-#pragma unroll
-  for (uint32_t k = 0; k < PER; ++k) sp[k] = (tile[k] - t0 < nt) ? cnt[tile[k] - t0] + rank[k] : 0xffffffffu;
-  const uint32_t total = nvalid;
-  for (uint32_t r0 = 0; r0 < total; r0 += stage) {
-#pragma unroll
-    for (uint32_t k = 0; k < PER; ++k) {
-      if (sp[k] < r0 || sp[k] >= r0 + stage) continue;  // also skips invalid slots (0xffffffff)
-      uint32_t hw[4 * SH], tw[4 * ST];
-#pragma unroll
-      for (uint32_t j = 0; j < 4 * SH; ++j)
-        hw[j] = j < DH ? record_word<C, PER>(r, k, local[k], base + i0 + k, j) : gb[tile[k] - t0] + rank[k];
-#pragma unroll
-      for (uint32_t j = 0; j < 4 * ST; ++j) tw[j] = j < DT ? record_word<C, PER>(r, k, local[k], base + i0 + k, DH + j) : 0u;
-      uint4* d = srec + (size_t)(sp[k] - r0) * SU;
-#pragma unroll
-      for (uint32_t u = 0; u < SH; ++u) d[u] = make_uint4(hw[4 * u], hw[4 * u + 1], hw[4 * u + 2], hw[4 * u + 3]);
-#pragma unroll
-      for (uint32_t u = 0; u < ST; ++u)
-        d[SH + u] = make_uint4(tw[4 * u], tw[4 * u + 1], tw[4 * u + 2], tw[4 * u + 3]);
-    }
-    __syncthreads();
-    const uint32_t ns = std::min(stage, total - r0);
-    for (uint32_t sidx = threadIdx.x; sidx < ns; sidx += blockDim.x) {
-      const uint4* q = srec + (size_t)sidx * SU;
-      uint32_t hw[4 * SH], tw[4 * ST];
-#pragma unroll
-      for (uint32_t u = 0; u < SH; ++u) {
-        const uint4 v = q[u];
-        hw[4 * u] = v.x; hw[4 * u + 1] = v.y; hw[4 * u + 2] = v.z; hw[4 * u + 3] = v.w;
-      }
-#pragma unroll
-      for (uint32_t u = 0; u < ST; ++u) {
-        const uint4 v = q[SH + u];
-        tw[4 * u] = v.x; tw[4 * u + 1] = v.y; tw[4 * u + 2] = v.z; tw[4 * u + 3] = v.w;
-      }
-      const uint64_t slot = hw[DH];
-      Words<DH> h;
-#pragma unroll
-      for (uint32_t j = 0; j < DH; ++j) h.w[j] = hw[j];
-      Words<DT> t;
-#pragma unroll
-      for (uint32_t j = 0; j < DT; ++j) t.w[j] = tw[j];
-      *(Words<DH>*)(head + slot * DH) = h;
-      *(Words<DT>*)(tail + slot * DT) = t;
-    }
-    __syncthreads();
-  }
-  }
-  nan_count = wave_sum(nan_count);
-  if ((threadIdx.x & 63) == 0 && nan_count) atomicAdd(dropped, (unsigned long long)nan_count);
-}
-
 template <int C, bool IDX, int THREADS>
 __global__ __launch_bounds__(THREADS) void k_scatter_global(wt_fragments f, Geom g, int vec,
                                                                     uint32_t* __restrict__ cursors,
@@ -720,6 +673,107 @@ __global__ __launch_bounds__(THREADS) void k_scatter_global(wt_fragments f, Geom
   if ((threadIdx.x & 63) == 0 && nan_count) atomicAdd(dropped, (unsigned long long)nan_count);
 }
 
+// Second level of two-level binning: one workgroup per super-tile moves its records (all classes, contiguous in
+// the first-level arrays) into the tiles' segments of the final arrays. Rounds of kSplitRecs records: rank by tile
+// in LDS, place in tile order in LDS, write with consecutive lanes on consecutive records. The workgroup owns
+// its tiles, so their write cursors live in LDS; runs are about kSplitRecs / (SW SH) records long.
+constexpr uint32_t kSplitThreads = 1024;
+constexpr uint32_t kSplitPer = 2;
+constexpr uint32_t kSplitRecs = kSplitThreads * kSplitPer;
+
+template <int C, bool IDX>
+__global__ __launch_bounds__(kSplitThreads) void k_split(Geom g, const uint32_t* __restrict__ offsets1,
+                                                         const uint32_t* __restrict__ offsets,
+                                                         const uint32_t* __restrict__ head1,
+                                                         const uint32_t* __restrict__ tail1,
+                                                         uint32_t* __restrict__ head, uint32_t* __restrict__ tail) {
+  constexpr uint32_t DH = head_dwords(C), DT = tail_dwords(IDX);
+  constexpr uint32_t SH = staged_head_units(C), ST = staged_tail_units(IDX), SU = SH + ST;
+  extern __shared__ uint4 srec[];                // [kSplitRecs][SU]
+  __shared__ uint32_t cur[kMaxSub], cnt[kMaxSub], pre[kMaxSub];
+  const uint32_t sidx = blockIdx.x;
+  const uint32_t sx = sidx % g.sX, sy = sidx / g.sX;
+  const uint32_t nsub = g.SW * g.SH;
+  const uint32_t beg = offsets1[sidx * g.NX], end = offsets1[(sidx + 1) * g.NX];
+  const uint32_t lTWs = g.lTW + g.lSW;  // super-tile width in pixels is 2^lTWs
+  if (threadIdx.x < nsub) {
+    const uint32_t j = threadIdx.x;
+    const uint32_t tx = (sx << g.lSW) + (j & (g.SW - 1)), ty = (sy << g.lSH) + (j >> g.lSW);
+    cur[j] = (tx < g.tilesX && ty < g.tilesY) ? offsets[(ty * g.tilesX + tx) * g.NX] : 0u;
+  }
+  for (uint32_t c0 = beg; c0 < end; c0 += kSplitRecs) {
+    if (threadIdx.x < nsub) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    uint32_t hw[kSplitPer][DH], tw[kSplitPer][DT], sub[kSplitPer], rank[kSplitPer];
+#pragma unroll
+    for (uint32_t k = 0; k < kSplitPer; ++k) {
+      const uint32_t i = c0 + k * kSplitThreads + threadIdx.x;
+      sub[k] = 0xffffffffu;
+      if (i < end) {
+#pragma unroll
+        for (uint32_t w = 0; w < DH; ++w) hw[k][w] = head1[(uint64_t)i * DH + w];
+#pragma unroll
+        for (uint32_t w = 0; w < DT; ++w) tw[k][w] = tail1[(uint64_t)i * DT + w];
+        const uint32_t loc = hw[k][0];  // pixel within the super-tile
+        const uint32_t lx = loc & ((1u << lTWs) - 1), ly = loc >> lTWs;
+        sub[k] = ((ly >> g.lTH) << g.lSW) + (lx >> g.lTW);
+        hw[k][0] = ((ly & (g.TH - 1)) << g.lTW) + (lx & (g.TW - 1));  // pixel within the tile
+        rank[k] = atomicAdd(&cnt[sub[k]], 1u);
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t run = 0;
+      for (uint32_t j = 0; j < nsub; ++j) {
+        pre[j] = run;
+        run += cnt[j];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t k = 0; k < kSplitPer; ++k) {
+      if (sub[k] == 0xffffffffu) continue;
+      uint32_t h4[4 * SH], t4[4 * ST];
+#pragma unroll
+      for (uint32_t w = 0; w < 4 * SH; ++w) h4[w] = w < DH ? hw[k][w] : cur[sub[k]] + rank[k];
+#pragma unroll
+      for (uint32_t w = 0; w < 4 * ST; ++w) t4[w] = w < DT ? tw[k][w] : 0u;
+      uint4* d = srec + (size_t)(pre[sub[k]] + rank[k]) * SU;
+#pragma unroll
+      for (uint32_t u = 0; u < SH; ++u) d[u] = make_uint4(h4[4 * u], h4[4 * u + 1], h4[4 * u + 2], h4[4 * u + 3]);
+#pragma unroll
+      for (uint32_t u = 0; u < ST; ++u) d[SH + u] = make_uint4(t4[4 * u], t4[4 * u + 1], t4[4 * u + 2], t4[4 * u + 3]);
+    }
+    __syncthreads();
+    const uint32_t ns = std::min(kSplitRecs, end - c0);
+    for (uint32_t q = threadIdx.x; q < ns; q += kSplitThreads) {
+      const uint4* r = srec + (size_t)q * SU;
+      uint32_t h4[4 * SH], t4[4 * ST];
+#pragma unroll
+      for (uint32_t u = 0; u < SH; ++u) {
+        const uint4 v = r[u];
+        h4[4 * u] = v.x; h4[4 * u + 1] = v.y; h4[4 * u + 2] = v.z; h4[4 * u + 3] = v.w;
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < ST; ++u) {
+        const uint4 v = r[SH + u];
+        t4[4 * u] = v.x; t4[4 * u + 1] = v.y; t4[4 * u + 2] = v.z; t4[4 * u + 3] = v.w;
+      }
+      const uint64_t slot = h4[DH];
+      Words<DH> hh;
+#pragma unroll
+      for (uint32_t w = 0; w < DH; ++w) hh.w[w] = h4[w];
+      Words<DT> tt;
+#pragma unroll
+      for (uint32_t w = 0; w < DT; ++w) tt.w[w] = t4[w];
+      *(Words<DH>*)(head + slot * DH) = hh;
+      *(Words<DT>*)(tail + slot * DT) = tt;
+    }
+    __syncthreads();
+    if (threadIdx.x < nsub) cur[threadIdx.x] += cnt[threadIdx.x];
+  }
+}
+
 static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
 template <int C, bool IDX, int PER>
@@ -734,7 +788,7 @@ static hipError_t launch_scatter_t(const Geom& g, const wt_fragments& f, int vec
     uint32_t stage = g.chunk;
     while (stage > 256 && (size_t)stage * SU * 16 + 8ull * g.rb > budget) stage >>= 1;
     const size_t lds = (size_t)stage * SU * 16 + 8ull * g.rb;
-    auto k = g.rb < g.ntiles ? k_scatter_ranged<C, IDX, THREADS, PER> : k_scatter_staged<C, IDX, THREADS, PER>;
+    auto k = k_scatter_staged<C, IDX, THREADS, PER>;
     if (lds > 65536) {
       hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return e;
@@ -787,7 +841,16 @@ hipError_t launch_bin_count(const Geom& g, const wt_fragments& f, void* ws, cons
     }
   }
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, counts, g, offsets, cursors,
-                     (uint32_t*)(b + l.order));
+                     (uint32_t*)(b + l.order), 1);
+  if (g.two) {
+    // first level: per-class super-tile counts, and their segments and cursors
+    const Geom gs = super_geom(g);
+    uint32_t* counts1 = (uint32_t*)(b + l.counts1);
+    const uint32_t n1 = g.NX * g.nsuper;
+    hipLaunchKernelGGL(k_super_counts, dim3((n1 + 255) / 256), dim3(256), 0, s, counts, g, counts1);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, counts1, gs, (uint32_t*)(b + l.offsets1),
+                       (uint32_t*)(b + l.cursors1), (uint32_t*)(b + l.order1), 0);
+  }
   return hipGetLastError();
 }
 
@@ -802,11 +865,43 @@ hipError_t launch_bin_scatter(const Geom& g, const wt_fragments& f, void* ws, co
   if (F == 0) return hipSuccess;
   const uint32_t nchunks = (uint32_t)(((uint64_t)F + g.chunk - 1) / g.chunk);
   const int vec = aligned16(f.pixel) && aligned16(f.depth) && aligned16(f.alpha) && aligned16(f.rgb);
+  if (!g.two) {
+    if (g.C == 1)
+      return record_index ? launch_scatter<1, true>(g, f, vec, cursors, head, tail, dropped, nchunks, s)
+                          : launch_scatter<1, false>(g, f, vec, cursors, head, tail, dropped, nchunks, s);
+    return record_index ? launch_scatter<3, true>(g, f, vec, cursors, head, tail, dropped, nchunks, s)
+                        : launch_scatter<3, false>(g, f, vec, cursors, head, tail, dropped, nchunks, s);
+  }
+  // two levels: the stream into super-tiles (first-level arrays), then each super-tile into its tiles
+  const Geom gs = super_geom(g);
+  uint32_t* cursors1 = (uint32_t*)(b + l.cursors1);
+  uint32_t* head1 = (uint32_t*)(b + l.heads1);
+  uint32_t* tail1 = (uint32_t*)(b + l.tails1);
+  const uint32_t* offsets1 = (const uint32_t*)(b + l.offsets1);
+  const uint32_t* offsets = (const uint32_t*)(b + l.offsets);
+  hipError_t e;
   if (g.C == 1)
-    return record_index ? launch_scatter<1, true>(g, f, vec, cursors, head, tail, dropped, nchunks, s)
-                        : launch_scatter<1, false>(g, f, vec, cursors, head, tail, dropped, nchunks, s);
-  return record_index ? launch_scatter<3, true>(g, f, vec, cursors, head, tail, dropped, nchunks, s)
-                      : launch_scatter<3, false>(g, f, vec, cursors, head, tail, dropped, nchunks, s);
+    e = record_index ? launch_scatter<1, true>(gs, f, vec, cursors1, head1, tail1, dropped, nchunks, s)
+                     : launch_scatter<1, false>(gs, f, vec, cursors1, head1, tail1, dropped, nchunks, s);
+  else
+    e = record_index ? launch_scatter<3, true>(gs, f, vec, cursors1, head1, tail1, dropped, nchunks, s)
+                     : launch_scatter<3, false>(gs, f, vec, cursors1, head1, tail1, dropped, nchunks, s);
+  if (e != hipSuccess) return e;
+  auto split = [&](auto kern, uint32_t su) -> hipError_t {
+    const size_t lds = (size_t)kSplitRecs * su * 16;
+    if (lds > 65536) {
+      hipError_t e2 = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e2 != hipSuccess) return e2;
+    }
+    hipLaunchKernelGGL(kern, dim3(g.nsuper), dim3(kSplitThreads), lds, s, g, offsets1, offsets, head1, tail1, head,
+                       tail);
+    return hipGetLastError();
+  };
+  if (g.C == 1)
+    return record_index ? split(k_split<1, true>, staged_head_units(1) + staged_tail_units(true))
+                        : split(k_split<1, false>, staged_head_units(1) + staged_tail_units(false));
+  return record_index ? split(k_split<3, true>, staged_head_units(3) + staged_tail_units(true))
+                      : split(k_split<3, false>, staged_head_units(3) + staged_tail_units(false));
 }
 
 hipError_t launch_bin(const Geom& g, const wt_fragments& f, void* ws, const Layout& l, bool record_index,

@@ -14,9 +14,11 @@ namespace wt {
 // partial cache lines of a frontier are filled inside a single L2 before they are written back.
 constexpr uint32_t kClasses = 8;
 constexpr uint32_t kPer = 8;               // fragments per scatter thread (held in registers)
-constexpr uint32_t kMaxLdsBins = 8192;     // tiles one scatter tile table holds (per pass of the staged binning)
-constexpr uint32_t kMaxRanges = 8;         // passes of tile ranges; beyond kMaxRanges * kMaxLdsBins: global path
+constexpr uint32_t kMaxLdsBins = 8192;     // bins one scatter table holds (super-tiles of a two-level binning)
 constexpr uint32_t kMaxHistBins = 36864;   // tiles one histogram table holds (144 KB of LDS)
+constexpr uint32_t kTwoLevelTiles = 4096;  // frames with more tiles are binned in two levels (super-tiles, then tiles)
+constexpr uint32_t kMaxSupers = 2048;      // super-tiles of the first level at most
+constexpr uint32_t kMaxSub = 64;           // tiles per super-tile at most
 constexpr uint32_t kLdsBytes = 160 * 1024; // LDS of one CDNA4 compute unit (also the per-workgroup limit)
 constexpr uint32_t kMaxTilePx = 2048;
 constexpr uint32_t kTileThreads = 1024;    // workgroup size of the per-tile kernels
@@ -59,7 +61,9 @@ struct Geom {
   uint32_t tilesX, tilesY, ntiles, tile_px;
   uint32_t NX;           // write-frontier classes (kClasses, or 1 when the tile count is large)
   uint32_t lds_bins;     // 1: LDS-staged scatter; 0: one global atomic per fragment
-  uint32_t rb;           // tiles per scatter table (range): ceil(ntiles / ranges)
+  uint32_t rb;           // bins of the scatter table (tiles of a one-level binning)
+  uint32_t two;          // 1: two-level binning (super-tiles of SW x SH tiles, then tiles)
+  uint32_t SW, SH, lSW, lSH, sX, sY, nsuper;
   uint32_t hrb;          // tiles per histogram table (range)
   uint32_t AW;           // accum floats per pixel in global memory: 4 (C = 1) or 8 (C = 3)
   uint32_t AL;           // accumulation floats per pixel in LDS: 4 (C = 1) or 6 (C = 3)
@@ -87,6 +91,13 @@ struct Layout {
   size_t order;    // uint32 [ntiles]: tiles by descending fragment count (heaviest first)
   size_t heads;    // uint32 [cap][head_dwords(C)]
   size_t tails;    // uint32 [cap][tail_dwords(true)]
+  // two-level binning only: the first level over super-tiles
+  size_t counts1;  // uint32 [NX][nsuper]
+  size_t offsets1; // uint32 [nsuper * NX + 1]
+  size_t cursors1; // uint32 [NX][nsuper]
+  size_t order1;   // uint32 [nsuper] (unused order of the super-tiles)
+  size_t heads1;   // uint32 [cap][head_dwords(C)]: tile-local pixel replaced by the super-tile-local pixel
+  size_t tails1;   // uint32 [cap][tail_dwords(true)]
   size_t total;    // bytes
   uint64_t cap;    // fragment capacity
 };
@@ -102,6 +113,8 @@ struct Binned {
 
 // backward = true picks tiles for the gradient kernel, which holds cell values and their adjoints.
 Geom make_geom(const wt_frame_desc& d, bool backward = false);
+// Geometry of the first binning level: super-tiles of g.SW x g.SH tiles as the bins, same chunking as g.
+Geom super_geom(const Geom& g);
 Layout make_layout(const Geom& g, uint64_t cap);
 uint64_t capacity_for(const Geom& g, size_t ws_bytes);
 size_t lds_tile_bytes(const Geom& g, bool with_accum);
