@@ -225,10 +225,13 @@ def request_footprint(width, height, rank, channels, dtype, count, stream_bytes=
     coefficient array and the composite."""
     from . import wt as _wt
     spec = _wt.FrameSpec(width, height, rank, channels, dtype)
-    sbytes = {"f32": 4, "f16": 2, "bf16": 2}[dtype]
+    sbytes = {"f32": 4, "f16": 2, "bf16": 2, "e5b9g9r9": 4}[dtype]
     ws = _wt.workspace_bytes(spec, max(count, 1))
     fr = count * (4 + 4 + 4 * channels + 12) if stream_bytes else 0
-    return fr + ws + spec.pixels * channels * spec.M * sbytes + spec.pixels * 12
+    coeff_elems = 1
+    for d in spec.coeff_shape():
+        coeff_elems *= d
+    return fr + ws + coeff_elems * sbytes + spec.pixels * 12
 
 
 class _WsView:
