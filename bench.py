@@ -34,7 +34,7 @@ CSRC = os.path.join(ROOT, "paper_2201_00094_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_smoke1080p.json")
 # short kernel names used in the JSON line -> prefix of the demangled name in rocprofv3's output
 KERNEL_PREFIX = {"k_scatter_staged": "void wt::k_scatter_staged<", "k_render": "void wt::k_render<",
-                 "k_hist_lds": "wt::k_hist_lds("}
+                 "k_hist_lds": "void wt::k_hist_lds<"}
 
 
 def sources_digest():
