@@ -404,16 +404,28 @@ __global__ __launch_bounds__(256) void k_super_counts(const uint32_t* __restrict
 // ------------------------------------------------------------------------------------------------ scatter
 
 
-// The fragment stream is read once: non-temporal loads keep it from evicting the partly written record lines
-// that the scatter's L2 is completing (measured: 17% less HBM write traffic and 11% less time in the scatter).
+// The fragment stream is read once. With two scatter workgroups per compute unit (PER = 4), non-temporal loads
+// keep it from evicting the partly written record lines that the L2 is completing (measured on the smoke frame:
+// 17% less HBM write traffic, scatter 1.96 -> 1.68 ms); with one workgroup per compute unit (PER = 8) they
+// made the scatter slower (2.05 -> 2.41 ms), so there the loads stay ordinary.
 typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+template <bool NT>
 __device__ __forceinline__ uint4 load_stream_u4(const uint32_t* p) {
-  const u32x4_t v = __builtin_nontemporal_load((const u32x4_t*)p);
-  return make_uint4(v.x, v.y, v.z, v.w);
+  if constexpr (NT) {
+    const u32x4_t v = __builtin_nontemporal_load((const u32x4_t*)p);
+    return make_uint4(v.x, v.y, v.z, v.w);
+  } else {
+    return *(const uint4*)p;
+  }
 }
+template <bool NT>
 __device__ __forceinline__ float4 load_stream_f4(const float* p) {
-  const u32x4_t v = __builtin_nontemporal_load((const u32x4_t*)p);
-  return make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), __uint_as_float(v.w));
+  if constexpr (NT) {
+    const u32x4_t v = __builtin_nontemporal_load((const u32x4_t*)p);
+    return make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z), __uint_as_float(v.w));
+  } else {
+    return *(const float4*)p;
+  }
 }
 
 // One chunk's fragments, held in registers by the thread that loaded them.
@@ -435,23 +447,23 @@ __device__ __forceinline__ void load_chunk(const wt_fragments& f, uint32_t base,
     // pixel ids first: the tile count needs only them, and the other loads stay in flight meanwhile
 #pragma unroll
     for (uint32_t v = 0; v < kPer / 4; ++v) {
-      const uint4 p4 = load_stream_u4(f.pixel + (uint64_t)base + i0 + 4 * v);
+      const uint4 p4 = load_stream_u4<PER == 4>(f.pixel + (uint64_t)base + i0 + 4 * v);
       r.p[4 * v + 0] = p4.x; r.p[4 * v + 1] = p4.y; r.p[4 * v + 2] = p4.z; r.p[4 * v + 3] = p4.w;
     }
 #pragma unroll
     for (uint32_t v = 0; v < kPer / 4; ++v) {
       const uint64_t i = (uint64_t)base + i0 + 4 * v;
-      const float4 x4 = load_stream_f4(f.depth + i);
+      const float4 x4 = load_stream_f4<PER == 4>(f.depth + i);
       r.x[4 * v + 0] = x4.x; r.x[4 * v + 1] = x4.y; r.x[4 * v + 2] = x4.z; r.x[4 * v + 3] = x4.w;
 #pragma unroll
       for (int q = 0; q < C; ++q) {
-        const float4 a4 = load_stream_f4(f.alpha + C * i + 4 * q);
+        const float4 a4 = load_stream_f4<PER == 4>(f.alpha + C * i + 4 * q);
         r.a[4 * C * v + 4 * q + 0] = a4.x; r.a[4 * C * v + 4 * q + 1] = a4.y;
         r.a[4 * C * v + 4 * q + 2] = a4.z; r.a[4 * C * v + 4 * q + 3] = a4.w;
       }
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
-        const float4 c4 = load_stream_f4(f.rgb + 3 * i + 4 * q);
+        const float4 c4 = load_stream_f4<PER == 4>(f.rgb + 3 * i + 4 * q);
         r.c[12 * v + 4 * q + 0] = c4.x; r.c[12 * v + 4 * q + 1] = c4.y;
         r.c[12 * v + 4 * q + 2] = c4.z; r.c[12 * v + 4 * q + 3] = c4.w;
       }
