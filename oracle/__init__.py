@@ -9,6 +9,8 @@ documented at the C definitions:
 
 * :func:`resolve`  -- build (section 2.3.1), cell averages (2.3), interpolation (2.3.2), visibility-weighted
   shading (2.1 step 3, the compositing sum of 2.2) and the composite over a constant background (2.1 step 4).
+* :func:`shade_prev` -- the one-pass variant: shading against the previous frame's coefficients (the
+  future-work proposal of the paper's closing section).
 * :func:`abuffer`  -- the exact sorted A-buffer the method approximates (visibility function of 1.2).
 * :func:`backward` -- gradient of the resolve with respect to alpha and colour (chain rule through the steps).
 * :func:`coeffs_one`, :func:`cells_one`, :func:`reconstruct`, :func:`Psi`, :func:`psi` -- the per-pixel pieces.
@@ -50,6 +52,9 @@ def _load():
     lib.orc_resolve.restype = C.c_int
     lib.orc_resolve.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64, vp, vp, vp, vp, vp, vp,
                                 C.c_int, C.c_int, vp, vp, vp, vp, vp, vp, vp, C.c_int]
+    lib.orc_shade_prev.restype = C.c_int
+    lib.orc_shade_prev.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64, vp, vp, vp, vp, vp, vp,
+                                   vp, vp, C.c_uint64, vp, vp, vp, vp, vp, C.c_int]
     lib.orc_abuffer.restype = C.c_int
     lib.orc_abuffer.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64, vp, vp, vp, vp, vp, vp, C.c_int, vp, vp,
                                 vp, C.c_int]
@@ -133,6 +138,43 @@ def resolve(width, height, rank, pixel, depth, alpha, rgb, bg=(0.0, 0.0, 0.0), c
                          _ptr(res["suma"]), _ptr(res["out"]), _ptr(res["vis"]), C.byref(dropped), int(threads))
     if rc != 0:
         raise RuntimeError("orc_resolve failed with %d" % rc)
+    out = {k: v for k, v in res.items() if v is not None}
+    out["dropped"] = int(dropped.value)
+    return out
+
+
+def shade_prev(width, height, rank, pixel, depth, alpha, rgb, prev=None, prev_pixel=None, bg=(0.0, 0.0, 0.0),
+               channels=1, mask=None, want=("accum", "suma", "out", "vis"), threads=0):
+    """One-pass shading against the previous frame's coefficients (the single-pass variant the paper proposes
+    as future work): each pixel's fragments see the visibility reconstructed from ``prev`` [Pp, C, M] (stored
+    values, FP64) at the pixel ``prev_pixel[p]`` (identity when None; entries >= Pp, or ``prev`` None, mean no
+    history: visibility 1). The background weight is exp(-sum a) of this frame's fragments. Returns the arrays of
+    :func:`resolve` named in ``want`` (accum, suma, out, vis) and ``dropped``."""
+    lib = _load()
+    pixel, depth, alpha, rgb, F = _stream(pixel, depth, alpha, rgb, channels)
+    P = int(width) * int(height)
+    M = 1 << (int(rank) + 1)
+    pv, pp, npp = None, None, 0
+    if prev is not None:
+        pv = np.ascontiguousarray(prev, dtype=np.float64).reshape(-1, channels, M)
+        npp = pv.shape[0]
+    if prev_pixel is not None:
+        pp = np.ascontiguousarray(prev_pixel, dtype=np.uint32).reshape(-1)
+        if pp.shape[0] != P:
+            raise ValueError("prev_pixel must hold one entry per pixel")
+    res = {}
+    res["accum"] = np.zeros((P, 3)) if "accum" in want else None
+    res["suma"] = np.zeros((P, channels)) if "suma" in want else None
+    res["out"] = np.zeros((P, 3)) if "out" in want else None
+    res["vis"] = np.full((F, channels), np.nan) if "vis" in want else None
+    m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    bgv = np.ascontiguousarray(bg, dtype=np.float64)
+    dropped = C.c_uint64(0)
+    rc = lib.orc_shade_prev(width, height, rank, channels, F, _ptr(pixel), _ptr(depth), _ptr(alpha), _ptr(rgb),
+                            _ptr(bgv), _ptr(m), _ptr(pv), _ptr(pp), npp, _ptr(res["accum"]), _ptr(res["suma"]),
+                            _ptr(res["out"]), _ptr(res["vis"]), C.byref(dropped), int(threads))
+    if rc != 0:
+        raise RuntimeError("orc_shade_prev failed with %d" % rc)
     out = {k: v for k, v in res.items() if v is not None}
     out["dropped"] = int(dropped.value)
     return out

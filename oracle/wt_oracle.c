@@ -431,6 +431,109 @@ int orc_resolve(uint32_t width, uint32_t height, uint32_t rank, uint32_t channel
 }
 
 /* ------------------------------------------------------------------------------------------------ */
+/* Single pass against the previous frame's coefficients                                            */
+/* ------------------------------------------------------------------------------------------------ */
+
+/*
+ * orc_shade_prev: the one-pass variant proposed as future work in the paper's closing section: the frame's
+ * fragments are shaded in the same pass that builds its coefficients, so the visibility they see is
+ * reconstructed from the PREVIOUS frame's coefficient buffer, read at each pixel's reprojected position.
+ *
+ *   prev        [Pp][C][M] the previous frame's stored coefficients (values as stored), or NULL: no history
+ *   prev_pixel  [P] pixel of the previous buffer that pixel p reads (NULL: p itself); an entry >= Pp means
+ *               that p has no history
+ *   out, accum, suma, vis as in orc_resolve.
+ *
+ * Per pixel: cells of the previous coefficients (section 2.3; all zero without history), then for every
+ * fragment v = exp(-A~_prev(x)) by the interpolation of section 2.3.2 and S += alpha c v (2.1 step 3). The
+ * background weight uses this frame's own absorbance total, exp(-sum a) (2.1 step 4 with the reading taken in
+ * orc_resolve): a plain sum over the frame's fragments that the single pass has in hand. Readings: the paper
+ * leaves the reprojection to the renderer (here an integer pixel map supplied by the caller, identity by
+ * default), and a pixel with no history (outside the guard band, disoccluded) sees nothing in front of it.
+ * Depth is used as given (no per-pixel bounds: the previous buffer was built over the previous frame's range).
+ */
+int orc_shade_prev(uint32_t width, uint32_t height, uint32_t rank, uint32_t channels, uint64_t count,
+                   const uint32_t* pixel, const float* depth, const float* alpha, const float* rgb, const double* bg,
+                   const uint8_t* mask, const double* prev, const uint32_t* prev_pixel, uint64_t prev_pixels,
+                   double* accum, double* suma, double* out, double* vis, uint64_t* dropped, int threads) {
+  if (rank > 12 || (channels != 1 && channels != 3) || (count && (!pixel || !depth || !alpha || !rgb)) || !bg)
+    return ORC_EINVAL;
+  orc_stream s = {width, height, rank, channels, count, pixel, depth, alpha, rgb};
+  uint64_t P = (uint64_t)width * height;
+  int M = 1 << (rank + 1);
+  int C = (int)channels;
+  uint64_t* start;
+  uint32_t* idx;
+  uint64_t nd;
+  int rc = group_by_pixel(&s, mask, &start, &idx, &nd);
+  if (rc) return rc;
+  if (dropped) *dropped = nd;
+  if (vis)
+    for (uint64_t i = 0; i < count; ++i)
+      if (!frag_valid(&s, i))
+        for (int c = 0; c < C; ++c) vis[i * C + c] = NAN;
+  uint64_t kmax = max_run(start, P);
+#ifdef _OPENMP
+  if (threads > 0) omp_set_num_threads(threads);
+#endif
+  int fail = 0;
+#pragma omp parallel
+  {
+    uint32_t* order = (uint32_t*)malloc(sizeof(uint32_t) * (kmax ? kmax : 1));
+    double* xs = (double*)malloc(sizeof(double) * (kmax ? kmax : 1));
+    double* ce = (double*)malloc(sizeof(double) * M);
+    if (!order || !xs || !ce) {
+#pragma omp atomic write
+      fail = 1;
+    } else {
+      g_sort_stream = &s;
+#pragma omp for schedule(dynamic, 256)
+      for (int64_t p = 0; p < (int64_t)P; ++p) {
+        if (mask && !mask[p]) continue;
+        uint64_t k = start[p + 1] - start[p];
+        memcpy(order, idx + start[p], sizeof(uint32_t) * k);
+        qsort(order, k, sizeof(uint32_t), cmp_frag);
+        pixel_depths(depth, order, k, 0, xs);
+        const uint64_t src = prev_pixel ? prev_pixel[p] : (uint64_t)p;
+        const int history = prev != NULL && src < prev_pixels;
+        double S[3] = {0.0, 0.0, 0.0};
+        double sa[3] = {0.0, 0.0, 0.0};
+        for (int c = 0; c < C; ++c) {
+          if (history)
+            orc_cells_one((int)rank, prev + (src * C + c) * M, ce);
+          else
+            memset(ce, 0, sizeof(double) * M);
+          for (uint64_t r = 0; r < k; ++r) {
+            uint32_t i = order[r];
+            double v = exp(-orc_reconstruct((int)rank, ce, xs[r]));
+            double al = alpha[(uint64_t)i * C + c];
+            double au = orc_alpha_used(al);
+            if (vis) vis[(uint64_t)i * C + c] = v;
+            sa[c] += orc_absorbance(al);
+            if (C == 3) {
+              S[c] += au * rgb[(uint64_t)i * 3 + c] * v;
+            } else {
+              for (int q = 0; q < 3; ++q) S[q] += au * rgb[(uint64_t)i * 3 + q] * v;
+            }
+          }
+        }
+        for (int q = 0; q < 3; ++q) {
+          int c = (C == 3) ? q : 0;
+          if (accum) accum[p * 3 + q] = S[q];
+          if (out) out[p * 3 + q] = S[q] + bg[q] * exp(-sa[c]);
+        }
+        if (suma)
+          for (int c = 0; c < C; ++c) suma[p * C + c] = sa[c];
+      }
+    }
+    free(order); free(xs); free(ce);
+  }
+  free(start);
+  free(idx);
+  return fail ? ORC_ENOMEM : ORC_OK;
+}
+
+/* ------------------------------------------------------------------------------------------------ */
 /* Exact A-buffer (the reference the method approximates)                                           */
 /* ------------------------------------------------------------------------------------------------ */
 

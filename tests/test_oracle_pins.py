@@ -546,6 +546,91 @@ def test_tight_depth_single_fragment(orc):
     np.testing.assert_allclose(t["out"], ref, rtol=1e-12, atol=1e-15)
 
 
+# ---------------------------------------------------------------------------------------------- one pass, previous frame
+def _layer_frame(rng, P, M, channels, on_grid):
+    """One fragment per pixel: depth on the cell grid (j0/M) or at an exact offset inside a cell ((j + t)/M)."""
+    j = rng.integers(0, M, P)
+    if on_grid:
+        t = np.zeros(P)
+    else:
+        t = rng.choice([0.0, 0.25, 0.5, 0.75], P)
+    dep = ((j + t) / M).astype(np.float32)
+    alpha = rng.uniform(0.1, 0.8, (P, channels) if channels == 3 else P).astype(np.float32)
+    rgb = rng.random((P, 3), dtype=np.float32)
+    return np.arange(P, dtype=np.uint32), dep, alpha, rgb, j, t
+
+
+@pytest.mark.parametrize("channels", [1, 3])
+def test_shade_prev_single_previous_layer_closed_form(orc, channels):
+    """The previous frame holds one layer of absorbance a0 on the grid at z0 = j0/M. Its Haar expansion is exact,
+    so the cell averages are a0 from cell j0 on and 0 before it, and the interpolation of section 2.3.2 gives
+    A~(x) = 0 before cell j0, t a0 inside it (x = (j0 + t)/M) and a0 beyond it. Checked for the identity map and
+    for a shifted map with pixels that have no history."""
+    rng = np.random.default_rng(60 + channels)
+    W, H, rank = 6, 5, 3
+    P, M = W * H, 16
+    bg = (0.3, 0.5, 0.7)
+    pp, dp, ap, rp, j0, _ = _layer_frame(rng, P, M, channels, True)
+    prev = orc.resolve(W, H, rank, pp, dp, ap, rp, channels=channels, want=("coeffs",))["coeffs"]
+    pc, dc, ac, rc, jc, tc = _layer_frame(rng, P, M, channels, False)
+    a0 = -np.log1p(-ap.astype(np.float64)).reshape(P, channels)
+    acur = ac.astype(np.float64).reshape(P, channels)
+    shift = (np.arange(P) + 7) % P
+    nohist = np.zeros(P, bool)
+    nohist[[3, 11, 29]] = True
+    maps = [(None, np.arange(P), np.zeros(P, bool)),
+            (np.where(nohist, P + 5, shift).astype(np.uint32), shift, nohist)]
+    for pmap, src, none in maps:
+        At = np.where((jc < j0[src])[:, None], 0.0,
+                      np.where((jc == j0[src])[:, None], tc[:, None] * a0[src], a0[src]))
+        At[none] = 0.0
+        v = np.exp(-At)
+        if channels == 1:
+            ref = acur * rc * v + np.array(bg)[None, :] * np.exp(np.log1p(-acur))
+        else:
+            ref = acur * rc * v + np.array(bg)[None, :] * (1.0 - acur)
+        got = orc.shade_prev(W, H, rank, pc, dc, ac, rc, prev=prev, prev_pixel=pmap, bg=bg, channels=channels)
+        np.testing.assert_allclose(got["vis"], v, rtol=1e-13, atol=1e-15)
+        np.testing.assert_allclose(got["out"], ref, rtol=1e-12, atol=1e-15)
+
+
+@pytest.mark.parametrize("channels,storage", [(1, "exact"), (1, "f16"), (3, "bf16"), (3, "e5b9g9r9")])
+def test_shade_prev_static_scene_is_the_two_pass_result(orc, channels, storage):
+    """A scene that does not change between frames: shading against the previous frame's (stored) coefficients
+    is the two-pass resolve with coefficients at that storage precision."""
+    f = synth.frame_c1(seed=61, width=11, height=7, mean=9.0) if channels == 1 else \
+        synth.frame_c3(seed=61, width=11, height=7, particles=6.0)
+    r = orc.resolve(f.width, f.height, 3, f.pixel, f.depth, f.alpha, f.rgb, bg=f.bg, channels=channels,
+                    want=("coeffs", "out", "vis", "suma"), storage=storage)
+    s = orc.shade_prev(f.width, f.height, 3, f.pixel, f.depth, f.alpha, f.rgb, prev=r["coeffs"], bg=f.bg,
+                       channels=channels)
+    np.testing.assert_allclose(s["vis"], r["vis"], rtol=1e-14, atol=0)
+    np.testing.assert_allclose(s["suma"], r["suma"], rtol=1e-14, atol=0)
+    np.testing.assert_allclose(s["out"], r["out"], rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("channels", [1, 3])
+def test_shade_prev_without_history_sees_nothing_in_front(orc, channels):
+    """No previous buffer (or every pixel mapped outside it): v = 1, out = sum alpha c + bg prod(1 - alpha)."""
+    f = synth.frame_c1(seed=62, width=9, height=6, mean=6.0) if channels == 1 else \
+        synth.frame_c3(seed=62, width=9, height=6, particles=4.0)
+    P = f.pixels
+    al = np.clip(f.alpha.astype(np.float64).reshape(f.count, channels), 0.0, 1.0 - 2.0 ** -24)
+    S = np.zeros((P, 3))
+    T = np.ones((P, channels))
+    for i in range(f.count):
+        p = f.pixel[i]
+        for q in range(3):
+            S[p, q] += al[i, q if channels == 3 else 0] * f.rgb[i, q]
+        T[p] *= 1.0 - al[i]
+    ref = S + np.array(f.bg)[None, :] * (T if channels == 3 else T[:, [0, 0, 0]])
+    prev = np.full((P, channels, 16), -0.5)
+    for kw in ({}, {"prev": prev, "prev_pixel": np.full(P, P, np.uint32)}):
+        got = orc.shade_prev(f.width, f.height, 3, f.pixel, f.depth, f.alpha, f.rgb, bg=f.bg, channels=channels, **kw)
+        assert (got["vis"] == 1.0).all()
+        np.testing.assert_allclose(got["out"], ref, rtol=1e-12, atol=1e-15)
+
+
 # ---------------------------------------------------------------------------------------------- generators
 def test_generators_are_seeded():
     a = synth.frame_c1(seed=7, width=16, height=16)
