@@ -34,7 +34,7 @@ CSRC = os.path.join(ROOT, "paper_2201_00094_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_smoke1080p.json")
 # short kernel names used in the JSON line -> prefix of the demangled name in rocprofv3's output
 KERNEL_PREFIX = {"k_scatter_staged": "void wt::k_scatter_staged<", "k_render": "void wt::k_render<",
-                 "k_hist_lds": "void wt::k_hist_lds<"}
+                 "k_hist_lds": "void wt::k_hist_lds<", "k_render_temporal": "void wt::k_render_temporal<"}
 
 
 def sources_digest():
@@ -48,7 +48,13 @@ def sources_digest():
     return h.hexdigest()
 
 
-def measured_traffic(kernel, rank, dtype):
+def workload_key(args):
+    """Key of a smoke-frame configuration in the traffic summary."""
+    return "r%d_%s" % (args.rank, args.dtype) + ("_tight" if args.tight else "") + \
+        ("_temporal" if args.temporal else "")
+
+
+def measured_traffic(kernel, key):
     """HBM bytes per launch of ``kernel`` from the committed counter summary, or None when the summary was taken
     on other kernel sources or another workload."""
     try:
@@ -58,7 +64,7 @@ def measured_traffic(kernel, rank, dtype):
         return None
     if t.get("sources_sha256") != sources_digest():
         return None
-    return t.get("workloads", {}).get("r%d_%s" % (rank, dtype), {}).get(kernel)
+    return t.get("workloads", {}).get(key, {}).get(kernel)
 
 
 def algorithmic_bytes(F, P, C, coeff_px):
@@ -76,6 +82,13 @@ def render_kernel_bytes(F, P, C, coeff_px):
     (tile-local pixel, depth, alpha: 8 + 4C B; plus rgb: 20 + 4C B), the coefficient store and the composite
     store (12 B/pixel); the accumulation never leaves LDS."""
     return F * ((8 + 4 * C) + (20 + 4 * C)) + P * (coeff_px + 12)
+
+
+def temporal_bytes(F, P, C, coeff_px):
+    """Algorithmic bytes of the one-pass render against the previous frame (path and kernel alike): each
+    fragment read once (tile-local pixel, depth, alpha, rgb: 20 + 4C B), the previous coefficients read and this
+    frame's written (2 x coeff_px B/pixel), the composite written (12 B/pixel)."""
+    return F * (20 + 4 * C) + P * (2 * coeff_px + 12)
 
 
 def scatter_kernel_bytes(F, C):
@@ -121,6 +134,8 @@ def main():
                          "precision: the glass + particles frame (3840x2160, three channels) with every coefficient "
                          "storage, timed, with errors against the FP64 oracle and the exact A-buffer")
     ap.add_argument("--tight", action="store_true", help="per-pixel depth bounds (WT_TIGHT_DEPTH)")
+    ap.add_argument("--temporal", action="store_true",
+                    help="one pass per frame against the previous frame's coefficients (WT_TEMPORAL)")
     ap.add_argument("--workload", default="smoke", choices=("smoke", "glass"),
                     help="frame mode: smoke (1920x1080, one visibility channel; the headline) or glass "
                          "(3840x2160 glass + particles, three visibility channels)")
@@ -163,17 +178,26 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    spec = wt.FrameSpec(f.width, f.height, args.rank, f.channels, args.dtype, args.tight)
+    spec = wt.FrameSpec(f.width, f.height, args.rank, f.channels, args.dtype, args.tight, args.temporal)
     fr = wt.Fragments.from_numpy(f.pixel, f.depth, f.alpha, f.rgb, device=dev)
     ws = wt.Workspace(spec, f.count, device=dev)
-    coeffs = spec.new_coeffs(device=dev)
+    # one-pass mode: this frame's coefficients go to one buffer while the previous frame's are read from the
+    # other; the two swap every frame
+    bufs = [spec.new_coeffs(device=dev), spec.new_coeffs(device=dev) if args.temporal else None]
     out = torch.empty((spec.pixels, 3), dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream()
+
+    def render():
+        if args.temporal:
+            wt.render_temporal_binned(spec, ws, f.bg, out, prev=bufs[1], coeffs=bufs[0], stream=stream)
+            bufs.reverse()
+        else:
+            wt.render_binned(spec, ws, f.bg, out, bufs[0], stream=stream)
 
     def step():
         wt.bin_count(spec, fr, ws, stream=stream)
         wt.bin_scatter(spec, fr, ws, stream=stream)
-        wt.render_binned(spec, ws, f.bg, out, coeffs, stream=stream)
+        render()
 
     for _ in range(args.warmup):
         step()
@@ -193,7 +217,7 @@ def main():
         ev[k][1].record(stream)
         wt.bin_scatter(spec, fr, ws, stream=stream)
         ev[k][2].record(stream)
-        wt.render_binned(spec, ws, f.bg, out, coeffs, stream=stream)
+        render()
         ev[k][3].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -205,11 +229,13 @@ def main():
     ms_per_step = wall * 1e3 / K
     F, P, M, C = f.count, f.pixels, spec.M, f.channels
     coeff_px = 4 * M if args.dtype == "e5b9g9r9" else {"f32": 4, "f16": 2, "bf16": 2}[args.dtype] * C * M
-    b_alg = algorithmic_bytes(F, P, C, coeff_px)
-    kernels = {
-        "k_render": (render_kernel_bytes(F, P, C, coeff_px), float(render_ms.mean())),
-        "k_scatter_staged": (scatter_kernel_bytes(F, C), float(scatter_ms.mean())),
-    }
+    if args.temporal:
+        b_alg = temporal_bytes(F, P, C, coeff_px)
+        kernels = {"k_render_temporal": (temporal_bytes(F, P, C, coeff_px), float(render_ms.mean()))}
+    else:
+        b_alg = algorithmic_bytes(F, P, C, coeff_px)
+        kernels = {"k_render": (render_kernel_bytes(F, P, C, coeff_px), float(render_ms.mean()))}
+    kernels["k_scatter_staged"] = (scatter_kernel_bytes(F, C), float(scatter_ms.mean()))
     dom = max(kernels, key=lambda k: kernels[k][1])
     dom_bytes, dom_ms = kernels[dom]
     dom_gbs = dom_bytes / (dom_ms * 1e-3) / 1e9
@@ -230,8 +256,9 @@ def main():
         "config": {"workload": ("glass + particles 3840x2160, 2-4 glass layers + Poisson(24) particles/px, three "
                                 "visibility channels" if glass else
                                 "smoke 1920x1080, Poisson(64 g) fragments/px") +
-                               " (unsorted stream), rank %d, %s coefficient storage%s" % (
-                                   args.rank, args.dtype, ", per-pixel depth bounds" if args.tight else ""),
+                               " (unsorted stream), rank %d, %s coefficient storage%s%s" % (
+                                   args.rank, args.dtype, ", per-pixel depth bounds" if args.tight else "",
+                                   ", one pass against the previous frame's coefficients" if args.temporal else ""),
                    "width": f.width, "height": f.height, "rank": args.rank, "coeff_dtype": args.dtype,
                    "fragments": F, "seed": args.seed},
         "p50_ms": float(np.percentile(frame_ms, 50)),
@@ -242,7 +269,7 @@ def main():
         "path_hbm_frac": b_alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": dom_gbs, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": dom_gbs / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(dom, args.rank, args.dtype),
+                     "traffic": None if glass else measured_traffic(dom, workload_key(args)),
                      "alg_bytes_per_launch": dom_bytes, "avg_ms": dom_ms},
     }
     if not args.no_cpu_baseline:
@@ -346,7 +373,7 @@ def run_traffic(args):
     gib = float(1 << 30)
     f_scale = gib / (cfetch[copy_name][0] * 1024.0)
     w_scale = gib / (cwrite[copy_name][0] * 1024.0)
-    key = "r%d_%s" % (args.rank, args.dtype)
+    key = workload_key(args)
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
@@ -372,8 +399,9 @@ def run_traffic(args):
         json.dump(t, fh, indent=1, sort_keys=True)
     md = TRAFFIC_FILE[:-5] + "_%s.md" % key
     with open(md, "w") as fh:
-        fh.write("# HBM traffic per launch, smoke 1920x1080, Poisson(64 g) fragments/px, rank %d, %s coefficients\n\n"
-                 % (args.rank, args.dtype))
+        fh.write("# HBM traffic per launch, smoke 1920x1080, Poisson(64 g) fragments/px, rank %d, %s coefficients%s\n\n"
+                 % (args.rank, args.dtype, (", per-pixel depth bounds" if args.tight else "") +
+                    (", one pass against the previous frame" if args.temporal else "")))
         fh.write("Counters: rocprofv3 `--pmc FETCH_SIZE`, then `--pmc WRITE_SIZE`, in separate runs (KiB per dispatch, "
                  "mean over dispatches). Scale: a 1 GiB device copy (`bench.py --mode copy`) reads FETCH_SIZE "
                  "%.0f KiB and WRITE_SIZE %.0f KiB, so FETCH_SIZE is multiplied by %.4f and WRITE_SIZE by %.4f "

@@ -72,6 +72,11 @@ typedef enum { WT_F32 = 0, WT_F16 = 1, WT_BF16 = 2, WT_E5B9G9R9 = 3 } wt_dtype;
  * depth), and the build, evaluate and gradient use x'. zmin and zmax are taken over the fragments one call sees,
  * so with this flag a frame's stream is passed whole to each call (no chunked accumulation). */
 #define WT_TIGHT_DEPTH 1u
+/* WT_TEMPORAL: the frame is rendered in one pass against the previous frame's coefficients
+ * (wt_render_temporal). Screen tiles are sized for that kernel's working set, so a stream binned under a
+ * WT_TEMPORAL description serves wt_render_temporal_binned; the other entry points accept the flag as well (smaller
+ * tiles, same results). Requires rank <= 4 and excludes WT_TIGHT_DEPTH (WT_ERR_UNSUPPORTED). */
+#define WT_TEMPORAL 2u
 
 typedef struct {
   uint32_t width;       /* pixels per row, >= 1 */
@@ -79,7 +84,7 @@ typedef struct {
   uint32_t rank;        /* N in 0..10: levels n = 0..N, M = 2^(N+1) coefficients per channel */
   uint32_t channels;    /* 1 (one visibility for r, g, b) or 3 (per-channel transmittance) */
   uint32_t coeff_dtype; /* wt_dtype */
-  uint32_t flags;       /* 0 or WT_TIGHT_DEPTH */
+  uint32_t flags;       /* 0, WT_TIGHT_DEPTH or WT_TEMPORAL */
 } wt_frame_desc;
 
 typedef struct {
@@ -144,6 +149,33 @@ wt_status wt_render(const wt_frame_desc* desc, const wt_fragments* frags, const 
  * ws_bytes). Writes out[P][3] and, if coeffs is not NULL, the coefficients (both overwritten). */
 wt_status wt_render_binned(const wt_frame_desc* desc, const void* ws, size_t ws_bytes, const float* bg_rgb,
                            void* coeffs, float* out, hipStream_t stream);
+
+/* One-pass render against the previous frame's coefficients: the single-pass variant proposed as future work
+ * in the paper's closing section. The frame's coefficients are built in the same pass that shades its fragments,
+ * so the shading cannot see them: each fragment's visibility is reconstructed (sections 2.3, 2.3.2) from the
+ * PREVIOUS frame's coefficients, read at the pixel's reprojected position. Every binned record is read once
+ * instead of twice.
+ *   desc         must carry WT_TEMPORAL (WT_ERR_INVALID otherwise); rank <= 4.
+ *   prev_coeffs  the previous frame's coefficients, same layout and storage type as coeffs ([P][C][M], or [P][M]
+ *                words for WT_E5B9G9R9), or NULL for a first frame (no history anywhere).
+ *   prev_pixel   uint32 [P] or NULL: pixel p reads the previous buffer at prev_pixel[p] (a reprojection computed
+ *                by the caller); NULL reads p itself. An entry >= P means that p has no history.
+ *   coeffs       this frame's coefficients (overwritten), for the next frame; may be NULL. It may be the same
+ *                buffer as prev_coeffs when prev_pixel is NULL (each tile reads the previous coefficients of its
+ *                own pixels before it writes them); with a map the two must not overlap (WT_ERR_INVALID when
+ *                they are equal).
+ *   out          [P][3] (overwritten): sum of alpha rgb exp(-A~_prev(x)) + bg * exp(-sum a), with sum a over this
+ *                frame's fragments. A pixel with no history sees nothing in front of its fragments (v = 1).
+ *   bg_rgb is a HOST array of 3. Depth is used as given (no per-pixel bounds: the previous coefficients were
+ *   built over the previous frame's range). */
+wt_status wt_render_temporal(const wt_frame_desc* desc, const wt_fragments* frags, const float* bg_rgb,
+                             const void* prev_coeffs, const uint32_t* prev_pixel, void* coeffs, float* out, void* ws,
+                             size_t ws_bytes, hipStream_t stream);
+
+/* wt_render_temporal over a stream already binned into ws by wt_bin (same WT_TEMPORAL desc and ws_bytes). */
+wt_status wt_render_temporal_binned(const wt_frame_desc* desc, const void* ws, size_t ws_bytes, const float* bg_rgb,
+                                    const void* prev_coeffs, const uint32_t* prev_pixel, void* coeffs, float* out,
+                                    hipStream_t stream);
 
 /* Gradient of a scalar loss through wt_render with respect to alpha and colour. grad_out is dL/dout
  * [P][3]; coeffs are the frame's complete coefficients and accum its accumulation (as written by wt_build

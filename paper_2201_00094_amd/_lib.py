@@ -12,6 +12,7 @@ STATUS_NAMES = {0: "WT_OK", -1: "WT_ERR_INVALID", -2: "WT_ERR_RANGE", -3: "WT_ER
                 -5: "WT_ERR_UNSUPPORTED"}
 WT_F32, WT_F16, WT_BF16, WT_E5B9G9R9 = 0, 1, 2, 3
 WT_TIGHT_DEPTH = 1
+WT_TEMPORAL = 2
 
 
 class FrameDesc(C.Structure):
@@ -41,6 +42,8 @@ SIGNATURES = {
     "wt_resolve": (C.c_int, [_D, _vp, C.POINTER(C.c_float), _vp, _st]),
     "wt_render": (C.c_int, [_D, _F, C.POINTER(C.c_float), _vp, _vp, _vp, _sz, _st]),
     "wt_render_binned": (C.c_int, [_D, _vp, _sz, C.POINTER(C.c_float), _vp, _vp, _st]),
+    "wt_render_temporal": (C.c_int, [_D, _F, C.POINTER(C.c_float), _vp, _vp, _vp, _vp, _vp, _sz, _st]),
+    "wt_render_temporal_binned": (C.c_int, [_D, _vp, _sz, C.POINTER(C.c_float), _vp, _vp, _vp, _vp, _st]),
     "wt_backward": (C.c_int, [_D, _F, _vp, _vp, C.POINTER(C.c_float), _vp, _vp, _vp, _vp, _sz, _st]),
     "wt_dropped_count": (C.c_int, [_vp, _sz, C.POINTER(C.c_uint64), _st]),
     "wt_last_error": (C.c_char_p, []),

@@ -37,7 +37,20 @@ wt_status check_desc(const wt_frame_desc* d) {
     return fail(WT_ERR_INVALID, "E5B9G9R9 storage packs three channels (channels = %u)", d->channels);
   if (d->coeff_dtype == WT_E5B9G9R9 && d->rank > 4)
     return fail(WT_ERR_UNSUPPORTED, "E5B9G9R9 storage supports rank <= 4 (rank = %u)", d->rank);
-  if (d->flags & ~WT_TIGHT_DEPTH) return fail(WT_ERR_INVALID, "unknown flags 0x%x", d->flags);
+  if (d->flags & ~(WT_TIGHT_DEPTH | WT_TEMPORAL)) return fail(WT_ERR_INVALID, "unknown flags 0x%x", d->flags);
+  if ((d->flags & WT_TEMPORAL) && (d->flags & WT_TIGHT_DEPTH))
+    return fail(WT_ERR_UNSUPPORTED, "WT_TEMPORAL excludes WT_TIGHT_DEPTH");
+  if ((d->flags & WT_TEMPORAL) && d->rank > 4)
+    return fail(WT_ERR_UNSUPPORTED, "WT_TEMPORAL supports rank <= 4 (rank = %u)", d->rank);
+  return WT_OK;
+}
+
+wt_status check_temporal(const wt_frame_desc* d, const void* prev, const uint32_t* map, const void* coeffs,
+                         const float* bg, const float* out) {
+  if (!(d->flags & WT_TEMPORAL)) return fail(WT_ERR_INVALID, "the one-pass render needs a WT_TEMPORAL description");
+  if (!bg || !out) return fail(WT_ERR_INVALID, "bg_rgb or out is NULL");
+  if (map && prev && prev == coeffs)
+    return fail(WT_ERR_INVALID, "prev_coeffs and coeffs are one buffer, which needs prev_pixel == NULL");
   return WT_OK;
 }
 
@@ -203,6 +216,33 @@ wt_status wt_render_binned(const wt_frame_desc* desc, const void* ws, size_t ws_
   hipError_t e = wt::launch_render(g, wt::binned_view(g, l, ws, false), bg_rgb, coeffs, out, stream);
   if (e != hipSuccess) return hip_fail(e, "wt_render_binned");
   return WT_OK;
+}
+
+wt_status wt_render_temporal_binned(const wt_frame_desc* desc, const void* ws, size_t ws_bytes, const float* bg_rgb,
+                                    const void* prev_coeffs, const uint32_t* prev_pixel, void* coeffs, float* out,
+                                    hipStream_t stream) {
+  WT_TRY(check_desc(desc));
+  WT_TRY(check_temporal(desc, prev_coeffs, prev_pixel, coeffs, bg_rgb, out));
+  const wt::Geom g = wt::make_geom(*desc);
+  if (wt::lds_temporal_bytes(g) > wt::kLdsBytes)
+    return fail(WT_ERR_UNSUPPORTED, "one-pass tile of %u pixels needs %zu bytes of LDS", g.tile_px,
+                wt::lds_temporal_bytes(g));
+  wt::Layout l;
+  WT_TRY(check_ws(g, ws, ws_bytes, 0, &l));
+  hipError_t e = wt::launch_render_temporal(g, wt::binned_view(g, l, ws, false), bg_rgb, prev_coeffs, prev_pixel,
+                                            coeffs, out, stream);
+  if (e != hipSuccess) return hip_fail(e, "wt_render_temporal");
+  return WT_OK;
+}
+
+wt_status wt_render_temporal(const wt_frame_desc* desc, const wt_fragments* frags, const float* bg_rgb,
+                             const void* prev_coeffs, const uint32_t* prev_pixel, void* coeffs, float* out, void* ws,
+                             size_t ws_bytes, hipStream_t stream) {
+  WT_TRY(check_desc(desc));
+  WT_TRY(check_frags(frags));
+  WT_TRY(check_temporal(desc, prev_coeffs, prev_pixel, coeffs, bg_rgb, out));
+  WT_TRY(wt_bin(desc, frags, ws, ws_bytes, stream));
+  return wt_render_temporal_binned(desc, ws, ws_bytes, bg_rgb, prev_coeffs, prev_pixel, coeffs, out, stream);
 }
 
 wt_status wt_backward(const wt_frame_desc* desc, const wt_fragments* frags, const void* coeffs, const float* accum,

@@ -62,6 +62,12 @@ Geom make_geom(const wt_frame_desc& d, bool backward) {
   const uint32_t bpx = g.tight ? 8 : 0;  // per-pixel depth bounds (two FP32) in LDS
   if (backward) {
     px = tile_for(12 * g.C * g.M + 4 * (3 + g.C) + bpx);
+  } else if (d.flags & WT_TEMPORAL) {
+    // one-pass render: endpoint masses, colour sums and the previous frame's FP32 cells (M <= 32 and no depth
+    // bounds are checked by the API); every pixel/channel has a thread
+    g.temporal = 1;
+    px = std::min<uint32_t>(tile_for(8 * g.C * (g.M + 1) + 24 + 4 * g.C * g.M), floor_pow2(kTileThreads / g.C));
+    g.ep = 1;
   } else {
     px = tile_for(8 * g.C * (g.M + 1) + 24 + bpx);
     // packed three-channel storage is converted on the endpoint path only: cap the tile so that every
@@ -121,7 +127,8 @@ Geom make_geom(const wt_frame_desc& d, bool backward) {
   g.sthreads = 1024;
   const uint32_t bins = g.two ? g.nsuper : g.rb;
   // (one channel only: the three-channel fragment does not fit the 64 registers of eight waves per SIMD)
-  g.kper = (g.C == 1 && g.lds_bins && 8ull * bins + 1024ull * 48 <= kLdsBytes / 2 - 1024) ? 4 : kPer;
+  // (a one-channel record stages in two 16-byte units, index or not: 1024 of them take 32 KB)
+  g.kper = (g.C == 1 && g.lds_bins && 8ull * bins + 1024ull * 32 <= kLdsBytes / 2 - 1024) ? 4 : kPer;
   g.chunk = g.sthreads * g.kper;
   return g;
 }

@@ -70,6 +70,7 @@ struct Geom {
   uint32_t dtype;        // wt_dtype of the coefficient storage
   uint32_t ep;           // 1: the build accumulates endpoint masses (M <= 32, one pixel/channel per thread)
   uint32_t tight;        // 1: per-pixel depth bounds (WT_TIGHT_DEPTH); the tile kernels keep them in LDS
+  uint32_t temporal;     // 1: tiles sized for the one-pass render against the previous frame (WT_TEMPORAL)
   uint32_t sthreads;     // scatter workgroup size
   uint32_t kper;         // fragments per scatter thread (4 or kPer)
   uint32_t chunk;        // fragments per scatter workgroup = sthreads * kPer (also the class granularity)
@@ -119,6 +120,7 @@ Layout make_layout(const Geom& g, uint64_t cap);
 uint64_t capacity_for(const Geom& g, size_t ws_bytes);
 size_t lds_tile_bytes(const Geom& g, bool with_accum);
 size_t lds_backward_bytes(const Geom& g);
+size_t lds_temporal_bytes(const Geom& g);
 Binned binned_view(const Geom& g, const Layout& l, const void* ws, bool with_index);
 
 // Launchers (return hipError_t of the launch).
@@ -131,6 +133,8 @@ hipError_t launch_build(const Geom& g, const Binned& b, void* coeffs, hipStream_
 hipError_t launch_evaluate(const Geom& g, const Binned& b, const void* coeffs, float* accum, hipStream_t s);
 hipError_t launch_resolve(const Geom& g, const float* accum, const float* bg, float* out, hipStream_t s);
 hipError_t launch_render(const Geom& g, const Binned& b, const float* bg, void* coeffs, float* out, hipStream_t s);
+hipError_t launch_render_temporal(const Geom& g, const Binned& b, const float* bg, const void* prev,
+                                  const uint32_t* map, void* coeffs, float* out, hipStream_t s);
 hipError_t launch_backward(const Geom& g, const Binned& b, const void* coeffs, const float* accum, const float* bg,
                            const float* grad_out, float* grad_alpha, float* grad_rgb, uint64_t count,
                            hipStream_t s);

@@ -762,6 +762,142 @@ __global__ __launch_bounds__(kTileThreads) void k_render(Binned b, Geom g, TS* _
   }
 }
 
+// ------------------------------------------------------------------------------------------- one pass, previous frame
+//
+// The single-pass variant the paper proposes as future work: the frame's coefficients are built in the same pass
+// that shades its fragments, so the shading reconstructs visibility from the PREVIOUS frame's coefficients, read
+// at each pixel's reprojected position (an integer pixel map supplied by the caller; identity without one). Each
+// binned record is read once instead of twice.
+
+// Row of M storage values of one pixel/channel, 16 bytes at a time where the layout allows.
+template <typename TS, int M>
+__device__ __forceinline__ void load_row(const TS* src, TS (&s)[M]) {
+  if ((M * sizeof(TS)) % 16 == 0) {
+#pragma unroll
+    for (int k = 0; k < (int)(M * sizeof(TS) / 16); ++k) {
+      const uint4 u = ((const uint4*)src)[k];
+      __builtin_memcpy((char*)s + 16 * k, &u, 16);
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m < M; ++m) s[m] = src[m];
+  }
+}
+
+// FP32 cells [C*M][TP] of the previous frame for the tile's pixels: pixel p reads the previous buffer at
+// map[p] (p without a map). Zero (no history: visibility 1) without a previous buffer, for a map entry >= P and
+// for pixels outside the frame.
+template <int C, typename TS, int M>
+__device__ __forceinline__ void prev_cells(const Geom& g, const TileRef& r, const TS* prev, const uint32_t* map,
+                                           float* lc) {
+  const uint32_t TP = g.tile_px;
+  for (uint32_t q = threadIdx.x; q < TP * C; q += blockDim.x) {
+    const uint32_t c = q / TP, lp = q - c * TP;
+    uint64_t p;
+    uint32_t src = 0xffffffffu;
+    if (prev && tile_pixel(g, r, lp, p)) src = map ? map[p] : (uint32_t)p;
+    float v[M];
+    if (src < g.P) {
+      if constexpr (is_e5<TS>::value) {
+        uint32_t w[M];
+        load_row<uint32_t, M>((const uint32_t*)prev + (uint64_t)src * M, w);
+#pragma unroll
+        for (int m = 0; m < M; ++m) v[m] = e5_sign(m) * e5_unpack(w[m], c);
+      } else {
+        TS s[M];
+        load_row<TS, M>(prev + ((uint64_t)src * C + c) * M, s);
+#pragma unroll
+        for (int m = 0; m < M; ++m) v[m] = widen<TS>(s[m]);
+      }
+      synth_regs<M>(v);
+    } else {
+#pragma unroll
+      for (int m = 0; m < M; ++m) v[m] = 0.f;
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) lc[(c * M + m) * TP + lp] = v[m];
+  }
+}
+
+// One fragment of the single pass: its two endpoint masses into this frame's build (le, [C*(M+1)][TP] FP64) and
+// its colour, weighted by the previous frame's visibility (lc), into the colour sums (la, [3][TP] FP64).
+template <int C>
+__device__ __forceinline__ void temporal_add(acc_t* le, const float* lc, acc_t* la, const Geom& g,
+                                             const Frag<C>& f) {
+  const uint32_t TP = g.tile_px, M1 = g.M + 1;
+  uint32_t j;
+  float t, omt;
+  cell_coord(f.x, nullptr, TP, f.lp, g.M, j, t, omt);
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const float alc = alpha_clamped(f.al[c]);
+    const float a = absorbance(alc);
+    acc_t* e = le + (c * M1 + j) * TP + f.lp;
+    atomicAdd(e, (acc_t)(a * omt));
+    atomicAdd(e + TP, (acc_t)(a * t));
+    const float* cf = lc + (c * g.M) * TP + f.lp;
+    const float hi = cf[j * TP];
+    const float lo = j ? cf[(j - 1) * TP] : 0.f;
+    const float v = __expf(-fmaf(t, hi, omt * lo));
+    if (C == 1) {
+      const float w = alc * v;
+      atomicAdd(la + 0 * TP + f.lp, (acc_t)(w * f.rgb[0]));
+      atomicAdd(la + 1 * TP + f.lp, (acc_t)(w * f.rgb[1]));
+      atomicAdd(la + 2 * TP + f.lp, (acc_t)(w * f.rgb[2]));
+    } else {
+      atomicAdd(la + c * TP + f.lp, (acc_t)(alc * f.rgb[c] * v));
+    }
+  }
+}
+
+// LDS: endpoint masses [C*(M+1)][TP] FP64 (then this frame's FP32 cells and sums of a in their place), colour sums
+// [3][TP] FP64, previous cells [C*M][TP] FP32. prev and coeffs may be the same buffer when map is null: a tile
+// reads the previous coefficients of its own pixels before it writes theirs.
+template <int C, typename TS>
+__global__ __launch_bounds__(kTileThreads) void k_render_temporal(Binned b, Geom g, const TS* prev,
+                                                                  const uint32_t* __restrict__ map, TS* coeffs,
+                                                                  float bg0, float bg1, float bg2,
+                                                                  float* __restrict__ out) {
+  extern __shared__ acc_t smem_d[];
+  const uint32_t TP = g.tile_px;
+  const TileRef r = tile_ref(g, b, b.order[blockIdx.x]);
+  const float bg[3] = {bg0, bg1, bg2};
+  acc_t* le = smem_d;
+  acc_t* la = smem_d + C * (g.M + 1) * TP;
+  float* lc = (float*)(la + 3 * TP);
+  for (uint32_t e = threadIdx.x; e < (C * (g.M + 1) + 3) * TP; e += blockDim.x) smem_d[e] = 0.0;
+  with_m(g, [&](auto mm) { prev_cells<C, TS, decltype(mm)::value>(g, r, prev, map, lc); });
+  __syncthreads();
+  uint32_t i = r.beg + threadIdx.x;
+  for (; i + (kEvalUnroll - 1) * blockDim.x < r.end; i += kEvalUnroll * blockDim.x) {
+    Frag<C> f[kEvalUnroll];
+    bool ok[kEvalUnroll];
+#pragma unroll
+    for (int u = 0; u < kEvalUnroll; ++u) ok[u] = load_full<C>(b, i + u * blockDim.x, f[u]);
+#pragma unroll
+    for (int u = 0; u < kEvalUnroll; ++u)
+      if (ok[u]) temporal_add<C>(le, lc, la, g, f[u]);
+  }
+  for (; i < r.end; i += blockDim.x) {
+    Frag<C> f0;
+    if (load_full<C>(b, i, f0)) temporal_add<C>(le, lc, la, g, f0);
+  }
+  __syncthreads();
+  if constexpr (is_e5<TS>::value)
+    with_m(g, [&](auto mm) { e5_render_convert<decltype(mm)::value>(g, r, le, (uint32_t*)coeffs); });
+  else
+    ep_render_convert<C, TS>(g, r, le, coeffs);
+  __syncthreads();
+  const float* sa = (const float*)le + C * g.M * TP;
+  for (uint32_t lp = threadIdx.x; lp < TP; lp += blockDim.x) {
+    uint64_t p;
+    if (!tile_pixel(g, r, lp, p)) continue;
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      out[p * 3 + q] = (float)la[q * TP + lp] + bg[q] * __expf(-sa[(C == 1 ? 0 : q) * TP + lp]);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_resolve(const float* __restrict__ accum, Geom g, float bg0, float bg1,
                                                  float bg2, float* __restrict__ out) {
   const float bg[3] = {bg0, bg1, bg2};
@@ -783,6 +919,10 @@ size_t lds_tile_bytes(const Geom& g, bool with_accum) {
   const size_t bounds = g.tight ? 8ull * g.tile_px : 0;
   if (g.ep) return (size_t)g.tile_px * (g.C * (g.M + 1) + (with_accum ? 3 : 0)) * sizeof(acc_t) + bounds;
   return (size_t)g.tile_px * (g.C * g.M + (with_accum ? g.AL : 0)) * sizeof(acc_t) + bounds;
+}
+
+size_t lds_temporal_bytes(const Geom& g) {
+  return (size_t)g.tile_px * ((g.C * (g.M + 1) + 3) * sizeof(acc_t) + g.C * g.M * sizeof(float));
 }
 
 static size_t lds_eval_bytes(const Geom& g) {
@@ -851,6 +991,22 @@ hipError_t launch_render(const Geom& g, const Binned& b, const float* bg, void* 
     hipError_t err = prep(k, lds);
     if (err != hipSuccess) return err;
     hipLaunchKernelGGL(k, dim3(g.ntiles), dim3(kTileThreads), lds, s, b, g, (TS*)coeffs, bg[0], bg[1], bg[2], out);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_render_temporal(const Geom& g, const Binned& b, const float* bg, const void* prev,
+                                  const uint32_t* map, void* coeffs, float* out, hipStream_t s) {
+  if (!g.ep) return hipErrorNotSupported;  // the API limits the one-pass render to the endpoint path
+  const size_t lds = lds_temporal_bytes(g);
+  return dispatch(g, [&](auto cc, auto* tag) {
+    constexpr int C = decltype(cc)::value;
+    using TS = std::remove_pointer_t<decltype(tag)>;
+    auto k = k_render_temporal<C, TS>;
+    hipError_t err = prep(k, lds);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k, dim3(g.ntiles), dim3(kTileThreads), lds, s, b, g, (const TS*)prev, map, (TS*)coeffs,
+                       bg[0], bg[1], bg[2], out);
     return hipGetLastError();
   });
 }

@@ -26,6 +26,7 @@ class FrameSpec:
     channels: int = 1
     dtype: str = "f32"
     tight: bool = False   # per-pixel depth bounds (WT_TIGHT_DEPTH): pass each frame's stream whole
+    temporal: bool = False  # one-pass render against the previous frame (WT_TEMPORAL): tiles sized for it
 
     @property
     def pixels(self) -> int:
@@ -42,8 +43,8 @@ class FrameSpec:
     def c_desc(self) -> _lib.FrameDesc:
         if self.dtype not in DTYPES:
             raise ValueError("unknown coefficient storage %r" % self.dtype)
-        return _lib.desc(self.width, self.height, self.rank, self.channels, DTYPES[self.dtype],
-                         _lib.WT_TIGHT_DEPTH if self.tight else 0)
+        flags = (_lib.WT_TIGHT_DEPTH if self.tight else 0) | (_lib.WT_TEMPORAL if self.temporal else 0)
+        return _lib.desc(self.width, self.height, self.rank, self.channels, DTYPES[self.dtype], flags)
 
     def coeff_shape(self):
         if self.dtype == "e5b9g9r9":
@@ -204,6 +205,42 @@ def render_binned(spec: FrameSpec, ws: Workspace, bg, out: torch.Tensor, coeffs:
         _check(coeffs, (TORCH_DTYPES[spec.dtype],), spec.coeff_shape(), "coeffs")
     _lib.check(_lib.load().wt_render_binned(C.byref(spec.c_desc()), ws.ptr, ws.nbytes, _lib.bg3(bg), _ptr(coeffs),
                                             _ptr(out), _stream(stream)), "wt_render_binned")
+    return out
+
+
+def _temporal_args(spec, prev, coeffs, prev_pixel, out):
+    if prev is not None:
+        _check(prev, (TORCH_DTYPES[spec.dtype],), spec.coeff_shape(), "prev")
+    if coeffs is not None:
+        _check(coeffs, (TORCH_DTYPES[spec.dtype],), spec.coeff_shape(), "coeffs")
+    if prev_pixel is not None:
+        _check(prev_pixel, (torch.int32, getattr(torch, "uint32", torch.int32)), (spec.pixels,), "prev_pixel")
+    _check(out, (torch.float32,), (spec.pixels, 3), "out")
+
+
+def render_temporal(spec: FrameSpec, frags: Fragments, bg, ws: Workspace, prev: torch.Tensor = None,
+                    coeffs: torch.Tensor = None, prev_pixel: torch.Tensor = None, out: torch.Tensor = None,
+                    stream=None) -> torch.Tensor:
+    """One pass against the previous frame: shades ``frags`` with the visibility of ``prev`` (the previous frame's
+    coefficients, read at ``prev_pixel[p]``, or at p when None; None for no history) while building this frame's
+    coefficients into ``coeffs`` (may be ``prev`` itself when ``prev_pixel`` is None). ``spec.temporal`` must be
+    set."""
+    if out is None:
+        out = torch.empty((spec.pixels, 3), dtype=torch.float32, device=frags.pixel.device)
+    _temporal_args(spec, prev, coeffs, prev_pixel, out)
+    _lib.check(_lib.load().wt_render_temporal(C.byref(spec.c_desc()), C.byref(frags.c_struct(spec.channels)),
+                                              _lib.bg3(bg), _ptr(prev), _ptr(prev_pixel), _ptr(coeffs), _ptr(out),
+                                              ws.ptr, ws.nbytes, _stream(stream)), "wt_render_temporal")
+    return out
+
+
+def render_temporal_binned(spec: FrameSpec, ws: Workspace, bg, out: torch.Tensor, prev: torch.Tensor = None,
+                           coeffs: torch.Tensor = None, prev_pixel: torch.Tensor = None, stream=None):
+    """:func:`render_temporal` over a stream already binned into ``ws`` by :func:`bin`."""
+    _temporal_args(spec, prev, coeffs, prev_pixel, out)
+    _lib.check(_lib.load().wt_render_temporal_binned(C.byref(spec.c_desc()), ws.ptr, ws.nbytes, _lib.bg3(bg),
+                                                     _ptr(prev), _ptr(prev_pixel), _ptr(coeffs), _ptr(out),
+                                                     _stream(stream)), "wt_render_temporal_binned")
     return out
 
 

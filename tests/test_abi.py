@@ -79,9 +79,15 @@ def test_validation_errors_before_any_launch(lib):
     assert lib.wt_bin(C.byref(_lib.desc(8, 8, 3, 1, e5)), C.byref(ok), ws, 1 << 30, None) == _lib.WT_ERR_INVALID
     assert lib.wt_bin(C.byref(_lib.desc(8, 8, 5, 3, e5)), C.byref(ok), ws, 1 << 30, None) == _lib.WT_ERR_UNSUPPORTED
     assert lib.wt_workspace_bytes(C.byref(_lib.desc(8, 8, 4, 3, e5)), 10) > 0
-    # flags: only WT_TIGHT_DEPTH is defined
-    assert lib.wt_bin(C.byref(_lib.desc(8, 8, 3, 1, 0, 2)), C.byref(ok), ws, 1 << 30, None) == _lib.WT_ERR_INVALID
+    # flags: WT_TIGHT_DEPTH and WT_TEMPORAL are defined, and exclude each other
+    assert lib.wt_bin(C.byref(_lib.desc(8, 8, 3, 1, 0, 4)), C.byref(ok), ws, 1 << 30, None) == _lib.WT_ERR_INVALID
     assert lib.wt_workspace_bytes(C.byref(_lib.desc(8, 8, 3, 1, 0, _lib.WT_TIGHT_DEPTH)), 10) > 0
+    assert lib.wt_workspace_bytes(C.byref(_lib.desc(8, 8, 3, 1, 0, _lib.WT_TEMPORAL)), 10) > 0
+    both = _lib.WT_TIGHT_DEPTH | _lib.WT_TEMPORAL
+    assert lib.wt_bin(C.byref(_lib.desc(8, 8, 3, 1, 0, both)), C.byref(ok), ws, 1 << 30, None) == \
+        _lib.WT_ERR_UNSUPPORTED
+    assert lib.wt_bin(C.byref(_lib.desc(8, 8, 5, 1, 0, _lib.WT_TEMPORAL)), C.byref(ok), ws, 1 << 30, None) == \
+        _lib.WT_ERR_UNSUPPORTED
     bg = _lib.bg3((0, 0, 0))
     assert lib.wt_resolve(C.byref(d), None, bg, ws, None) == _lib.WT_ERR_INVALID
     assert lib.wt_render(C.byref(d), C.byref(ok), None, None, ws, ws, 1 << 30, None) == _lib.WT_ERR_INVALID
@@ -89,6 +95,16 @@ def test_validation_errors_before_any_launch(lib):
     assert lib.wt_evaluate_binned(C.byref(d), ws, None, ws, 1 << 30, None) == _lib.WT_ERR_INVALID
     assert lib.wt_backward(C.byref(d), C.byref(ok), ws, ws, bg, None, ws, ws, ws, 1 << 30, None) == \
         _lib.WT_ERR_INVALID
+    # the one-pass render: a WT_TEMPORAL description, and no in-place update through a reprojection map
+    assert lib.wt_render_temporal(C.byref(d), C.byref(ok), bg, None, None, ws, ws, ws, 1 << 30, None) == \
+        _lib.WT_ERR_INVALID
+    assert "WT_TEMPORAL" in _err(lib)
+    dt = _lib.desc(64, 64, 3, 1, 0, _lib.WT_TEMPORAL)
+    assert lib.wt_render_temporal_binned(C.byref(dt), ws, 1 << 30, bg, ws, ws, ws, ws, None) == _lib.WT_ERR_INVALID
+    assert "prev_pixel" in _err(lib)
+    assert lib.wt_render_temporal_binned(C.byref(dt), ws, 1 << 30, None, None, None, None, ws, None) == \
+        _lib.WT_ERR_INVALID
+    assert lib.wt_render_temporal_binned(C.byref(dt), ws, 16, bg, None, None, None, ws, None) == _lib.WT_ERR_RANGE
     n = C.c_uint64(0)
     assert lib.wt_dropped_count(None, 1 << 20, C.byref(n), None) == _lib.WT_ERR_INVALID
     assert lib.wt_dropped_count(ws, 8, C.byref(n), None) == _lib.WT_ERR_RANGE
