@@ -11,6 +11,8 @@ documented at the C definitions:
   shading (2.1 step 3, the compositing sum of 2.2) and the composite over a constant background (2.1 step 4).
 * :func:`shade_prev` -- the one-pass variant: shading against the previous frame's coefficients (the
   future-work proposal of the paper's closing section).
+* :func:`resolve_chromatic`, :func:`spectral_weight` -- the composite over a background image gathered along the
+  refraction offset with per-channel spectral weights (the chromatic-aberration approximation of section 3).
 * :func:`abuffer`  -- the exact sorted A-buffer the method approximates (visibility function of 1.2).
 * :func:`backward` -- gradient of the resolve with respect to alpha and colour (chain rule through the steps).
 * :func:`coeffs_one`, :func:`cells_one`, :func:`reconstruct`, :func:`Psi`, :func:`psi` -- the per-pixel pieces.
@@ -55,6 +57,10 @@ def _load():
     lib.orc_shade_prev.restype = C.c_int
     lib.orc_shade_prev.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64, vp, vp, vp, vp, vp, vp,
                                    vp, vp, C.c_uint64, vp, vp, vp, vp, vp, C.c_int]
+    lib.orc_spectral_weight.restype = None
+    lib.orc_spectral_weight.argtypes = [C.c_int, C.c_int, _f64p]
+    lib.orc_resolve_chromatic.restype = C.c_int
+    lib.orc_resolve_chromatic.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32, vp, vp, vp, vp, C.c_double, C.c_int, vp]
     lib.orc_abuffer.restype = C.c_int
     lib.orc_abuffer.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64, vp, vp, vp, vp, vp, vp, C.c_int, vp, vp,
                                 vp, C.c_int]
@@ -177,6 +183,30 @@ def shade_prev(width, height, rank, pixel, depth, alpha, rgb, prev=None, prev_pi
         raise RuntimeError("orc_shade_prev failed with %d" % rc)
     out = {k: v for k, v in res.items() if v is not None}
     out["dropped"] = int(dropped.value)
+    return out
+
+
+def spectral_weight(i, k):
+    """(red, green, blue) weight of gather tap i of k in the chromatic-aberration composite (section 3)."""
+    w = np.zeros(3)
+    _load().orc_spectral_weight(int(i), int(k), w)
+    return w
+
+
+def resolve_chromatic(width, height, S, suma, background, offset, dispersion=0.5, taps=5, channels=1):
+    """Composite over a background image gathered with k taps along each pixel's refraction offset, weighted per
+    channel (section 3). ``S`` [P, 3] and ``suma`` [P, C] are the accumulated colour and absorbance (e.g. from
+    :func:`resolve`), ``background`` [P, 3] and ``offset`` [P, 2] (pixels) float32. Returns out [P, 3]."""
+    P = int(width) * int(height)
+    S = np.ascontiguousarray(S, dtype=np.float64).reshape(P, 3)
+    suma = np.ascontiguousarray(suma, dtype=np.float64).reshape(P, channels)
+    bg = np.ascontiguousarray(background, dtype=np.float32).reshape(P, 3)
+    off = np.ascontiguousarray(offset, dtype=np.float32).reshape(P, 2)
+    out = np.zeros((P, 3))
+    rc = _load().orc_resolve_chromatic(width, height, channels, _ptr(S), _ptr(suma), _ptr(bg), _ptr(off),
+                                       float(dispersion), int(taps), _ptr(out))
+    if rc != 0:
+        raise RuntimeError("orc_resolve_chromatic failed with %d" % rc)
     return out
 
 

@@ -631,6 +631,109 @@ def test_shade_prev_without_history_sees_nothing_in_front(orc, channels):
         np.testing.assert_allclose(got["out"], ref, rtol=1e-12, atol=1e-15)
 
 
+# ---------------------------------------------------------------------------------------------- chromatic composite
+def test_spectral_weights_golden(orc):
+    """Section 3 spectral weights, hand-computed (tests/golden/spectral_weights.txt), and their invariants: each
+    tap's weights are non-negative and sum to one, red only below t = 1/2, blue only above it."""
+    rows = np.loadtxt(os.path.join(GOLDEN, "spectral_weights.txt"))
+    for k, i, r, g, b in rows:
+        np.testing.assert_allclose(orc.spectral_weight(int(i), int(k)), [r, g, b], rtol=0, atol=1e-15)
+    for k in (3, 5, 7, 9, 11, 17):
+        for i in range(k):
+            w = orc.spectral_weight(i, k)
+            t = i / (k - 1)
+            assert (w >= -1e-15).all() and abs(w.sum() - 1.0) < 1e-15
+            assert (w[0] == 0.0) if t >= 0.5 else True
+            assert (w[2] == 0.0) if t <= 0.5 else True
+
+
+def _chromatic_inputs(rng, W, H, channels, max_off):
+    P = W * H
+    S = rng.random((P, 3))
+    suma = rng.uniform(0.0, 3.0, (P, channels))
+    bg = rng.random((P, 3), dtype=np.float32)
+    off = rng.uniform(-max_off, max_off, (P, 2)).astype(np.float32)
+    return S, suma, bg, off
+
+
+@pytest.mark.parametrize("channels", [1, 3])
+def test_chromatic_zero_offset_reads_the_pixel(orc, channels):
+    """No refraction: every tap lands on the pixel centre, where the bilinear sample is the texel itself."""
+    rng = np.random.default_rng(70 + channels)
+    W, H = 13, 9
+    S, suma, bg, off = _chromatic_inputs(rng, W, H, channels, 0.0)
+    T = np.exp(-suma)[:, [0, 0, 0] if channels == 1 else [0, 1, 2]]
+    for disp in (0.0, 0.5, 2.0):
+        out = orc.resolve_chromatic(W, H, S, suma, bg, np.zeros_like(off), dispersion=disp, taps=5, channels=channels)
+        np.testing.assert_allclose(out, S + T * bg, rtol=1e-15, atol=1e-15)
+
+
+def test_chromatic_uniform_background_is_the_plain_composite(orc):
+    """A uniform background is unchanged by any gather (weights normalised per channel): the chromatic composite of
+    a frame equals the two-pass resolve over that constant colour."""
+    f = synth.frame_c3(seed=71, width=10, height=8, particles=5.0)
+    r = orc.resolve(f.width, f.height, 3, f.pixel, f.depth, f.alpha, f.rgb, bg=(0.3, 0.6, 0.1), channels=3,
+                    want=("accum", "suma", "out"))
+    rng = np.random.default_rng(71)
+    off = rng.uniform(-30, 30, (f.pixels, 2)).astype(np.float32)
+    bg = np.tile(np.array([0.3, 0.6, 0.1], np.float32), (f.pixels, 1))
+    out = orc.resolve_chromatic(f.width, f.height, r["accum"], r["suma"], bg, off, dispersion=0.7, taps=7, channels=3)
+    np.testing.assert_allclose(out, r["out"], rtol=1e-7, atol=1e-8)  # background stored as float32
+
+
+@pytest.mark.parametrize("taps,disp", [(5, 0.5), (3, 1.0), (9, 0.25)])
+def test_chromatic_linear_background_closed_form(orc, taps, disp):
+    """Bilinear interpolation reproduces a linear image exactly, so away from the edges channel q of the gathered
+    background is the image at c + sbar_q delta, sbar_q the spectral-weighted mean of s_i = 1 + disp (t_i - 1/2)."""
+    W, H = 40, 30
+    P = W * H
+    y, x = np.divmod(np.arange(P), W)
+    cx, cy = x + 0.5, y + 0.5
+    A = np.array([0.1, 0.4, 0.7])
+    Bx = np.array([0.01, -0.02, 0.015])
+    By = np.array([-0.005, 0.01, 0.02])
+    Xg, Yg = np.meshgrid(np.arange(W) + 0.5, np.arange(H) + 0.5)
+    img = (A[None, None, :] + Bx[None, None, :] * Xg[..., None] + By[None, None, :] * Yg[..., None])
+    img = img.reshape(P, 3).astype(np.float64)
+    rng = np.random.default_rng(72 + taps)
+    off = rng.uniform(-3, 3, (P, 2))
+    inner = (x >= 6) & (x < W - 6) & (y >= 6) & (y < H - 6)
+    t = np.arange(taps) / (taps - 1)
+    w = np.array([orc.spectral_weight(i, taps) for i in range(taps)])
+    s = 1.0 + disp * (t - 0.5)
+    sbar = (w * s[:, None]).sum(axis=0) / w.sum(axis=0)
+    S = np.zeros((P, 3))
+    suma = np.zeros((P, 1))
+    out = orc.resolve_chromatic(W, H, S, suma, img.astype(np.float32), off.astype(np.float32), dispersion=disp,
+                                taps=taps, channels=1)
+    offf = off.astype(np.float32).astype(np.float64)
+    ref = A[None, :] + Bx[None, :] * (cx[:, None] + sbar[None, :] * offf[:, [0]]) + \
+        By[None, :] * (cy[:, None] + sbar[None, :] * offf[:, [1]])
+    # the image is stored as float32: compare within its rounding
+    np.testing.assert_allclose(out[inner], ref[inner], rtol=0, atol=2e-7)
+
+
+def test_chromatic_edge_clamp_and_integer_offsets(orc):
+    """With no dispersion every tap samples c + delta: an integer offset reads the texel it points at, and an
+    offset far off screen reads the edge texel (clamp-to-edge addressing)."""
+    rng = np.random.default_rng(73)
+    W, H = 17, 11
+    P = W * H
+    S, suma, bg, _ = _chromatic_inputs(rng, W, H, 1, 0.0)
+    S[:] = 0.0
+    suma[:] = 0.0
+    y, x = np.divmod(np.arange(P), W)
+    dx = rng.integers(-4, 5, P)
+    dy = rng.integers(-3, 4, P)
+    off = np.stack([dx, dy], axis=1).astype(np.float32)
+    out = orc.resolve_chromatic(W, H, S, suma, bg, off, dispersion=0.0, taps=5, channels=1)
+    tx, ty = np.clip(x + dx, 0, W - 1), np.clip(y + dy, 0, H - 1)
+    np.testing.assert_allclose(out, bg[ty * W + tx], rtol=0, atol=1e-15)
+    far = np.tile(np.array([[-1000.0, 2000.0]], np.float32), (P, 1))
+    out = orc.resolve_chromatic(W, H, S, suma, bg, far, dispersion=0.0, taps=3, channels=1)
+    np.testing.assert_allclose(out, bg[(H - 1) * W + np.zeros(P, int)], rtol=0, atol=1e-15)
+
+
 # ---------------------------------------------------------------------------------------------- generators
 def test_generators_are_seeded():
     a = synth.frame_c1(seed=7, width=16, height=16)
