@@ -138,6 +138,24 @@ wt_status wt_evaluate(const wt_frame_desc* desc, const wt_fragments* frags, cons
 wt_status wt_resolve(const wt_frame_desc* desc, const float* accum, const float* bg_rgb, float* out,
                      hipStream_t stream);
 
+/* Composite over a background IMAGE with the chromatic-aberration gather of section 3 (instead of wt_resolve's
+ * constant colour). Each pixel's background is gathered along its screen-space refraction offset (accumulated by
+ * the renderer's shading): `taps` bilinear samples (clamp-to-edge addressing; pixel (x, y) has its centre at
+ * (x + 0.5, y + 0.5)) at the centre plus s_i * offset, s_i = 1 + dispersion * (t_i - 1/2), t_i = i / (taps - 1),
+ * so the segment is centred on the single refracted sample and spans dispersion times the offset. Channel q takes
+ * the mean of the taps under its spectral weight: red = smoothstep formula u^2 (3 - 2u), u = clamp((t - 1/2) /
+ * (1/3 - 1/2), 0, 1) (1 for t <= 1/3, 0 for t >= 1/2), blue the same with edges 1/2 and 2/3 (0 for t <= 1/2,
+ * 1 for t >= 2/3), green = 1 - red - blue; red samples the least displaced end, blue the most.
+ * out[p][q] = accum colour + exp(-sum a) * sum_i w_q(t_i) sample_i[q] / sum_i w_q(t_i). With a zero offset, or
+ * dispersion 0 and a constant image, this is wt_resolve over that background.
+ *   accum       [P][4] or [P][8] as written by wt_evaluate.
+ *   background  float [P][3] device image, row-major like out.
+ *   offset      float [P][2] device, (dx, dy) in pixels.
+ *   dispersion  finite; taps odd, 3..63 (WT_ERR_INVALID otherwise; odd counts sample t = 1/2, where green
+ *               has its weight). out [P][3] is overwritten. */
+wt_status wt_resolve_chromatic(const wt_frame_desc* desc, const float* accum, const float* background,
+                               const float* offset, float dispersion, uint32_t taps, float* out, hipStream_t stream);
+
 /* The whole path for one frame in one pass over the binned stream: bin, build, evaluate and resolve, with
  * the per-pixel state held on chip. Writes out[P][3] (overwritten) and, if coeffs is not NULL, the frame's
  * coefficients (overwritten). The evaluation sees the coefficients at storage precision, exactly as a

@@ -40,6 +40,7 @@ SIGNATURES = {
     "wt_build": (C.c_int, [_D, _F, _vp, _vp, _sz, _st]),
     "wt_evaluate": (C.c_int, [_D, _F, _vp, _vp, _vp, _sz, _st]),
     "wt_resolve": (C.c_int, [_D, _vp, C.POINTER(C.c_float), _vp, _st]),
+    "wt_resolve_chromatic": (C.c_int, [_D, _vp, _vp, _vp, C.c_float, C.c_uint32, _vp, _st]),
     "wt_render": (C.c_int, [_D, _F, C.POINTER(C.c_float), _vp, _vp, _vp, _sz, _st]),
     "wt_render_binned": (C.c_int, [_D, _vp, _sz, C.POINTER(C.c_float), _vp, _vp, _st]),
     "wt_render_temporal": (C.c_int, [_D, _F, C.POINTER(C.c_float), _vp, _vp, _vp, _vp, _vp, _sz, _st]),

@@ -3,6 +3,7 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <cmath>
 #include <string>
 
 #include "wt_internal.h"
@@ -186,6 +187,18 @@ wt_status wt_resolve(const wt_frame_desc* desc, const float* accum, const float*
   const wt::Geom g = wt::make_geom(*desc);
   hipError_t e = wt::launch_resolve(g, accum, bg_rgb, out, stream);
   if (e != hipSuccess) return hip_fail(e, "wt_resolve");
+  return WT_OK;
+}
+
+wt_status wt_resolve_chromatic(const wt_frame_desc* desc, const float* accum, const float* background,
+                               const float* offset, float dispersion, uint32_t taps, float* out, hipStream_t stream) {
+  WT_TRY(check_desc(desc));
+  if (!accum || !background || !offset || !out) return fail(WT_ERR_INVALID, "accum, background, offset or out is NULL");
+  if (taps < 3 || taps > 63 || !(taps & 1)) return fail(WT_ERR_INVALID, "taps must be odd and in 3..63, got %u", taps);
+  if (!std::isfinite(dispersion)) return fail(WT_ERR_INVALID, "dispersion is not finite");
+  const wt::Geom g = wt::make_geom(*desc);
+  hipError_t e = wt::launch_resolve_chromatic(g, accum, background, offset, dispersion, taps, out, stream);
+  if (e != hipSuccess) return hip_fail(e, "wt_resolve_chromatic");
   return WT_OK;
 }
 

@@ -135,6 +135,8 @@ hipError_t launch_resolve(const Geom& g, const float* accum, const float* bg, fl
 hipError_t launch_render(const Geom& g, const Binned& b, const float* bg, void* coeffs, float* out, hipStream_t s);
 hipError_t launch_render_temporal(const Geom& g, const Binned& b, const float* bg, const void* prev,
                                   const uint32_t* map, void* coeffs, float* out, hipStream_t s);
+hipError_t launch_resolve_chromatic(const Geom& g, const float* accum, const float* bgimg, const float* offset,
+                                   float dispersion, uint32_t taps, float* out, hipStream_t s);
 hipError_t launch_backward(const Geom& g, const Binned& b, const void* coeffs, const float* accum, const float* bg,
                            const float* grad_out, float* grad_alpha, float* grad_rgb, uint64_t count,
                            hipStream_t s);

@@ -911,6 +911,67 @@ __global__ __launch_bounds__(256) void k_resolve(const float* __restrict__ accum
   }
 }
 
+// ------------------------------------------------------------------------------------------- chromatic composite
+//
+// Composite over a background image sampled through each pixel's screen-space refraction offset, with the
+// chromatic-aberration gather of section 3: k taps along the offset, tap i at parameter t = i / (k - 1) displaced
+// by s = 1 + dispersion (t - 1/2) times the offset, each a bilinear sample of the background (clamp to edge),
+// weighted per channel by the spectral weights (red: the smoothstep formula falling from 1 at t = 1/3 to 0 at
+// t = 1/2; blue: rising from 0 at t = 1/2 to 1 at t = 2/3; green: the remainder) and normalised per channel.
+
+__device__ __forceinline__ float smoothstep_formula(float e0, float e1, float x) {
+  const float u = fminf(fmaxf((x - e0) / (e1 - e0), 0.f), 1.f);
+  return u * u * (3.f - 2.f * u);
+}
+
+// One pixel per thread. The tap position is split into the pixel's integer coordinate and the offset's own
+// integer and fractional parts, so the bilinear fractions keep the offset's precision at any frame size.
+__global__ __launch_bounds__(256) void k_resolve_chromatic(const float* __restrict__ accum, Geom g,
+                                                           const float* __restrict__ bgimg,
+                                                           const float* __restrict__ offset, float dispersion,
+                                                           uint32_t taps, float* __restrict__ out) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= g.P) return;
+  const uint32_t y = fastdiv(p, g.divW);
+  const uint32_t x = p - y * g.W;
+  const float dx = offset[2 * (uint64_t)p], dy = offset[2 * (uint64_t)p + 1];
+  float num[3] = {0.f, 0.f, 0.f}, den[3] = {0.f, 0.f, 0.f};
+  const int Wm = (int)g.W - 1, Hm = (int)g.H - 1;
+  for (uint32_t i = 0; i < taps; ++i) {
+    const float t = (float)i / (float)(taps - 1);
+    float w[3];
+    w[0] = smoothstep_formula(0.5f, 1.f / 3.f, t);
+    w[2] = smoothstep_formula(0.5f, 2.f / 3.f, t);
+    w[1] = 1.f - w[0] - w[2];
+    const float sc = 1.f + dispersion * (t - 0.5f);
+    const float ox = sc * dx, oy = sc * dy;
+    const float fox = floorf(ox), foy = floorf(oy);
+    const float fx = ox - fox, fy = oy - foy;  // exact
+    // sample position minus the half-texel shift: (x + ox, y + oy); the left/top texel and the clamped pair (the
+    // integer parts are bounded before conversion, so a NaN or huge offset still addresses the image's edge)
+    const long lx = (long)x + (long)fminf(fmaxf(fox, -1e9f), 1e9f);
+    const long ly = (long)y + (long)fminf(fmaxf(foy, -1e9f), 1e9f);
+    const int x0 = (int)min<long>(max<long>(lx, 0), Wm), x1 = (int)min<long>(max<long>(lx + 1, 0), Wm);
+    const int y0 = (int)min<long>(max<long>(ly, 0), Hm), y1 = (int)min<long>(max<long>(ly + 1, 0), Hm);
+    const float* r0 = bgimg + (uint64_t)y0 * g.W * 3;
+    const float* r1 = bgimg + (uint64_t)y1 * g.W * 3;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      if (w[q] == 0.f) continue;  // the weights depend on the tap only: uniform across the wavefront
+      const float a = r0[x0 * 3 + q], b = r0[x1 * 3 + q], c = r1[x0 * 3 + q], d = r1[x1 * 3 + q];
+      const float v = (1.f - fy) * ((1.f - fx) * a + fx * b) + fy * ((1.f - fx) * c + fx * d);
+      num[q] += w[q] * v;
+      den[q] += w[q];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const float colour = accum[(uint64_t)p * g.AW + q];
+    const float suma = (g.AW == 4) ? accum[(uint64_t)p * 4 + 3] : accum[(uint64_t)p * 8 + 4 + q];
+    out[(uint64_t)p * 3 + q] = colour + __expf(-suma) * (num[q] / den[q]);
+  }
+}
+
 // ------------------------------------------------------------------------------------------- launchers
 
 // LDS of the render (with_accum) and build kernels: endpoint masses (+ three colour sums), or coefficient
@@ -1009,6 +1070,13 @@ hipError_t launch_render_temporal(const Geom& g, const Binned& b, const float* b
                        bg[0], bg[1], bg[2], out);
     return hipGetLastError();
   });
+}
+
+hipError_t launch_resolve_chromatic(const Geom& g, const float* accum, const float* bgimg, const float* offset,
+                                   float dispersion, uint32_t taps, float* out, hipStream_t s) {
+  const unsigned grid = (unsigned)(((uint64_t)g.P + 255) / 256);
+  hipLaunchKernelGGL(k_resolve_chromatic, dim3(grid), dim3(256), 0, s, accum, g, bgimg, offset, dispersion, taps, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_resolve(const Geom& g, const float* accum, const float* bg, float* out, hipStream_t s) {

@@ -184,6 +184,22 @@ def resolve(spec: FrameSpec, accum: torch.Tensor, bg, out: torch.Tensor = None, 
     return out
 
 
+def resolve_chromatic(spec: FrameSpec, accum: torch.Tensor, background: torch.Tensor, offset: torch.Tensor,
+                      dispersion: float = 0.5, taps: int = 5, out: torch.Tensor = None, stream=None) -> torch.Tensor:
+    """Composite over a background image [P, 3] gathered along each pixel's refraction offset [P, 2] (pixels) with
+    the per-channel spectral weights of the chromatic-aberration approximation (``taps`` odd, >= 3)."""
+    _check(accum, (torch.float32,), (spec.pixels, spec.accum_width), "accum")
+    _check(background, (torch.float32,), (spec.pixels, 3), "background")
+    _check(offset, (torch.float32,), (spec.pixels, 2), "offset")
+    if out is None:
+        out = torch.empty((spec.pixels, 3), dtype=torch.float32, device=accum.device)
+    _check(out, (torch.float32,), (spec.pixels, 3), "out")
+    _lib.check(_lib.load().wt_resolve_chromatic(C.byref(spec.c_desc()), _ptr(accum), _ptr(background), _ptr(offset),
+                                                float(dispersion), int(taps), _ptr(out), _stream(stream)),
+               "wt_resolve_chromatic")
+    return out
+
+
 def render(spec: FrameSpec, frags: Fragments, bg, ws: Workspace, out: torch.Tensor = None,
            coeffs: torch.Tensor = None, stream=None) -> torch.Tensor:
     """Whole path for one frame (bin, build, evaluate, resolve); writes ``out`` and, if given, ``coeffs``."""

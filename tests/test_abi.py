@@ -105,6 +105,12 @@ def test_validation_errors_before_any_launch(lib):
     assert lib.wt_render_temporal_binned(C.byref(dt), ws, 1 << 30, None, None, None, None, ws, None) == \
         _lib.WT_ERR_INVALID
     assert lib.wt_render_temporal_binned(C.byref(dt), ws, 16, bg, None, None, None, ws, None) == _lib.WT_ERR_RANGE
+    # chromatic composite: odd taps in 3..63, finite dispersion, no NULL arrays
+    for taps in (1, 2, 4, 65):
+        assert lib.wt_resolve_chromatic(C.byref(d), ws, ws, ws, 0.5, taps, ws, None) == _lib.WT_ERR_INVALID
+    assert "taps" in _err(lib)
+    assert lib.wt_resolve_chromatic(C.byref(d), ws, ws, ws, float("nan"), 5, ws, None) == _lib.WT_ERR_INVALID
+    assert lib.wt_resolve_chromatic(C.byref(d), ws, None, ws, 0.5, 5, ws, None) == _lib.WT_ERR_INVALID
     n = C.c_uint64(0)
     assert lib.wt_dropped_count(None, 1 << 20, C.byref(n), None) == _lib.WT_ERR_INVALID
     assert lib.wt_dropped_count(ws, 8, C.byref(n), None) == _lib.WT_ERR_RANGE
