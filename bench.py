@@ -29,6 +29,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+LDS_F64_ATOMIC_CEILING = 3.0  # ds_add_f64 per compute unit per clock, random addresses (measured probe)
 METRIC = "resolved fragments/s (build+eval) 1080p×64 frag/px; % HBM peak; p99 ms"
 CSRC = os.path.join(ROOT, "paper_2201_00094_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_smoke1080p.json")
@@ -276,6 +277,16 @@ def main():
                      "traffic": None if glass else measured_traffic(dom, workload_key(args)),
                      "alg_bytes_per_launch": dom_bytes, "avg_ms": dom_ms},
     }
+    # coefficient and colour updates of the tile kernel: LDS FP64 atomics, 2 per channel for the endpoint masses
+    # and 3 for the colour sums per fragment (the clock and CU count are the published ones; the ceiling is what a
+    # random-address ds_add_f64 probe sustained on this GPU)
+    n_at = F * (2 * C + 3)
+    at_s = n_at / (float(render_ms.mean()) * 1e-3)
+    per_cu_clk = at_s / (256 * 2.4e9)
+    line["atomics"] = {"kind": "LDS ds_add_f64 in the tile kernel (%d per fragment)" % (2 * C + 3),
+                       "per_launch": n_at, "per_s": at_s, "per_cu_per_clock": per_cu_clk,
+                       "ceiling_per_cu_per_clock": LDS_F64_ATOMIC_CEILING,
+                       "frac": per_cu_clk / LDS_F64_ATOMIC_CEILING}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(f, args.cpu_fraction, args.seed)
     print(json.dumps(line))

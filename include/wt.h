@@ -148,9 +148,9 @@ wt_status wt_resolve(const wt_frame_desc* desc, const float* accum, const float*
  * 1 for t >= 2/3), green = 1 - red - blue; red samples the least displaced end, blue the most.
  * out[p][q] = accum colour + exp(-sum a) * sum_i w_q(t_i) sample_i[q] / sum_i w_q(t_i). With a zero offset, or
  * dispersion 0 and a constant image, this is wt_resolve over that background.
- *   accum       [P][4] or [P][8] as written by wt_evaluate.
+ *   accum       [P][4] or [P][8] as written by wt_evaluate; 16-byte aligned.
  *   background  float [P][3] device image, row-major like out.
- *   offset      float [P][2] device, (dx, dy) in pixels.
+ *   offset      float [P][2] device, (dx, dy) in pixels; 8-byte aligned.
  *   dispersion  finite; taps odd, 3..63 (WT_ERR_INVALID otherwise; odd counts sample t = 1/2, where green
  *               has its weight). out [P][3] is overwritten. */
 wt_status wt_resolve_chromatic(const wt_frame_desc* desc, const float* accum, const float* background,

@@ -196,6 +196,8 @@ wt_status wt_resolve_chromatic(const wt_frame_desc* desc, const float* accum, co
   if (!accum || !background || !offset || !out) return fail(WT_ERR_INVALID, "accum, background, offset or out is NULL");
   if (taps < 3 || taps > 63 || !(taps & 1)) return fail(WT_ERR_INVALID, "taps must be odd and in 3..63, got %u", taps);
   if (!std::isfinite(dispersion)) return fail(WT_ERR_INVALID, "dispersion is not finite");
+  if ((uintptr_t)accum % 16 || (uintptr_t)offset % 8)
+    return fail(WT_ERR_INVALID, "accum must be 16-byte and offset 8-byte aligned");
   const wt::Geom g = wt::make_geom(*desc);
   hipError_t e = wt::launch_resolve_chromatic(g, accum, background, offset, dispersion, taps, out, stream);
   if (e != hipSuccess) return hip_fail(e, "wt_resolve_chromatic");

@@ -924,8 +924,43 @@ __device__ __forceinline__ float smoothstep_formula(float e0, float e1, float x)
   return u * u * (3.f - 2.f * u);
 }
 
-// One pixel per thread. The tap position is split into the pixel's integer coordinate and the offset's own
-// integer and fractional parts, so the bilinear fractions keep the offset's precision at any frame size.
+// Tap i of k for one pixel: the bilinear sample of every channel with a non-zero spectral weight, accumulated
+// into num/den. The tap position is split into the pixel's integer coordinate and the offset's own integer and
+// fractional parts, so the bilinear fractions keep the offset's precision at any frame size.
+__device__ __forceinline__ void chromatic_tap(const Geom& g, const float* __restrict__ bgimg, uint32_t x, uint32_t y,
+                                              float dx, float dy, float dispersion, uint32_t i, uint32_t k,
+                                              float (&num)[3], float (&den)[3]) {
+  const float t = (float)i / (float)(k - 1);
+  float w[3];
+  w[0] = smoothstep_formula(0.5f, 1.f / 3.f, t);
+  w[2] = smoothstep_formula(0.5f, 2.f / 3.f, t);
+  w[1] = 1.f - w[0] - w[2];
+  const float sc = 1.f + dispersion * (t - 0.5f);
+  const float ox = sc * dx, oy = sc * dy;
+  const float fox = floorf(ox), foy = floorf(oy);
+  const float fx = ox - fox, fy = oy - foy;  // exact
+  // sample position minus the half-texel shift: (x + ox, y + oy); the left/top texel and the clamped pair (the
+  // integer parts are bounded before conversion, so a NaN or huge offset still addresses the image's edge)
+  const long lx = (long)x + (long)fminf(fmaxf(fox, -1e9f), 1e9f);
+  const long ly = (long)y + (long)fminf(fmaxf(foy, -1e9f), 1e9f);
+  const int Wm = (int)g.W - 1, Hm = (int)g.H - 1;
+  const int x0 = (int)min<long>(max<long>(lx, 0), Wm), x1 = (int)min<long>(max<long>(lx + 1, 0), Wm);
+  const int y0 = (int)min<long>(max<long>(ly, 0), Hm), y1 = (int)min<long>(max<long>(ly + 1, 0), Hm);
+  const float* r0 = bgimg + (uint64_t)y0 * g.W * 3;
+  const float* r1 = bgimg + (uint64_t)y1 * g.W * 3;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    if (w[q] == 0.f) continue;  // depends on the tap only (a constant when k is)
+    const float a = r0[x0 * 3 + q], b = r0[x1 * 3 + q], c = r1[x0 * 3 + q], d = r1[x1 * 3 + q];
+    const float v = (1.f - fy) * ((1.f - fx) * a + fx * b) + fy * ((1.f - fx) * c + fx * d);
+    num[q] += w[q] * v;
+    den[q] += w[q];
+  }
+}
+
+// One pixel per thread. K > 0 fixes the tap count at compile time (the weights fold to constants and the taps'
+// loads issue together); K = 0 takes it from `taps`.
+template <int K>
 __global__ __launch_bounds__(256) void k_resolve_chromatic(const float* __restrict__ accum, Geom g,
                                                            const float* __restrict__ bgimg,
                                                            const float* __restrict__ offset, float dispersion,
@@ -934,42 +969,27 @@ __global__ __launch_bounds__(256) void k_resolve_chromatic(const float* __restri
   if (p >= g.P) return;
   const uint32_t y = fastdiv(p, g.divW);
   const uint32_t x = p - y * g.W;
-  const float dx = offset[2 * (uint64_t)p], dy = offset[2 * (uint64_t)p + 1];
+  const float2 o = ((const float2*)offset)[p];
   float num[3] = {0.f, 0.f, 0.f}, den[3] = {0.f, 0.f, 0.f};
-  const int Wm = (int)g.W - 1, Hm = (int)g.H - 1;
-  for (uint32_t i = 0; i < taps; ++i) {
-    const float t = (float)i / (float)(taps - 1);
-    float w[3];
-    w[0] = smoothstep_formula(0.5f, 1.f / 3.f, t);
-    w[2] = smoothstep_formula(0.5f, 2.f / 3.f, t);
-    w[1] = 1.f - w[0] - w[2];
-    const float sc = 1.f + dispersion * (t - 0.5f);
-    const float ox = sc * dx, oy = sc * dy;
-    const float fox = floorf(ox), foy = floorf(oy);
-    const float fx = ox - fox, fy = oy - foy;  // exact
-    // sample position minus the half-texel shift: (x + ox, y + oy); the left/top texel and the clamped pair (the
-    // integer parts are bounded before conversion, so a NaN or huge offset still addresses the image's edge)
-    const long lx = (long)x + (long)fminf(fmaxf(fox, -1e9f), 1e9f);
-    const long ly = (long)y + (long)fminf(fmaxf(foy, -1e9f), 1e9f);
-    const int x0 = (int)min<long>(max<long>(lx, 0), Wm), x1 = (int)min<long>(max<long>(lx + 1, 0), Wm);
-    const int y0 = (int)min<long>(max<long>(ly, 0), Hm), y1 = (int)min<long>(max<long>(ly + 1, 0), Hm);
-    const float* r0 = bgimg + (uint64_t)y0 * g.W * 3;
-    const float* r1 = bgimg + (uint64_t)y1 * g.W * 3;
+  if constexpr (K > 0) {
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      if (w[q] == 0.f) continue;  // the weights depend on the tap only: uniform across the wavefront
-      const float a = r0[x0 * 3 + q], b = r0[x1 * 3 + q], c = r1[x0 * 3 + q], d = r1[x1 * 3 + q];
-      const float v = (1.f - fy) * ((1.f - fx) * a + fx * b) + fy * ((1.f - fx) * c + fx * d);
-      num[q] += w[q] * v;
-      den[q] += w[q];
-    }
+    for (uint32_t i = 0; i < (uint32_t)K; ++i) chromatic_tap(g, bgimg, x, y, o.x, o.y, dispersion, i, K, num, den);
+  } else {
+    for (uint32_t i = 0; i < taps; ++i) chromatic_tap(g, bgimg, x, y, o.x, o.y, dispersion, i, taps, num, den);
+  }
+  float colour[3], suma[3];
+  if (g.AW == 4) {
+    const float4 a = ((const float4*)accum)[p];
+    colour[0] = a.x; colour[1] = a.y; colour[2] = a.z;
+    suma[0] = suma[1] = suma[2] = a.w;
+  } else {
+    const float4 a = ((const float4*)accum)[2 * (uint64_t)p];
+    const float4 b = ((const float4*)accum)[2 * (uint64_t)p + 1];
+    colour[0] = a.x; colour[1] = a.y; colour[2] = a.z;
+    suma[0] = b.x; suma[1] = b.y; suma[2] = b.z;
   }
 #pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    const float colour = accum[(uint64_t)p * g.AW + q];
-    const float suma = (g.AW == 4) ? accum[(uint64_t)p * 4 + 3] : accum[(uint64_t)p * 8 + 4 + q];
-    out[(uint64_t)p * 3 + q] = colour + __expf(-suma) * (num[q] / den[q]);
-  }
+  for (int q = 0; q < 3; ++q) out[(uint64_t)p * 3 + q] = colour[q] + __expf(-suma[q]) * (num[q] / den[q]);
 }
 
 // ------------------------------------------------------------------------------------------- launchers
@@ -1075,7 +1095,9 @@ hipError_t launch_render_temporal(const Geom& g, const Binned& b, const float* b
 hipError_t launch_resolve_chromatic(const Geom& g, const float* accum, const float* bgimg, const float* offset,
                                    float dispersion, uint32_t taps, float* out, hipStream_t s) {
   const unsigned grid = (unsigned)(((uint64_t)g.P + 255) / 256);
-  hipLaunchKernelGGL(k_resolve_chromatic, dim3(grid), dim3(256), 0, s, accum, g, bgimg, offset, dispersion, taps, out);
+  auto k = taps == 3 ? k_resolve_chromatic<3> : taps == 5 ? k_resolve_chromatic<5> : taps == 7 ? k_resolve_chromatic<7>
+         : taps == 9 ? k_resolve_chromatic<9> : k_resolve_chromatic<0>;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(256), 0, s, accum, g, bgimg, offset, dispersion, taps, out);
   return hipGetLastError();
 }
 

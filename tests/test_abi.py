@@ -111,6 +111,8 @@ def test_validation_errors_before_any_launch(lib):
     assert "taps" in _err(lib)
     assert lib.wt_resolve_chromatic(C.byref(d), ws, ws, ws, float("nan"), 5, ws, None) == _lib.WT_ERR_INVALID
     assert lib.wt_resolve_chromatic(C.byref(d), ws, None, ws, 0.5, 5, ws, None) == _lib.WT_ERR_INVALID
+    assert lib.wt_resolve_chromatic(C.byref(d), C.c_void_p(0x1004), ws, ws, 0.5, 5, ws, None) == _lib.WT_ERR_INVALID
+    assert "aligned" in _err(lib)
     n = C.c_uint64(0)
     assert lib.wt_dropped_count(None, 1 << 20, C.byref(n), None) == _lib.WT_ERR_INVALID
     assert lib.wt_dropped_count(ws, 8, C.byref(n), None) == _lib.WT_ERR_RANGE
