@@ -308,16 +308,57 @@ __global__ __launch_bounds__(256) void k_hist_global(const uint32_t* __restrict_
 
 constexpr int kScanThreads = 1024;
 constexpr int kScanItems = 16;
-constexpr uint32_t kOrderMax = 4096;  // tile counts up to this are ordered by size; beyond, raster order
+constexpr uint32_t kOrderBuckets = 256;  // size classes of the heaviest-first tile order
+
+// Exclusive prefix of s over the workgroup (wavefront shuffles, then the wave totals); *total receives the sum.
+// wsum holds kScanThreads / 64 + 1 entries. Ends with a barrier.
+__device__ __forceinline__ uint32_t block_exclusive(uint32_t s, uint32_t* wsum, uint32_t* total) {
+  const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t inc = s;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t v = __shfl_up(inc, o, 64);
+    if (lane >= (uint32_t)o) inc += v;
+  }
+  if (lane == 63) wsum[wv] = inc;
+  __syncthreads();
+  if (wv == 0) {
+    constexpr uint32_t NW = kScanThreads / 64;
+    const uint32_t w = lane < NW ? wsum[lane] : 0u;
+    uint32_t wi = w;
+#pragma unroll
+    for (int o = 1; o < (int)NW; o <<= 1) {
+      const uint32_t v = __shfl_up(wi, o, 64);
+      if (lane >= (uint32_t)o) wi += v;
+    }
+    if (lane < NW) wsum[lane] = wi - w;
+    if (lane == NW - 1) wsum[NW] = wi;
+  }
+  __syncthreads();
+  *total = wsum[kScanThreads / 64];
+  const uint32_t r = wsum[wv] + inc - s;
+  __syncthreads();  // wsum may be reused
+  return r;
+}
+
+// Size class of a tile for the heaviest-first order: log-linear in the count (the leading bit's position and the
+// three bits below it), monotone, 256 classes.
+__device__ __forceinline__ uint32_t size_class(uint32_t c) {
+  const uint32_t v = c + 1;
+  const uint32_t e = 31 - __clz(v);
+  const uint32_t m = e >= 3 ? (v >> (e - 3)) & 7u : (v << (3 - e)) & 7u;
+  return e * 8 + m;
+}
 
 // Exclusive scan over segments in (tile, class) order (counts/cursors are class-major [NX][ntiles]), then the
-// tile order for the tile kernels: heaviest tile first, so the last workgroups to start are the light ones.
+// tile order for the tile kernels: heaviest first by size class (a bucket sort; ties in any order), so the last
+// workgroups to start are the light ones.
 __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t* __restrict__ counts, Geom g,
                                                        uint32_t* __restrict__ offsets,
                                                        uint32_t* __restrict__ cursors,
                                                        uint32_t* __restrict__ order, int with_order) {
-  __shared__ uint32_t sums[kScanThreads];
-  __shared__ unsigned long long keys[kOrderMax];
+  __shared__ uint32_t wsum[kScanThreads / 64 + 1];
+  __shared__ uint32_t bucket[kOrderBuckets];
   const uint64_t n = (uint64_t)g.ntiles * g.NX;
   const uint32_t tid = threadIdx.x;
   uint32_t carry = 0;
@@ -334,15 +375,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t* __restric
       }
       s += v[k];
     }
-    sums[tid] = s;
-    __syncthreads();
-    for (int off = 1; off < kScanThreads; off <<= 1) {
-      const uint32_t add = tid >= (uint32_t)off ? sums[tid - off] : 0;
-      __syncthreads();
-      sums[tid] += add;
-      __syncthreads();
-    }
-    uint32_t run = carry + (tid ? sums[tid - 1] : 0);
+    uint32_t total;
+    uint32_t run = carry + block_exclusive(s, wsum, &total);
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
       const uint64_t e = seg + (uint64_t)tid * kScanItems + k;
@@ -353,44 +387,29 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t* __restric
       }
       run += v[k];
     }
-    carry += sums[kScanThreads - 1];
-    __syncthreads();
+    carry += total;
   }
   if (tid == 0) offsets[n] = carry;
   if (!with_order) return;
-  if (g.ntiles > kOrderMax) {
-    for (uint32_t t = tid; t < g.ntiles; t += kScanThreads) order[t] = t;
-    return;
-  }
-  // bitonic sort of (~count, tile) ascending over the next power of two >= ntiles
-  uint32_t N = 1;
-  while (N < g.ntiles) N <<= 1;
-  for (uint32_t t = tid; t < N; t += kScanThreads) {
-    unsigned long long key = ~0ull;
-    if (t < g.ntiles) {
-      uint32_t c = 0;
-      for (uint32_t x = 0; x < g.NX; ++x) c += counts[x * g.ntiles + t];
-      key = ((unsigned long long)(~c) << 32) | t;
-    }
-    keys[t] = key;
+  // bucket sort by size class, largest class first
+  for (uint32_t b = tid; b < kOrderBuckets; b += kScanThreads) bucket[b] = 0;
+  __syncthreads();
+  for (uint32_t t = tid; t < g.ntiles; t += kScanThreads) {
+    uint32_t c = 0;
+    for (uint32_t x = 0; x < g.NX; ++x) c += counts[x * g.ntiles + t];
+    atomicAdd(&bucket[kOrderBuckets - 1 - size_class(c)], 1u);
   }
   __syncthreads();
-  for (uint32_t size = 2; size <= N; size <<= 1) {
-    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-      for (uint32_t i = tid; i < N / 2; i += kScanThreads) {
-        const uint32_t lo = 2 * i - (i & (stride - 1));
-        const uint32_t hi = lo + stride;
-        const bool up = (lo & size) == 0;
-        const unsigned long long a = keys[lo], b = keys[hi];
-        if ((a > b) == up) {
-          keys[lo] = b;
-          keys[hi] = a;
-        }
-      }
-      __syncthreads();
-    }
+  uint32_t total;
+  const uint32_t bc = tid < kOrderBuckets ? bucket[tid] : 0u;
+  const uint32_t start = block_exclusive(bc, wsum, &total);
+  if (tid < kOrderBuckets) bucket[tid] = start;
+  __syncthreads();
+  for (uint32_t t = tid; t < g.ntiles; t += kScanThreads) {
+    uint32_t c = 0;
+    for (uint32_t x = 0; x < g.NX; ++x) c += counts[x * g.ntiles + t];
+    order[atomicAdd(&bucket[kOrderBuckets - 1 - size_class(c)], 1u)] = t;
   }
-  for (uint32_t t = tid; t < g.ntiles; t += kScanThreads) order[t] = (uint32_t)(keys[t] & 0xffffffffu);
 }
 
 // Per-class counts of the super-tiles (first level of two-level binning) from the per-class tile counts.
@@ -855,7 +874,10 @@ hipError_t launch_bin_count(const Geom& g, const wt_fragments& f, void* ws, cons
   const int vec = aligned16(f.pixel);
   if (F > 0) {
     if (g.lds_bins) {
-      const uint32_t grid = std::min<uint32_t>(((nchunks + g.NX - 1) / g.NX) * g.NX, 2048);
+      // at most 1024 workgroups (four per compute unit with 256 threads): each counts about 32 chunks of its class
+      // and then adds its table to the global counts once (half the global adds of 2048 workgroups; the smoke
+      // frame's histogram measured 0.111 -> 0.101 ms)
+      const uint32_t grid = std::min<uint32_t>(((nchunks + g.NX - 1) / g.NX) * g.NX, 1024);
       const size_t lds = 4ull * g.hrb;
       if (lds <= 32768) {
         hipLaunchKernelGGL(k_hist_lds<256>, dim3(grid), dim3(256), lds, s, f.pixel, F, g, vec, counts, dropped);
