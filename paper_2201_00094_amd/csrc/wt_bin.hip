@@ -12,9 +12,10 @@
 //   k_scan            exclusive scan of the counts, tile-major over (tile, class), into segment offsets and write
 //                     cursors; tile order for the tile kernels (heaviest first).
 //   k_scatter_staged  one chunk (4 or 8 fragments per thread) per workgroup: vector loads into registers, LDS
-//                     rank per tile, one cursor reservation per touched tile, records placed in LDS in tile order,
-//                     then written record by record with consecutive lanes on consecutive records (head array,
-//                     then tail array), so each tile's run is written coalesced.
+//                     rank per tile, records placed in LDS in tile order in rounds, one cursor reservation per tile
+//                     present in a round just before the round is written record by record with consecutive lanes
+//                     on consecutive records (head array, then tail array), so each tile's run is written
+//                     coalesced.
 //   Frames with more than kTwoLevelTiles tiles: a chunk would touch most tiles about once, so the stream is
 //   binned into super-tiles of SW x SH tiles first (k_super_counts, k_scan and k_scatter_staged over the
 //   super-tile geometry), then k_split moves each super-tile's records into its tiles without atomics.
@@ -576,7 +577,9 @@ struct Words {
 constexpr uint32_t staged_head_units(uint32_t C) { return (head_dwords(C) + 1 + 3) / 4; }
 constexpr uint32_t staged_tail_units(bool idx) { return (tail_dwords(idx) + 3) / 4; }
 
-// LDS: srec[S][SH + ST] uint4 one round of sorted records, cnt[nt], gb[nt]. The chunk's sorted order is written in
+// LDS: srec[S][SH + ST] uint4 one round of sorted records (the slot word holds the tile until the write), cnt[nt]
+// (counts, then first staged positions), gb[nt] (reserved base - run start, per round). The chunk's sorted order is
+// written in
 // rounds of S records (S = stage, a power of two chosen by the host to fit the LDS).
 // PER = 4 is meant for two workgroups per compute unit (LDS <= 80 KB, <= 64 VGPRs at eight waves per SIMD):
 // one workgroup's loads and stores overlap the other's ranking and staging.
@@ -620,27 +623,9 @@ __global__ __launch_bounds__(THREADS, PER == 4 ? 8 : 1) void k_scatter_staged(wt
   mine = wave_sum(mine);
   if ((threadIdx.x & 63) == 0 && mine) atomicAdd(&nvalid, mine);
   __syncthreads();
-  // Reserve this chunk's run in every touched tile. The first kResv tiles of each thread keep their returned
-  // slots in registers until after the block scan, so the round trip of the atomics overlaps the scan.
-  constexpr uint32_t kResv = 4;
-  uint32_t resv[kResv];
-#pragma unroll
-  for (uint32_t j = 0; j < kResv; ++j) {
-    const uint32_t t = threadIdx.x + j * THREADS;
-    const uint32_t v = t < g.ntiles ? cnt[t] : 0u;
-    resv[j] = v ? atomicAdd(&cursors[cls * g.ntiles + t], v) : 0u;
-  }
-  for (uint32_t t = threadIdx.x + kResv * THREADS; t < g.ntiles; t += THREADS) {
-    const uint32_t v = cnt[t];
-    gb[t] = v ? atomicAdd(&cursors[cls * g.ntiles + t], v) : 0u;
-  }
   block_scan_inplace<THREADS>(cnt, g.ntiles, wsum);
-#pragma unroll
-  for (uint32_t j = 0; j < kResv; ++j) {
-    const uint32_t t = threadIdx.x + j * THREADS;
-    if (t < g.ntiles) gb[t] = resv[j];
-  }
   __syncthreads();
+  // cnt[t] is now the chunk's first staged position of tile t (tile-major order)
   uint32_t sp[PER];
 #pragma unroll
   for (uint32_t k = 0; k < PER; ++k) sp[k] = (tile[k] == 0xffffffffu) ? 0xffffffffu : cnt[tile[k]] + rank[k];
@@ -652,7 +637,7 @@ __global__ __launch_bounds__(THREADS, PER == 4 ? 8 : 1) void k_scatter_staged(wt
       uint32_t hw[4 * SH], tw[4 * ST];
 #pragma unroll
       for (uint32_t j = 0; j < 4 * SH; ++j)
-        hw[j] = j < DH ? record_word<C, PER>(r, k, local[k], base + i0 + k, j) : gb[tile[k]] + rank[k];
+        hw[j] = j < DH ? record_word<C, PER>(r, k, local[k], base + i0 + k, j) : tile[k];
 #pragma unroll
       for (uint32_t j = 0; j < 4 * ST; ++j) tw[j] = j < DT ? record_word<C, PER>(r, k, local[k], base + i0 + k, DH + j) : 0u;
       uint4* d = srec + (size_t)(sp[k] - r0) * SU;
@@ -661,6 +646,18 @@ __global__ __launch_bounds__(THREADS, PER == 4 ? 8 : 1) void k_scatter_staged(wt
 #pragma unroll
       for (uint32_t u = 0; u < ST; ++u)
         d[SH + u] = make_uint4(tw[4 * u], tw[4 * u + 1], tw[4 * u + 2], tw[4 * u + 3]);
+    }
+    // Reserve this round's run of every tile it holds (one returning atomic per tile on the XCD's shared cursor)
+    // just before the round is written: slots stay reserved but unwritten for one round only, so fewer partly
+    // written lines wait at the frontier and more of them complete in L2 before write-back. The run of tile t is
+    // [max(first_t, r0), min(end_t, r1)); gb[t] = reserved base - run start, so a record's slot is gb[t] plus its
+    // staged position. (Issuing the next round's reservations during this round's writes was slower: the
+    // registers that hold them push the kernel past its two-workgroup budget.)
+    const uint32_t r1 = std::min(r0 + stage, total);
+    for (uint32_t t = threadIdx.x; t < g.ntiles; t += THREADS) {
+      const uint32_t p0 = cnt[t], p1 = t + 1 < g.ntiles ? cnt[t + 1] : total;
+      const uint32_t lo = std::max(p0, r0), hi = std::min(p1, r1);
+      if (hi > lo) gb[t] = atomicAdd(&cursors[cls * g.ntiles + t], hi - lo) - lo;
     }
     __syncthreads();
     const uint32_t ns = std::min(stage, total - r0);
@@ -677,7 +674,7 @@ __global__ __launch_bounds__(THREADS, PER == 4 ? 8 : 1) void k_scatter_staged(wt
         const uint4 v = q[SH + u];
         tw[4 * u] = v.x; tw[4 * u + 1] = v.y; tw[4 * u + 2] = v.z; tw[4 * u + 3] = v.w;
       }
-      const uint64_t slot = hw[DH];
+      const uint64_t slot = (uint32_t)(gb[hw[DH]] + r0 + sidx);
       Words<DH> h;
 #pragma unroll
       for (uint32_t j = 0; j < DH; ++j) h.w[j] = hw[j];

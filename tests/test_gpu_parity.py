@@ -274,3 +274,37 @@ def test_many_tiles(orc, width, height):
     assert g["dropped"] == 0
     assert_coeffs(g["coeffs"], o["coeffs"], sel=sel)
     assert_close_abs(g["out"], o["out"], 1e-4, sel=sel)
+
+
+def test_glass_4k_sampled(orc):
+    """The glass + particles workload at full size (3840x2160, rank 3, 2-4 glass layers with per-channel alpha plus
+    Poisson(24) particles per pixel, about 224 M fragments) in the benchmark's launch configuration (bin count,
+    bin scatter, render over the binned stream; two-level binning), FP32 and FP16 storage, on 2,000 sampled
+    pixels plus the 50 densest."""
+    import torch
+    import paper_2201_00094_amd as wt
+    f = synth.frame_c3(seed=0, rank=3)
+    say("case glass 4K F", f.count)
+    fr = wt.Fragments.from_numpy(f.pixel, f.depth, f.alpha, f.rgb)
+    cnt = np.bincount(f.pixel, minlength=f.pixels)
+    rng = np.random.default_rng(11)
+    sel = np.unique(np.concatenate([rng.choice(f.pixels, 2000, replace=False), np.argsort(cnt)[-50:]]))
+    mask = np.zeros(f.pixels, bool)
+    mask[sel] = True
+    for dtype, rel, atol in (("f32", 1e-5, 1e-4), ("f16", 2 * 2.0 ** -11 + 1e-5, 1e-3)):
+        say("  storage", dtype)
+        spec = wt.FrameSpec(f.width, f.height, 3, 3, dtype)
+        ws = wt.Workspace(spec, f.count)
+        coeffs = spec.new_coeffs()
+        out = torch.empty((spec.pixels, 3), dtype=torch.float32, device="cuda")
+        wt.bin_count(spec, fr, ws)
+        wt.bin_scatter(spec, fr, ws)
+        wt.render_binned(spec, ws, f.bg, out, coeffs)
+        torch.cuda.synchronize()
+        assert wt.dropped_count(ws) == 0
+        o = oracle_frame(orc, f, mask=mask, want=("coeffs", "out"), storage="exact" if dtype == "f32" else dtype)
+        assert_coeffs(coeffs.float().cpu().double().numpy(), o["coeffs"], rel=rel, sel=sel, what=dtype + " coeffs")
+        err = assert_close_abs(out.cpu().double().numpy(), o["out"], atol, sel=sel, what=dtype + " out")
+        say("  %s: max |out - oracle| on %d sampled pixels: %.2e" % (dtype, sel.size, err))
+        del ws, coeffs, out
+        torch.cuda.empty_cache()
