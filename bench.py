@@ -149,7 +149,8 @@ def main():
     ap.add_argument("--requests", type=int, default=500, help="serve mode: requests per trace")
     ap.add_argument("--load", default="0.5,0.8,0.95",
                     help="serve mode: arrival rates as shares of the solo capacity (comma-separated sweep)")
-    ap.add_argument("--budget-gb", type=float, default=32.0, help="serve mode: HBM admission budget")
+    ap.add_argument("--budget-gb", type=float, default=64.0,
+                    help="serve mode: HBM admission budget (default: four slots of a 3840x2160 request)")
     ap.add_argument("--slots", type=int, default=4, help="serve mode: concurrent requests (HIP streams)")
     args = ap.parse_args()
 

@@ -106,7 +106,7 @@ class Server:
     """Admission by HBM footprint and free slots; FIFO with bounded back-filling (a request that does not fit
     may be passed by later, smaller ones at most ``max_bypass`` times, after which admission waits for it)."""
 
-    def __init__(self, executor, slots: int = 4, budget_bytes: int = 32 << 30, max_bypass: int = 8,
+    def __init__(self, executor, slots: int = 4, budget_bytes: int = 64 << 30, max_bypass: int = 8,
                  poll_interval: float = 0.0002, clock=time.perf_counter):
         self.ex = executor
         self.slots = int(slots)
@@ -264,7 +264,10 @@ class GpuExecutor:
         from . import wt as _wt
         torch = self.torch
         need_ws = _wt.workspace_bytes(spec, max(req.count, 1))
-        need_cf = spec.pixels * spec.channels * spec.M * {"f32": 4, "f16": 2, "bf16": 2}[spec.dtype]
+        n_el = 1
+        for d in spec.coeff_shape():
+            n_el *= d
+        need_cf = n_el * _wt.TORCH_DTYPES[spec.dtype].itemsize
         with torch.cuda.stream(self.streams[slot]):
             if self.ws[slot] is None or self.ws[slot].numel() < need_ws:
                 self.ws[slot] = torch.empty(need_ws, dtype=torch.uint8, device=self.device)
