@@ -149,9 +149,9 @@ def main():
     ap.add_argument("--requests", type=int, default=500, help="serve mode: requests per trace")
     ap.add_argument("--load", default="0.5,0.8,0.95",
                     help="serve mode: arrival rates as shares of the solo capacity (comma-separated sweep)")
-    ap.add_argument("--budget-gb", type=float, default=64.0,
-                    help="serve mode: HBM admission budget (default: four slots of a 3840x2160 request)")
-    ap.add_argument("--slots", type=int, default=4, help="serve mode: concurrent requests (HIP streams)")
+    ap.add_argument("--budget-gb", type=float, default=96.0,
+                    help="serve mode: HBM admission budget (default: room for five 3840x2160 requests)")
+    ap.add_argument("--slots", type=int, default=3, help="serve mode: concurrent requests (HIP streams)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))

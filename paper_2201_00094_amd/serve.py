@@ -106,7 +106,7 @@ class Server:
     """Admission by HBM footprint and free slots; FIFO with bounded back-filling (a request that does not fit
     may be passed by later, smaller ones at most ``max_bypass`` times, after which admission waits for it)."""
 
-    def __init__(self, executor, slots: int = 4, budget_bytes: int = 64 << 30, max_bypass: int = 8,
+    def __init__(self, executor, slots: int = 3, budget_bytes: int = 96 << 30, max_bypass: int = 8,
                  poll_interval: float = 0.0002, clock=time.perf_counter):
         self.ex = executor
         self.slots = int(slots)
@@ -249,7 +249,7 @@ class GpuExecutor:
     one resident coefficient buffer, grown to the largest request seen and shared by every frame description;
     completion observed through an event recorded after the request's work."""
 
-    def __init__(self, slots: int = 4, device="cuda"):
+    def __init__(self, slots: int = 3, device="cuda"):
         import torch
         self.torch = torch
         self.device = torch.device(device)
