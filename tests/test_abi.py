@@ -127,3 +127,26 @@ def test_python_binding_rejects_host_tensors():
         fr.c_struct(1)
     with pytest.raises(ValueError):
         wt.FrameSpec(8, 8, 3, dtype="f64").c_desc()
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """No fallback: without libwt.so every entry point raises instead of computing anything elsewhere."""
+    import paper_2201_00094_amd as wt
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "libwt.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        _lib.load()
+    with pytest.raises(RuntimeError, match="not built"):
+        wt.workspace_bytes(wt.FrameSpec(8, 8, 3), 10)
+
+
+def test_product_never_touches_the_oracle():
+    """The product package and its C sources neither import, load nor name the oracle (test infrastructure)."""
+    pkg = os.path.join(ROOT, "paper_2201_00094_amd")
+    for base, _, files in os.walk(pkg):
+        for name in files:
+            if name.endswith((".py", ".hip", ".h", ".cpp")):
+                with open(os.path.join(base, name), encoding="utf-8") as fh:
+                    assert "oracle" not in fh.read().lower(), os.path.join(base, name)
+    with open(HEADER, encoding="utf-8") as fh:
+        assert "oracle" not in fh.read().lower()
