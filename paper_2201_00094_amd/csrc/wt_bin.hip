@@ -128,7 +128,7 @@ Geom make_geom(const wt_frame_desc& d, bool backward) {
   g.sthreads = 1024;
   const uint32_t bins = g.two ? g.nsuper : g.rb;
   // (one channel only: the three-channel fragment does not fit the 64 registers of eight waves per SIMD)
-  // (a one-channel record stages in two 16-byte units, index or not: 1024 of them take 32 KB)
+  // (a one-channel record stages in at most 32 bytes, index or not: 1024 of them take 32 KB)
   g.kper = (g.C == 1 && g.lds_bins && 8ull * bins + 1024ull * 32 <= kLdsBytes / 2 - 1024) ? 4 : kPer;
   g.chunk = g.sthreads * g.kper;
   return g;
@@ -576,6 +576,44 @@ struct Words {
 // (SH of them), then the tail dwords padded likewise (ST units).
 constexpr uint32_t staged_head_units(uint32_t C) { return (head_dwords(C) + 1 + 3) / 4; }
 constexpr uint32_t staged_tail_units(bool idx) { return (tail_dwords(idx) + 3) / 4; }
+// Bytes of one record staged by the chunk scatter: its head words plus the tile, and its tail words, unpadded.
+constexpr uint32_t staged_record_bytes(uint32_t C, bool idx) { return 4 * (head_dwords(C) + 1 + tail_dwords(idx)); }
+
+// N words to or from LDS with the widest accesses the address allows (d holds N-word records back to back, at a
+// 16-byte aligned base).
+template <uint32_t N>
+__device__ __forceinline__ void lds_put(uint32_t* d, const uint32_t* w) {
+  if constexpr (N % 4 == 0) {
+#pragma unroll
+    for (uint32_t u = 0; u < N / 4; ++u) ((uint4*)d)[u] = make_uint4(w[4 * u], w[4 * u + 1], w[4 * u + 2], w[4 * u + 3]);
+  } else if constexpr (N % 2 == 0) {
+#pragma unroll
+    for (uint32_t u = 0; u < N / 2; ++u) ((uint2*)d)[u] = make_uint2(w[2 * u], w[2 * u + 1]);
+  } else {
+#pragma unroll
+    for (uint32_t u = 0; u < N; ++u) d[u] = w[u];
+  }
+}
+
+template <uint32_t N>
+__device__ __forceinline__ void lds_get(const uint32_t* d, uint32_t* w) {
+  if constexpr (N % 4 == 0) {
+#pragma unroll
+    for (uint32_t u = 0; u < N / 4; ++u) {
+      const uint4 v = ((const uint4*)d)[u];
+      w[4 * u] = v.x; w[4 * u + 1] = v.y; w[4 * u + 2] = v.z; w[4 * u + 3] = v.w;
+    }
+  } else if constexpr (N % 2 == 0) {
+#pragma unroll
+    for (uint32_t u = 0; u < N / 2; ++u) {
+      const uint2 v = ((const uint2*)d)[u];
+      w[2 * u] = v.x; w[2 * u + 1] = v.y;
+    }
+  } else {
+#pragma unroll
+    for (uint32_t u = 0; u < N; ++u) w[u] = d[u];
+  }
+}
 
 // LDS: srec[S][SH + ST] uint4 one round of sorted records (the slot word holds the tile until the write), cnt[nt]
 // (counts, then first staged positions), gb[nt] (reserved base - run start, per round). The chunk's sorted order is
@@ -590,11 +628,11 @@ __global__ __launch_bounds__(THREADS, PER == 4 ? 8 : 1) void k_scatter_staged(wt
                                                                     uint32_t* __restrict__ head,
                                                                     uint32_t* __restrict__ tail,
                                                                     unsigned long long* __restrict__ dropped) {
-  constexpr uint32_t DH = head_dwords(C), DT = tail_dwords(IDX);
-  constexpr uint32_t SH = staged_head_units(C), ST = staged_tail_units(IDX), SU = SH + ST;
+  constexpr uint32_t DH = head_dwords(C), DT = tail_dwords(IDX), HW = DH + 1;
   extern __shared__ uint4 sm4[];
-  uint4* srec = sm4;
-  uint32_t* cnt = (uint32_t*)(srec + (size_t)stage * SU);
+  uint32_t* sh = (uint32_t*)sm4;               // [stage][HW]: head words, then the tile
+  uint32_t* st = sh + (size_t)stage * HW;      // [stage][DT]: tail words
+  uint32_t* cnt = st + (size_t)stage * DT;
   uint32_t* gb = cnt + g.ntiles;
   __shared__ uint32_t wsum[THREADS / 64];
   __shared__ uint32_t nvalid;
@@ -634,18 +672,13 @@ __global__ __launch_bounds__(THREADS, PER == 4 ? 8 : 1) void k_scatter_staged(wt
 #pragma unroll
     for (uint32_t k = 0; k < PER; ++k) {
       if (sp[k] < r0 || sp[k] >= r0 + stage) continue;  // also skips invalid slots (0xffffffff)
-      uint32_t hw[4 * SH], tw[4 * ST];
+      uint32_t hw[HW], tw[DT];
 #pragma unroll
-      for (uint32_t j = 0; j < 4 * SH; ++j)
-        hw[j] = j < DH ? record_word<C, PER>(r, k, local[k], base + i0 + k, j) : tile[k];
+      for (uint32_t j = 0; j < HW; ++j) hw[j] = j < DH ? record_word<C, PER>(r, k, local[k], base + i0 + k, j) : tile[k];
 #pragma unroll
-      for (uint32_t j = 0; j < 4 * ST; ++j) tw[j] = j < DT ? record_word<C, PER>(r, k, local[k], base + i0 + k, DH + j) : 0u;
-      uint4* d = srec + (size_t)(sp[k] - r0) * SU;
-#pragma unroll
-      for (uint32_t u = 0; u < SH; ++u) d[u] = make_uint4(hw[4 * u], hw[4 * u + 1], hw[4 * u + 2], hw[4 * u + 3]);
-#pragma unroll
-      for (uint32_t u = 0; u < ST; ++u)
-        d[SH + u] = make_uint4(tw[4 * u], tw[4 * u + 1], tw[4 * u + 2], tw[4 * u + 3]);
+      for (uint32_t j = 0; j < DT; ++j) tw[j] = record_word<C, PER>(r, k, local[k], base + i0 + k, DH + j);
+      lds_put<HW>(sh + (size_t)(sp[k] - r0) * HW, hw);
+      lds_put<DT>(st + (size_t)(sp[k] - r0) * DT, tw);
     }
     // Reserve this round's run of every tile it holds (one returning atomic per tile on the XCD's shared cursor)
     // just before the round is written: slots stay reserved but unwritten for one round only, so fewer partly
@@ -662,18 +695,9 @@ __global__ __launch_bounds__(THREADS, PER == 4 ? 8 : 1) void k_scatter_staged(wt
     __syncthreads();
     const uint32_t ns = std::min(stage, total - r0);
     for (uint32_t sidx = threadIdx.x; sidx < ns; sidx += blockDim.x) {
-      const uint4* q = srec + (size_t)sidx * SU;
-      uint32_t hw[4 * SH], tw[4 * ST];
-#pragma unroll
-      for (uint32_t u = 0; u < SH; ++u) {
-        const uint4 v = q[u];
-        hw[4 * u] = v.x; hw[4 * u + 1] = v.y; hw[4 * u + 2] = v.z; hw[4 * u + 3] = v.w;
-      }
-#pragma unroll
-      for (uint32_t u = 0; u < ST; ++u) {
-        const uint4 v = q[SH + u];
-        tw[4 * u] = v.x; tw[4 * u + 1] = v.y; tw[4 * u + 2] = v.z; tw[4 * u + 3] = v.w;
-      }
+      uint32_t hw[HW], tw[DT];
+      lds_get<HW>(sh + (size_t)sidx * HW, hw);
+      lds_get<DT>(st + (size_t)sidx * DT, tw);
       const uint64_t slot = (uint32_t)(gb[hw[DH]] + r0 + sidx);
       Words<DH> h;
 #pragma unroll
@@ -823,18 +847,24 @@ __global__ __launch_bounds__(kSplitThreads) void k_split(Geom g, const uint32_t*
 
 static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
+// Largest staging round with two workgroups per compute unit. A round's slots are reserved when it is staged and
+// stay partly written until it is, so longer rounds leave more partial lines at the frontier: on the smoke frame
+// rounds of 2048 records took 1.93 ms against 1.69 ms for 1024 (and shorter rounds expose the reservations' latency
+// more often: 512, 2.07 ms).
+constexpr uint32_t kStageTwoWg = 1024;
+
 template <int C, bool IDX, int PER>
 static hipError_t launch_scatter_t(const Geom& g, const wt_fragments& f, int vec, uint32_t* cursors, uint32_t* head,
                                    uint32_t* tail, unsigned long long* dropped, uint32_t nchunks, hipStream_t s) {
   constexpr int THREADS = 1024;
   if (g.lds_bins) {
-    constexpr uint32_t SU = staged_head_units(C) + staged_tail_units(IDX);
+    constexpr uint32_t RB = staged_record_bytes(C, IDX);
     // largest power-of-two round beside the tile tables (1 KB left for static LDS), within half the LDS when two
     // workgroups share a compute unit
     const size_t budget = (PER == 4 ? kLdsBytes / 2 : kLdsBytes) - 1024;
-    uint32_t stage = g.chunk;
-    while (stage > 256 && (size_t)stage * SU * 16 + 8ull * g.rb > budget) stage >>= 1;
-    const size_t lds = (size_t)stage * SU * 16 + 8ull * g.rb;
+    uint32_t stage = std::min<uint32_t>(g.chunk, PER == 4 ? kStageTwoWg : g.chunk);
+    while (stage > 256 && (size_t)stage * RB + 8ull * g.rb > budget) stage >>= 1;
+    const size_t lds = (size_t)stage * RB + 8ull * g.rb;
     auto k = k_scatter_staged<C, IDX, THREADS, PER>;
     if (lds > 65536) {
       hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
