@@ -244,6 +244,15 @@ def test_smoke_1080p_64_sampled(orc, rank):
     assert wt.dropped_count(ws) == 0
     c = coeffs[:, 0, :]
     assert bool((c[:, 0] >= 0).all()) and bool((c[:, 1:] <= 0).all())
+    # P5 over the whole frame: the cell values of the stored coefficients (the level-scaled inverse Haar transform,
+    # children = parent +/- d) never decrease with depth, up to the FP32 rounding of the stored values
+    v = c[:, :1].double()
+    for n in range(rank + 1):
+        d = c[:, (1 << n):(2 << n)].double()
+        v = torch.stack([v + d, v - d], dim=2).reshape(c.shape[0], 2 << n)
+    tol = 4 * 2.0 ** -24 * v.abs().amax(dim=1, keepdim=True)
+    assert bool(((v[:, 1:] - v[:, :-1]) >= -tol).all()), "cell values decrease with depth"
+    del v, d
     cnt = np.bincount(f.pixel, minlength=f.pixels)
     rng = np.random.default_rng(rank)
     sel = np.unique(np.concatenate([rng.choice(f.pixels, 1500, replace=False), np.argsort(cnt)[-100:]]))
