@@ -1,0 +1,41 @@
+"""Host-side checks of bench.py (no GPU): the one-GPU guard and the byte models behind the roofline figures."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr
+    assert p.stdout == ""
+
+
+def test_byte_models():
+    # one fragment, no pixels: the two passes read 12 + 24 bytes (one channel), 20 + 32 (three)
+    assert bench.algorithmic_bytes(1, 0, 1, 64) == 36
+    assert bench.algorithmic_bytes(1, 0, 3, 192) == 52
+    # one pixel, no fragments: coefficients written and read, accumulation written and read, composite written
+    assert bench.algorithmic_bytes(0, 1, 1, 64) == 2 * 64 + 2 * 16 + 12
+    assert bench.algorithmic_bytes(0, 1, 3, 192) == 2 * 192 + 2 * 32 + 12
+    # the fused tile kernel: the stream twice, the coefficients and composite once
+    assert bench.render_kernel_bytes(1, 1, 1, 64) == 36 + 64 + 12
+    # the scatter: read and write one record (24 B at one channel, 32 B at three)
+    assert bench.scatter_kernel_bytes(1, 1) == 48 and bench.scatter_kernel_bytes(1, 3) == 64
+    # the one-pass render: the stream once, previous coefficients read, this frame's written, composite
+    assert bench.temporal_bytes(1, 1, 1, 64) == 24 + 2 * 64 + 12
+    # the smoke frame's whole-path figure quoted in the design notes (132.7 M fragments, rank 3, FP32)
+    assert bench.algorithmic_bytes(132_689_233, 1920 * 1080, 1, 64) == pytest.approx(5.13e9, rel=2e-3)
+
+
+def test_traffic_is_keyed_to_the_sources():
+    """A counter summary taken on other kernel sources is not reported."""
+    assert len(bench.sources_digest()) == 64
+    assert bench.measured_traffic("k_scatter_staged", "no_such_workload") is None
