@@ -270,8 +270,8 @@ def test_smoke_1080p_64_sampled(orc, rank):
 
 @pytest.mark.parametrize("width,height", [(1200, 1100), (2000, 1100), (3840, 2160)])
 def test_many_tiles(orc, width, height):
-    """Three channels at rank 4 use 16 x 8 tiles: about 10,000 tiles (one LDS tile table), about 17,000 (two
-    passes of tile ranges) and 64,800 at 3840 x 2160 (four passes)."""
+    """Three channels at rank 4 use 16 x 8 tiles: about 10,000, 17,000 and 64,800 tiles (at 3840 x 2160), each binned
+    in two levels (super-tiles of up to 64 tiles, then a split into tiles)."""
     f = synth.frame_c3(seed=width, width=width, height=height, rank=4, particles=1.0)
     say("case many tiles", width, height, "F", f.count)
     g = gpu_render(f)
@@ -317,3 +317,21 @@ def test_glass_4k_sampled(orc):
         say("  %s: max |out - oracle| on %d sampled pixels: %.2e" % (dtype, sel.size, err))
         del ws, coeffs, out
         torch.cuda.empty_cache()
+
+
+def test_global_binning_fallback(orc):
+    """More than 8192 super-tiles of 64 tiles: three channels at rank 8 use 8-pixel tiles (their FP64 coefficient
+    sums take 12 KB of LDS per pixel), so a 2048 x 2064 frame has 528,384 tiles and 8,256 super-tiles, beyond one
+    LDS table; the stream is then binned with one global atomic per fragment. The composite (no coefficient array
+    is written) on 2,000 sampled pixels against the oracle."""
+    f = synth.frame_c3(seed=5, width=2048, height=2064, rank=8, particles=0.3)
+    say("case global binning fallback F", f.count)
+    g = gpu_render(f, want_coeffs=False)
+    assert g["dropped"] == 0
+    rng = np.random.default_rng(5)
+    sel = np.unique(rng.choice(f.pixels, 2000, replace=False))
+    mask = np.zeros(f.pixels, bool)
+    mask[sel] = True
+    o = oracle_frame(orc, f, mask=mask, want=("out",))
+    err = assert_close_abs(g["out"], o["out"], 1e-4, sel=sel)
+    say("  max |out - oracle| on %d sampled pixels: %.2e" % (sel.size, err))
