@@ -522,6 +522,14 @@ __device__ __forceinline__ bool has_nan(const ChunkRegs<C, PER>& r, uint32_t k) 
 }
 
 // Record dword j of fragment k (tile-local pixel `local`, stream index `src`).
+// Forward binning stores each alpha as its absorbance step (binned_absorbance); records binned for the gradient
+// keep alpha.
+template <int C, int PER>
+__device__ __forceinline__ void to_absorbance(ChunkRegs<C, PER>& r) {
+#pragma unroll
+  for (int i = 0; i < C * PER; ++i) r.a[i] = binned_absorbance(r.a[i]);
+}
+
 template <int C, int PER>
 __device__ __forceinline__ uint32_t record_word(const ChunkRegs<C, PER>& r, uint32_t k, uint32_t local, uint32_t src,
                                                 uint32_t j) {
@@ -645,6 +653,7 @@ __global__ __launch_bounds__(THREADS, PER == 4 ? 8 : 1) void k_scatter_staged(wt
   ChunkRegs<C, PER> r;
   const uint32_t i0 = threadIdx.x * PER;
   load_chunk<C, PER>(f, base, i0, n, vec, r);
+  if constexpr (!IDX) to_absorbance<C, PER>(r);
   __syncthreads();
   uint32_t tile[PER], rank[PER], local[PER];
   uint32_t nan_count = 0, mine = 0;
@@ -727,6 +736,7 @@ __global__ __launch_bounds__(THREADS) void k_scatter_global(wt_fragments f, Geom
   ChunkRegs<C, kPer> r;
   const uint32_t i0 = threadIdx.x * kPer;
   load_chunk<C, kPer>(f, base, i0, n, vec, r);
+  if constexpr (!IDX) to_absorbance<C, kPer>(r);
   uint32_t nan_count = 0;
 #pragma unroll
   for (uint32_t k = 0; k < kPer; ++k) {

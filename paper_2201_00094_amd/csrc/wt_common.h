@@ -137,4 +137,10 @@ __device__ __forceinline__ void cell_coord(float x, const uint32_t* lb, uint32_t
 __device__ __forceinline__ float alpha_clamped(float al) { return al > 0.f ? fminf(al, kAlphaMax) : 0.f; }
 __device__ __forceinline__ float absorbance(float al_clamped) { return -log1pf(-al_clamped); }
 
+// What a forward binning stores for each alpha of a fragment: the absorbance step of the clamped alpha, computed
+// once where the binning waits on memory rather than in every pass of the tile kernels; NaN stays NaN (the tile
+// kernels skip such fragments). alpha_of gives the clamped alpha back, 1 - exp(-a), within a few ulp.
+__device__ __forceinline__ float binned_absorbance(float al) { return isnan(al) ? al : absorbance(alpha_clamped(al)); }
+__device__ __forceinline__ float alpha_of(float a) { return -expm1f(-a); }
+
 }  // namespace wt

@@ -77,7 +77,8 @@ struct Geom {
 };
 
 // Binned fragment records, two arrays of structures in the same order:
-//   head [cap][2 + C]: tile-local pixel index, depth, alpha[C]   (everything the build pass reads)
+//   head [cap][2 + C]: tile-local pixel index, depth, and per channel the absorbance -ln(1 - alpha) of the clamped
+//                      alpha (forward binning) or alpha itself (binning for the gradient)   (all the build reads)
 //   tail [cap][3 or 4]: rgb[3], then the stream index when recorded
 constexpr uint32_t head_dwords(uint32_t C) { return 2 + C; }
 constexpr uint32_t tail_dwords(bool with_index) { return 3 + (with_index ? 1 : 0); }

@@ -57,7 +57,7 @@ template <int C>
 struct Frag {
   uint32_t lp;
   float x;
-  float al[C];
+  float al[C];  // absorbance a = -ln(1 - alpha) per channel (forward binning; NaN for a dropped fragment)
   float rgb[3];
 };
 
@@ -126,7 +126,7 @@ __device__ __forceinline__ void build_add(acc_t* lc, const Geom& g, const Frag<C
   float a[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) {
-    a[c] = absorbance(alpha_clamped(f.al[c]));
+    a[c] = f.al[c];  // binned records hold the absorbance
     atomicAdd(lc + (c * g.M) * TP + f.lp, (acc_t)(a[c] * (float)(1.0 - xd)));
   }
   for (uint32_t n = 0; n <= g.rank; ++n) {
@@ -292,7 +292,7 @@ __device__ __forceinline__ void build_ep_add(acc_t* le, const Geom& g, const Fra
   cell_coord(f.x, lb, TP, f.lp, g.M, j, t, omt);
 #pragma unroll
   for (int c = 0; c < C; ++c) {
-    const float a = absorbance(alpha_clamped(f.al[c]));
+    const float a = f.al[c];  // binned records hold the absorbance
     acc_t* e = le + (c * M1 + j) * TP + f.lp;
     atomicAdd(e, (acc_t)(a * omt));
     atomicAdd(e + TP, (acc_t)(a * t));
@@ -567,16 +567,16 @@ __device__ __forceinline__ void eval_add(const T* lc, acc_t* la, const Geom& g, 
     }
     const float At = fmaf(t, hi, omt * lo);
     const float v = __expf(-At);
-    const float alc = alpha_clamped(f.al[c]);
+    const float alc = alpha_of(f.al[c]);
     if (C == 1) {
       const float w = alc * v;
       atomicAdd(la + 0 * TP + f.lp, (acc_t)(w * f.rgb[0]));
       atomicAdd(la + 1 * TP + f.lp, (acc_t)(w * f.rgb[1]));
       atomicAdd(la + 2 * TP + f.lp, (acc_t)(w * f.rgb[2]));
-      if (SUMA) atomicAdd(la + 3 * TP + f.lp, (acc_t)absorbance(alc));
+      if (SUMA) atomicAdd(la + 3 * TP + f.lp, (acc_t)f.al[c]);
     } else {
       atomicAdd(la + c * TP + f.lp, (acc_t)(alc * f.rgb[c] * v));
-      if (SUMA) atomicAdd(la + (3 + c) * TP + f.lp, (acc_t)absorbance(alc));
+      if (SUMA) atomicAdd(la + (3 + c) * TP + f.lp, (acc_t)f.al[c]);
     }
   }
 }
@@ -830,8 +830,8 @@ __device__ __forceinline__ void temporal_add(acc_t* le, const float* lc, acc_t* 
   cell_coord(f.x, nullptr, TP, f.lp, g.M, j, t, omt);
 #pragma unroll
   for (int c = 0; c < C; ++c) {
-    const float alc = alpha_clamped(f.al[c]);
-    const float a = absorbance(alc);
+    const float a = f.al[c];  // binned records hold the absorbance
+    const float alc = alpha_of(a);
     acc_t* e = le + (c * M1 + j) * TP + f.lp;
     atomicAdd(e, (acc_t)(a * omt));
     atomicAdd(e + TP, (acc_t)(a * t));
