@@ -135,7 +135,7 @@ __device__ __forceinline__ void cell_coord(float x, const uint32_t* lb, uint32_t
 
 // Absorbance step a = -ln(1 - alpha) of a (non-NaN) coverage value, with alpha clamped to [0, 1 - 2^-24].
 __device__ __forceinline__ float alpha_clamped(float al) { return al > 0.f ? fminf(al, kAlphaMax) : 0.f; }
-__device__ __forceinline__ float absorbance(float al_clamped) { return -log1pf(-al_clamped); }
+__device__ __forceinline__ float absorbance(float al_clamped) { return neg_log1m(al_clamped); }
 
 // What a forward binning stores for each alpha of a fragment: the absorbance step of the clamped alpha, computed
 // once where the binning waits on memory rather than in every pass of the tile kernels; NaN stays NaN (the tile

@@ -51,6 +51,36 @@ __host__ __device__ inline uint32_t fastdiv(uint32_t n, const FastDiv& f) {
   return (t + ((n - t) >> f.s1)) >> f.s2;
 }
 
+// -ln(1 - al) for al in [0, 1 - 2^-24] to a few ulp, in a few dozen instructions instead of a general-purpose
+// log1p. For al <= 1/2 it is the series -ln(1 - al) = 2 atanh(u) = 2 (u + u^3/3 + u^5/5 + ...) with
+// u = al / (2 - al) <= 1/3, summed to u^15/15 (what is left is below 2^-29 of the sum); 2u is formed as
+// 2 al / (2 - al) so that denormal alphas do not underflow. Above 1/2, 1 - al is exact in FP32 (Sterbenz) and
+// -ln(1 - al) = -log2(1 - al) ln 2.
+__host__ __device__ inline float neg_log1m(float al) {
+  if (al <= 0.5f) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const float v = (2.f * al) * __builtin_amdgcn_rcpf(2.f - al);
+#else
+    const float v = (2.f * al) / (2.f - al);
+#endif
+    const float u2 = 0.25f * v * v;
+    float p = 1.f / 15.f;
+    p = fmaf(p, u2, 1.f / 13.f);
+    p = fmaf(p, u2, 1.f / 11.f);
+    p = fmaf(p, u2, 1.f / 9.f);
+    p = fmaf(p, u2, 1.f / 7.f);
+    p = fmaf(p, u2, 1.f / 5.f);
+    p = fmaf(p, u2, 1.f / 3.f);
+    p = fmaf(p, u2, 1.f);
+    return v * p;
+  }
+#if defined(__HIP_DEVICE_COMPILE__)
+  return -__log2f(1.f - al) * 0.693147182f;
+#else
+  return -log2f(1.f - al) * 0.693147182f;
+#endif
+}
+
 // Frame geometry as the kernels see it.
 struct Geom {
   uint32_t W, H, P;      // frame

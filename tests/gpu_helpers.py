@@ -111,3 +111,36 @@ def accum_to_oracle_layout(acc, channels):
     if channels == 1:
         return acc[:, :3], acc[:, 3:4]
     return acc[:, :3], acc[:, 4:7]
+
+
+def storage_out_bound(orc, rank, coeffs, accum, channels, rel, floor=1e-4):
+    """Per-pixel bound on |composite(GPU) - composite(oracle)| when both store coefficients at reduced precision
+    and may round one coefficient to neighbouring storage values (FP32 accumulation on one side, FP64 on the other,
+    straddling a rounding midpoint). The composite is S + bg exp(-sum a) (section 2.1, steps 3-4); the sum of
+    absorbances is exact on both sides, so storage reaches it only through each fragment's visibility
+    V = exp(-A~(z)). A~ interpolates between 0 and the cell averages (section 2.3.2), so |dA~| is at most
+    E = max_j sum_m |dAbar_j/dc_m| |dc_m| with |dc_m| <= rel |c_m|, and every V, hence S, moves by a factor within
+    exp(+-E): |d out_q| <= (exp(E) - 1) S_q. ``floor`` covers FP32 arithmetic. coeffs [P][C*M] or [P][C][M]
+    (oracle, at the reduced storage), accum [P][3] (oracle); returns [P][3]."""
+    M = 1 << (rank + 1)
+    jac = np.abs(np.stack([orc.cells_one(rank, np.eye(M)[m]) for m in range(M)], axis=1))  # [j][m]
+    c = np.abs(np.asarray(coeffs, dtype=np.float64).reshape(-1, channels, M))
+    E = (c @ jac.T).max(axis=2) * rel  # [P][C]
+    if channels == 1:
+        E = np.repeat(E, 3, axis=1)
+    return np.expm1(E) * np.abs(np.asarray(accum, dtype=np.float64).reshape(-1, 3)) + floor
+
+
+def assert_within(g, o, tol, sel=None, what="out"):
+    """|g - o| <= tol elementwise (tol broadcast to o's shape); returns the largest error and the largest ratio of
+    error to bound."""
+    g = g.reshape(o.shape)
+    tol = np.broadcast_to(tol, o.shape)
+    if sel is not None:
+        g, o, tol = g[sel], o[sel], tol[sel]
+    err = np.abs(g - o)
+    if not (err <= tol).all():
+        i = np.unravel_index(np.argmax(err / tol), o.shape)
+        raise AssertionError("%s: error %.3e > bound %.3e at %s: gpu %r oracle %r" % (what, err[i], tol[i], i, g[i],
+                                                                                       o[i]))
+    return (float(err.max()) if err.size else 0.0), (float((err / tol).max()) if err.size else 0.0)

@@ -750,3 +750,34 @@ def test_smoke_density_mean_and_clip():
     g = synth.smoke_density(rng, 192, 108)
     assert g.mean() == pytest.approx(1.0, abs=1e-6)
     assert g.min() >= 0.1 and g.max() <= 2.0
+
+
+def test_storage_bound_covers_one_step_moves(orc):
+    """The composite bound the reduced-storage parity tests use (each stored coefficient one storage step from the
+    oracle's, section 2.1 steps 3-4 and the interpolation of section 2.3.2) holds when the oracle's own coefficients
+    of random pixels are moved by up to that step: the visibility-weighted sum of the moved expansion stays within
+    it."""
+    from gpu_helpers import storage_out_bound
+    rng = np.random.default_rng(0)
+    rel = 2 * 2.0 ** -11
+    worst = 0.0
+    for _ in range(120):
+        rank = int(rng.integers(1, 5))
+        M = 1 << (rank + 1)
+        k = int(rng.integers(1, 30))
+        x = np.sort(rng.random(k))
+        a = -np.log1p(-rng.random(k) * 0.9)
+        rgb = rng.random(k)
+        cf = orc.coeffs_one(rank, x, a)
+
+        def shade(c):
+            cells = orc.cells_one(rank, c)
+            return sum(-np.expm1(-a[i]) * rgb[i] * np.exp(-orc.reconstruct(rank, cells, x[i])) for i in range(k))
+
+        s0 = shade(cf)
+        bound = storage_out_bound(orc, rank, cf, np.full(3, s0), 1, rel, floor=0.0)[0, 0]
+        for _ in range(10):
+            moved = cf * (1 + rel * rng.choice([-1.0, 1.0], M) * rng.random(M))
+            worst = max(worst, abs(shade(moved) - s0) / bound)
+    assert worst <= 1.0
+    assert worst > 0.3  # the bound is not vacuous
