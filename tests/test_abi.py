@@ -150,3 +150,37 @@ def test_product_never_touches_the_oracle():
                     assert "oracle" not in fh.read().lower(), os.path.join(base, name)
     with open(HEADER, encoding="utf-8") as fh:
         assert "oracle" not in fh.read().lower()
+
+
+def test_every_description_sizes_and_validates(lib):
+    """Every rank, channel count, storage type and flag combination over frame sizes up to the 2^32-pixel limit:
+    the workspace size is 0 exactly for descriptions the validation rejects, grows with the fragment count and
+    holds the binned copy, and each binning or one-pass call with a 16-byte workspace stops at validation (range or
+    unsupported, never a launch)."""
+    sizes = [(1, 1), (7, 5), (1920, 1080), (3840, 2160), (65535, 65537)]
+    counts = [0, 1, 1_000_000, (1 << 32) - 1]
+    ok = _lib.Fragments(10, 8, 8, 8, 8)
+    ws = C.c_void_p(0x1000)  # never dereferenced: validation fails first
+    bg = _lib.bg3((0, 0, 0))
+    errs = (_lib.WT_ERR_RANGE, _lib.WT_ERR_UNSUPPORTED)
+    n_valid = 0
+    for rank in range(11):
+        for ch in (1, 3):
+            for dt in (_lib.WT_F32, _lib.WT_F16, _lib.WT_BF16, _lib.WT_E5B9G9R9):
+                for fl in (0, _lib.WT_TIGHT_DEPTH, _lib.WT_TEMPORAL):
+                    for w, h in sizes:
+                        d = _lib.desc(w, h, rank, ch, dt, fl)
+                        got = [lib.wt_workspace_bytes(C.byref(d), n) for n in counts]
+                        st = lib.wt_bin(C.byref(d), C.byref(ok), ws, 16, None)
+                        if got[0] == 0:
+                            assert all(g == 0 for g in got)
+                            assert st in (_lib.WT_ERR_INVALID, _lib.WT_ERR_UNSUPPORTED), (rank, ch, dt, fl, w, h)
+                            continue
+                        n_valid += 1
+                        assert got == sorted(got) and got[0] < got[2], (rank, ch, dt, fl, w, h, got)
+                        assert got[2] >= 1_000_000 * 28 and got[3] >= ((1 << 32) - 1) * 28
+                        assert st in errs, (rank, ch, dt, fl, w, h, st, _err(lib))
+                        if fl == _lib.WT_TEMPORAL:
+                            st = lib.wt_render_temporal_binned(C.byref(d), ws, 16, bg, None, None, None, ws, None)
+                            assert st in errs, (rank, ch, dt, w, h, st, _err(lib))
+    assert n_valid > 500

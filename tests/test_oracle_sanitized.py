@@ -28,7 +28,7 @@ def test_oracle_pins_under_sanitizers(tmp_path):
                            "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-o", str(lib),
                            os.path.join(ROOT, "oracle", "wt_oracle.c"), "-lm"])
     runner = ("import sys; sys.path.insert(0, %r); import oracle; oracle._LIB = %r; import pytest; "
-              "sys.exit(pytest.main(['-q', '-x', '-p', 'no:cacheprovider', '-m', 'not gpu', %r]))"
+              "sys.exit(pytest.main(['-q', '-s', '-x', '-p', 'no:cacheprovider', '-m', 'not gpu', %r]))"
               % (ROOT, str(lib), os.path.join(ROOT, "tests", "test_oracle_pins.py")))
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:halt_on_error=1", UBSAN_OPTIONS="halt_on_error=1",
                LD_PRELOAD=" ".join([_runtime("libasan.so"), _runtime("libubsan.so")]))
