@@ -583,8 +583,8 @@ static double bilinear(const float* img, uint32_t W, uint32_t H, double X, doubl
  * offset delta_p (pixels; accumulated by the renderer's shading): k taps at c_p + s_i delta_p along the offset,
  * s_i = 1 + dispersion (t_i - 1/2), each a bilinear sample of the background; channel q of the background term is
  * the spectral-weighted mean sum_i w_q(t_i) sample_i[q] / sum_i w_q(t_i); out_q = S_q + T_q * that, with
- * T_q = exp(-suma_{c(q)}). Reading: the paper gives the segment as aligned with the refraction vector and of
- * proportional magnitude; here it is centred on the single-sample position (s = 1) and spans dispersion x delta,
+ * T_q = exp(-suma_{c(q)}). Reading: the paper places the segment along the refraction offset, its length scaling
+ * with the offset's; here it is centred on the single-sample position (s = 1) and spans dispersion x delta,
  * red (t = 0) displaced least and blue (t = 1) most, as normal dispersion bends shorter wavelengths more; the
  * weights of a channel are normalised so that a uniform background is unchanged. k must be odd and >= 3 (the
  * centre tap t = 1/2 is the one green tap for k = 3 .. 7).
