@@ -82,6 +82,7 @@ class _Running:
 class ServerStats:
     completed: int = 0
     rejected: int = 0
+    failed: int = 0      # launch or completion raised; reported on the request's future
     fragments: int = 0
     latencies: list = field(default_factory=list)
     waits: list = field(default_factory=list)   # arrival to admission
@@ -94,7 +95,8 @@ class ServerStats:
         lat = np.array(self.latencies) * 1e3 if self.latencies else np.zeros(1)
         span = max(self.last_done - self.first_submit, 1e-12)
         wait = np.array(self.waits) * 1e3 if self.waits else np.zeros(1)
-        return {"completed": self.completed, "rejected": self.rejected, "fragments": self.fragments,
+        return {"completed": self.completed, "rejected": self.rejected, "failed": self.failed,
+                "fragments": self.fragments,
                 "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                 "mean_ms": float(lat.mean()), "fragments_per_s": self.fragments / span,
                 "queued": int((wait > 1.0).sum()), "wait_p50_ms": float(np.percentile(wait, 50)),
@@ -130,6 +132,8 @@ class Server:
         t = self.clock()
         fp = int(self.ex.footprint(req))
         with self._cv:
+            if self._stop:
+                raise RuntimeError("the server is closed")
             self.stats.first_submit = min(self.stats.first_submit, t)
             if fp > self.budget:
                 self.stats.rejected += 1
@@ -172,6 +176,7 @@ class Server:
                 except Exception as e:  # launch failure: report to the client, release resources
                     self._bytes -= p.footprint
                     self._free_slots.append(slot)
+                    self.stats.failed += 1
                     p.fut.set_exception(e)
                     continue
                 self._running.append(_Running(p, slot, handle, t))
@@ -189,21 +194,28 @@ class Server:
     def _complete_locked(self):
         still = []
         for r in self._running:
-            if self.ex.done(r.handle):
+            try:
+                if not self.ex.done(r.handle):
+                    still.append(r)
+                    continue
                 res = self.ex.finish(r.handle)
-                t = self.clock()
-                res.t_submit, res.t_admit, res.t_done, res.slot, res.tag = r.pend.t_submit, r.t_admit, t, r.slot, \
-                    r.pend.req.tag
+            except Exception as e:  # the request failed on completion: report it, release its slot and bytes
                 self._bytes -= r.pend.footprint
                 self._free_slots.append(r.slot)
-                self.stats.completed += 1
-                self.stats.fragments += r.pend.req.count
-                self.stats.latencies.append(res.latency)
-                self.stats.waits.append(r.t_admit - r.pend.t_submit)
-                self.stats.last_done = max(self.stats.last_done, t)
-                r.pend.fut.set_result(res)
-            else:
-                still.append(r)
+                self.stats.failed += 1
+                r.pend.fut.set_exception(e)
+                continue
+            t = self.clock()
+            res.t_submit, res.t_admit, res.t_done, res.slot, res.tag = r.pend.t_submit, r.t_admit, t, r.slot, \
+                r.pend.req.tag
+            self._bytes -= r.pend.footprint
+            self._free_slots.append(r.slot)
+            self.stats.completed += 1
+            self.stats.fragments += r.pend.req.count
+            self.stats.latencies.append(res.latency)
+            self.stats.waits.append(r.t_admit - r.pend.t_submit)
+            self.stats.last_done = max(self.stats.last_done, t)
+            r.pend.fut.set_result(res)
         self._running = still
 
     def _loop(self):

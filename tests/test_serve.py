@@ -138,6 +138,46 @@ def test_launch_failure_is_reported_and_releases_resources(orc):
     srv.close()
 
 
+class FinishFailsExecutor(OracleExecutor):
+    """Completion raises for one tag, as a device error surfacing when a frame's results are collected would."""
+
+    def __init__(self, orc, bad_tag, **kw):
+        super().__init__(orc, **kw)
+        self.bad_tag = bad_tag
+
+    def launch(self, req, slot):
+        return (req.tag, super().launch(req, slot))
+
+    def done(self, h):
+        return h[1].done()
+
+    def finish(self, h):
+        if h[0] == self.bad_tag:
+            raise RuntimeError("completion failed on purpose")
+        return FrameResult(out=h[1].result())
+
+
+def test_completion_failure_is_reported_and_the_scheduler_keeps_serving(orc):
+    ex = FinishFailsExecutor(orc, "bad")
+    srv = Server(ex, slots=1, budget_bytes=10 ** 9)
+    f_bad = srv.submit(_req(1, 8, 8, tag="bad"))
+    f_ok = [srv.submit(_req(2 + i, 8, 8, tag="ok%d" % i)) for i in range(3)]
+    with pytest.raises(RuntimeError, match="on purpose"):
+        f_bad.result(timeout=30)
+    assert [f.result(timeout=30).tag for f in f_ok] == ["ok0", "ok1", "ok2"]
+    srv.drain(timeout=30)
+    assert srv.stats.failed == 1 and srv.stats.completed == 3
+    assert srv._bytes == 0 and sorted(srv._free_slots) == [0]
+    srv.close()
+
+
+def test_submit_after_close_is_refused(orc):
+    srv = Server(OracleExecutor(orc), slots=1, budget_bytes=10 ** 9)
+    srv.close()
+    with pytest.raises(RuntimeError, match="closed"):
+        srv.submit(_req(1, 8, 8))
+
+
 def test_poisson_trace_generator():
     tr = synth.poisson_arrivals(3, 200, rate_hz=100.0)
     assert len(tr) == 200
