@@ -127,31 +127,58 @@ class Workspace:
         return C.c_void_p(self.buf.data_ptr())
 
 
+# The tile kernels read a binned workspace under the tile geometry of the description they are given, so a call
+# over an already binned stream must use the description it was binned with. The binding records that description
+# on the workspace object (``binned_spec``: set by a binning, cleared when the workspace is reused otherwise) and
+# refuses a mismatch before anything reaches the library.
+def _binned_as(ws, spec, counted=None):
+    ws.binned_spec = spec
+    ws.counted_spec = counted
+
+
+def _require_binned(ws, spec, name, attr="binned_spec"):
+    got = getattr(ws, attr, None)
+    if got is None:
+        raise ValueError("%s: the workspace holds no stream %s" % (
+            name, "counted by bin_count()" if attr == "counted_spec" else "binned by bin() or bin_count() + bin_scatter()"))
+    if got != spec:
+        raise ValueError("%s: the workspace was binned for %r, not for %r" % (name, got, spec))
+
+
 def bin(spec: FrameSpec, frags: Fragments, ws: Workspace, stream=None):
     lib = _lib.load()
+    _binned_as(ws, None)
     _lib.check(lib.wt_bin(C.byref(spec.c_desc()), C.byref(frags.c_struct(spec.channels)), ws.ptr, ws.nbytes,
                           _stream(stream)), "wt_bin")
+    _binned_as(ws, spec)
 
 
 def bin_count(spec: FrameSpec, frags: Fragments, ws: Workspace, stream=None):
     """First half of :func:`bin`: per-tile counts and segment layout."""
+    _binned_as(ws, None)
     _lib.check(_lib.load().wt_bin_count(C.byref(spec.c_desc()), C.byref(frags.c_struct(spec.channels)), ws.ptr,
                                         ws.nbytes, _stream(stream)), "wt_bin_count")
+    _binned_as(ws, None, counted=spec)
 
 
 def bin_scatter(spec: FrameSpec, frags: Fragments, ws: Workspace, stream=None):
-    """Second half of :func:`bin`: copy the stream into its tile segments (after :func:`bin_count`)."""
+    """Second half of :func:`bin`: copy the stream into its tile segments (after :func:`bin_count` with the same
+    arguments)."""
+    _require_binned(ws, spec, "bin_scatter", attr="counted_spec")
     _lib.check(_lib.load().wt_bin_scatter(C.byref(spec.c_desc()), C.byref(frags.c_struct(spec.channels)), ws.ptr,
                                           ws.nbytes, _stream(stream)), "wt_bin_scatter")
+    _binned_as(ws, spec)
 
 
 def build_binned(spec: FrameSpec, coeffs: torch.Tensor, ws: Workspace, stream=None):
+    _require_binned(ws, spec, "build_binned")
     _check(coeffs, (TORCH_DTYPES[spec.dtype],), spec.coeff_shape(), "coeffs")
     _lib.check(_lib.load().wt_build_binned(C.byref(spec.c_desc()), _ptr(coeffs), ws.ptr, ws.nbytes, _stream(stream)),
                "wt_build_binned")
 
 
 def evaluate_binned(spec: FrameSpec, coeffs: torch.Tensor, accum: torch.Tensor, ws: Workspace, stream=None):
+    _require_binned(ws, spec, "evaluate_binned")
     _check(coeffs, (TORCH_DTYPES[spec.dtype],), spec.coeff_shape(), "coeffs")
     _check(accum, (torch.float32,), (spec.pixels, spec.accum_width), "accum")
     _lib.check(_lib.load().wt_evaluate_binned(C.byref(spec.c_desc()), _ptr(coeffs), _ptr(accum), ws.ptr, ws.nbytes,
@@ -161,8 +188,10 @@ def evaluate_binned(spec: FrameSpec, coeffs: torch.Tensor, accum: torch.Tensor, 
 def build(spec: FrameSpec, frags: Fragments, coeffs: torch.Tensor, ws: Workspace, stream=None):
     """coeffs += coefficients of ``frags`` (build pass)."""
     _check(coeffs, (TORCH_DTYPES[spec.dtype],), spec.coeff_shape(), "coeffs")
+    _binned_as(ws, None)
     _lib.check(_lib.load().wt_build(C.byref(spec.c_desc()), C.byref(frags.c_struct(spec.channels)), _ptr(coeffs),
                                     ws.ptr, ws.nbytes, _stream(stream)), "wt_build")
+    _binned_as(ws, spec)
 
 
 def evaluate(spec: FrameSpec, frags: Fragments, coeffs: torch.Tensor, accum: torch.Tensor, ws: Workspace,
@@ -170,8 +199,10 @@ def evaluate(spec: FrameSpec, frags: Fragments, coeffs: torch.Tensor, accum: tor
     """accum += visibility-weighted colour and absorbance of ``frags`` (evaluate pass)."""
     _check(coeffs, (TORCH_DTYPES[spec.dtype],), spec.coeff_shape(), "coeffs")
     _check(accum, (torch.float32,), (spec.pixels, spec.accum_width), "accum")
+    _binned_as(ws, None)
     _lib.check(_lib.load().wt_evaluate(C.byref(spec.c_desc()), C.byref(frags.c_struct(spec.channels)), _ptr(coeffs),
                                        _ptr(accum), ws.ptr, ws.nbytes, _stream(stream)), "wt_evaluate")
+    _binned_as(ws, spec)
 
 
 def resolve(spec: FrameSpec, accum: torch.Tensor, bg, out: torch.Tensor = None, stream=None) -> torch.Tensor:
@@ -209,13 +240,16 @@ def render(spec: FrameSpec, frags: Fragments, bg, ws: Workspace, out: torch.Tens
     _check(out, (torch.float32,), (spec.pixels, 3), "out")
     if coeffs is not None:
         _check(coeffs, (TORCH_DTYPES[spec.dtype],), spec.coeff_shape(), "coeffs")
+    _binned_as(ws, None)
     _lib.check(_lib.load().wt_render(C.byref(spec.c_desc()), C.byref(frags.c_struct(spec.channels)), _lib.bg3(bg),
                                      _ptr(coeffs), _ptr(out), ws.ptr, ws.nbytes, _stream(stream)), "wt_render")
+    _binned_as(ws, spec)
     return out
 
 
 def render_binned(spec: FrameSpec, ws: Workspace, bg, out: torch.Tensor, coeffs: torch.Tensor = None, stream=None):
     """Build, evaluate and resolve of a stream already binned into ``ws`` by :func:`bin`."""
+    _require_binned(ws, spec, "render_binned")
     _check(out, (torch.float32,), (spec.pixels, 3), "out")
     if coeffs is not None:
         _check(coeffs, (TORCH_DTYPES[spec.dtype],), spec.coeff_shape(), "coeffs")
@@ -244,15 +278,18 @@ def render_temporal(spec: FrameSpec, frags: Fragments, bg, ws: Workspace, prev: 
     if out is None:
         out = torch.empty((spec.pixels, 3), dtype=torch.float32, device=frags.pixel.device)
     _temporal_args(spec, prev, coeffs, prev_pixel, out)
+    _binned_as(ws, None)
     _lib.check(_lib.load().wt_render_temporal(C.byref(spec.c_desc()), C.byref(frags.c_struct(spec.channels)),
                                               _lib.bg3(bg), _ptr(prev), _ptr(prev_pixel), _ptr(coeffs), _ptr(out),
                                               ws.ptr, ws.nbytes, _stream(stream)), "wt_render_temporal")
+    _binned_as(ws, spec)
     return out
 
 
 def render_temporal_binned(spec: FrameSpec, ws: Workspace, bg, out: torch.Tensor, prev: torch.Tensor = None,
                            coeffs: torch.Tensor = None, prev_pixel: torch.Tensor = None, stream=None):
     """:func:`render_temporal` over a stream already binned into ``ws`` by :func:`bin`."""
+    _require_binned(ws, spec, "render_temporal_binned")
     _temporal_args(spec, prev, coeffs, prev_pixel, out)
     _lib.check(_lib.load().wt_render_temporal_binned(C.byref(spec.c_desc()), ws.ptr, ws.nbytes, _lib.bg3(bg),
                                                      _ptr(prev), _ptr(prev_pixel), _ptr(coeffs), _ptr(out),
@@ -271,6 +308,7 @@ def backward(spec: FrameSpec, frags: Fragments, coeffs: torch.Tensor, accum: tor
     _check(coeffs, (TORCH_DTYPES[spec.dtype],), spec.coeff_shape(), "coeffs")
     _check(accum, (torch.float32,), (spec.pixels, spec.accum_width), "accum")
     _check(grad_out, (torch.float32,), (spec.pixels, 3), "grad_out")
+    _binned_as(ws, None)  # the gradient bins its own layout (smaller tiles, records that keep alpha)
     _lib.check(_lib.load().wt_backward(C.byref(spec.c_desc()), C.byref(frags.c_struct(spec.channels)), _ptr(coeffs),
                                        _ptr(accum), _lib.bg3(bg), _ptr(grad_out), _ptr(grad_alpha), _ptr(grad_rgb),
                                        ws.ptr, ws.nbytes, _stream(stream)), "wt_backward")
