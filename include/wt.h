@@ -199,7 +199,9 @@ wt_status wt_render_temporal_binned(const wt_frame_desc* desc, const void* ws, s
  * [P][3]; coeffs are the frame's complete coefficients and accum its accumulation (as written by wt_build
  * and wt_evaluate, or recomputed). Writes grad_alpha[F * channels] and grad_rgb[F * 3] (overwritten, in
  * stream order). Depth is not differentiated (A~ has kinks on the subdivision grid). The clamp of alpha has
- * zero slope outside (0, 1 - 2^-24); dropped fragments get zero gradients. bg_rgb is a HOST array of 3. */
+ * zero slope outside (0, 1 - 2^-24); dropped fragments get zero gradients. bg_rgb is a HOST array of 3.
+ * It bins frags into ws in the gradient's own layout (smaller tiles, records that keep alpha), so a stream binned
+ * there before for wt_*_binned calls is gone: bin again before the next such call. */
 wt_status wt_backward(const wt_frame_desc* desc, const wt_fragments* frags, const void* coeffs, const float* accum,
                       const float* bg_rgb, const float* grad_out, float* grad_alpha, float* grad_rgb, void* ws,
                       size_t ws_bytes, hipStream_t stream);
