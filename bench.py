@@ -98,23 +98,79 @@ def scatter_kernel_bytes(F, C):
     return F * 2 * (20 + 4 * C)
 
 
-def cpu_baseline(f, fraction, seed, min_seconds=10.0, max_reps=8):
-    """The FP64 oracle resolving the pixels of a seeded sample of the same frame on the host cores, repeated until
-    about ``min_seconds`` of CPU work have been timed."""
-    import oracle
-    rng = np.random.default_rng(seed + 17)
-    mask = rng.random(f.pixels) < fraction
-    n = int(np.bincount(f.pixel, minlength=f.pixels)[mask].sum())
+def roofline(path_bytes, kernel, kernel_ms, traffic):
+    """Roofline object of the benchmark line. achieved = the path's algorithmic bytes per frame (the per-fragment and
+    per-pixel figures of ``algorithmic_bytes``, times the frame's fragments and pixels, which one launch of the
+    dominant kernel processes) over that kernel's mean launch time; frac = achieved / the published 8 TB/s. The
+    binned copy that the scatter writes and the tile kernel reads back is not algorithmic and earns nothing here.
+    traffic = the kernel's HBM bytes per launch from the committed counter summary (None when it was taken on other
+    sources)."""
+    achieved = path_bytes / (kernel_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "alg_bytes_per_launch": path_bytes,
+            "avg_ms": kernel_ms}
+
+
+def cpu_model():
+    """The host CPU's model name (what lscpu reports as "Model name"), or "unknown"."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.lower().startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _time_oracle(fn, min_seconds, max_reps):
     reps, dt = 0, 0.0
     while reps < max_reps and (reps == 0 or dt < min_seconds):
         t0 = time.perf_counter()
-        oracle.resolve(f.width, f.height, f.rank, f.pixel, f.depth, f.alpha, f.rgb, bg=f.bg, mask=mask,
-                       want=("out",))
+        fn()
         dt += time.perf_counter() - t0
         reps += 1
-    return {"value": n * reps / dt, "unit": "fragments/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": "FP64 oracle resolve of the pixels of a seeded %.0f%% sample of the same frame (%d fragments), "
-                      "%d times, %.1f s wall" % (100 * fraction, n, reps, dt)}
+    return reps, dt
+
+
+def cpu_baseline(f, fraction, seed, single_fraction=0.05, min_seconds=4.0, max_reps=4):
+    """The FP64 oracle on the host cores, three legs on seeded pixel samples of the same frame (each repeated until
+    about ``min_seconds`` of wall time): the wavelet resolve on every core (OpenMP over pixels; the headline
+    ``value``), the same on one thread, and the exact sorted A-buffer on every core. Thread counts are passed
+    explicitly: the oracle's thread setting persists between calls."""
+    import oracle
+    rng = np.random.default_rng(seed + 17)
+    u = rng.random(f.pixels)
+    per_px = np.bincount(f.pixel, minlength=f.pixels)
+    n_all = oracle.num_threads()
+    legs = {}
+
+    def leg(name, frac, threads, fn):
+        mask = u < frac
+        n = int(per_px[mask].sum())
+        reps, dt = _time_oracle(lambda: fn(mask, threads), min_seconds, max_reps)
+        legs[name] = {"value": n * reps / dt, "unit": "fragments/s", "threads": threads,
+                      "sample": "%.0f%% of the pixels (%d fragments), %d time(s), %.1f s wall" % (100 * frac, n, reps,
+                                                                                                   dt)}
+
+    def wavelet(mask, threads):
+        oracle.resolve(f.width, f.height, f.rank, f.pixel, f.depth, f.alpha, f.rgb, bg=f.bg, channels=f.channels,
+                       mask=mask, want=("out",), threads=threads)
+
+    def abuf(mask, threads):
+        oracle.abuffer(f.width, f.height, f.pixel, f.depth, f.alpha, f.rgb, bg=f.bg, channels=f.channels, mask=mask,
+                       threads=threads)
+
+    leg("wavelet_all_cores", fraction, n_all, wavelet)
+    leg("wavelet_one_thread", min(fraction, single_fraction), 1, wavelet)
+    leg("abuffer_all_cores", fraction, n_all, abuf)
+    head = legs["wavelet_all_cores"]
+    return {"value": head["value"], "unit": "fragments/s", "cores": n_all, "kind": "oracle",
+            "sample": "FP64 oracle wavelet resolve (build, cells, interpolation, composite) of the same frame on %d "
+                      "threads: %s; legs below: one thread, and the exact A-buffer timed separately" % (n_all,
+                                                                                                      head["sample"]),
+            "nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "cpu_model": cpu_model(),
+            "legs": legs}
 
 
 def main():
@@ -237,14 +293,18 @@ def main():
     coeff_px = 4 * M if args.dtype == "e5b9g9r9" else {"f32": 4, "f16": 2, "bf16": 2}[args.dtype] * C * M
     if args.temporal:
         b_alg = temporal_bytes(F, P, C, coeff_px)
-        kernels = {"k_render_temporal": (temporal_bytes(F, P, C, coeff_px), float(render_ms.mean()))}
+        models = {"k_render_temporal": (temporal_bytes(F, P, C, coeff_px), float(render_ms.mean()))}
     else:
         b_alg = algorithmic_bytes(F, P, C, coeff_px)
-        kernels = {"k_render": (render_kernel_bytes(F, P, C, coeff_px), float(render_ms.mean()))}
-    kernels["k_scatter_staged"] = (scatter_kernel_bytes(F, C), float(scatter_ms.mean()))
-    dom = max(kernels, key=lambda k: kernels[k][1])
-    dom_bytes, dom_ms = kernels[dom]
-    dom_gbs = dom_bytes / (dom_ms * 1e-3) / 1e9
+        models = {"k_render": (render_kernel_bytes(F, P, C, coeff_px), float(render_ms.mean()))}
+    models["k_scatter_staged"] = (scatter_kernel_bytes(F, C), float(scatter_ms.mean()))
+    dom = max(models, key=lambda k: models[k][1])
+    dom_ms = models[dom][1]
+    roof = roofline(b_alg, dom, dom_ms, None if glass else measured_traffic(dom, workload_key(args)))
+    # each kernel's own byte model (what it reads and writes) over its own time: how close each runs to the memory
+    # system's rate, which is not the method's roofline (the binning's bytes are not algorithmic)
+    kernel_rates = {k: {"model_bytes": by, "ms": ms, "GBps": by / (ms * 1e-3) / 1e9,
+                        "frac": by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS} for k, (by, ms) in models.items()}
 
     line = {
         "metric": METRIC,
@@ -257,7 +317,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": args.dtype,
         "data": "synthetic",
         "config": {"workload": ("glass + particles 3840x2160, 2-4 glass layers + Poisson(24) particles/px, three "
                                 "visibility channels" if glass else
@@ -273,10 +333,9 @@ def main():
                      "render": float(render_ms.mean())},
         "path_alg_bytes": b_alg,
         "path_hbm_frac": b_alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": dom_gbs, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": dom_gbs / HBM_PEAK_GBS,
-                     "traffic": None if glass else measured_traffic(dom, workload_key(args)),
-                     "alg_bytes_per_launch": dom_bytes, "avg_ms": dom_ms},
+        "roofline": roof,
+        "kernel_rates": kernel_rates,
+        "binning_rate_frac": kernel_rates["k_scatter_staged"]["frac"],
     }
     # coefficient and colour updates of the tile kernel: LDS FP64 atomics, 2 per channel for the endpoint masses
     # and 3 for the colour sums per fragment (the clock and CU count are the published ones; the ceiling is what a

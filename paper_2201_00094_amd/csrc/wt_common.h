@@ -22,25 +22,17 @@ __device__ __forceinline__ float widen<__half>(__half v) { return __half2float(v
 template <>
 __device__ __forceinline__ float widen<bf16_t>(bf16_t v) { return __uint_as_float((uint32_t)v.u << 16); }
 
-// Round to the storage type, to nearest even.
+// Round an FP64 on-chip sum to the storage type once, to nearest even (FP32 by the hardware conversion, FP16 and
+// BF16 on the FP64 bit pattern).
 template <typename T>
-__device__ __forceinline__ T narrow(float v);
+__device__ __forceinline__ T narrow_d(double v);
 template <>
-__device__ __forceinline__ float narrow<float>(float v) { return v; }
+__device__ __forceinline__ float narrow_d<float>(double v) { return (float)v; }
 template <>
-__device__ __forceinline__ __half narrow<__half>(float v) { return __float2half_rn(v); }
+__device__ __forceinline__ __half narrow_d<__half>(double v) { return __ushort_as_half(round_f64_bits<10, 15>(v)); }
 template <>
-__device__ __forceinline__ bf16_t narrow<bf16_t>(float v) {
-  uint32_t u = __float_as_uint(v);
-  bf16_t r;
-  if ((u & 0x7fffffffu) > 0x7f800000u) {
-    r.u = (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
-  } else {
-    u += 0x7fffu + ((u >> 16) & 1u);
-    r.u = (uint16_t)(u >> 16);
-  }
-  return r;
-}
+__device__ __forceinline__ bf16_t narrow_d<bf16_t>(double v) { return bf16_t{round_f64_bits<7, 127>(v)}; }
+
 
 // E5B9G9R9 coefficient storage (section 2.1): one 32-bit word per coefficient index holds the magnitudes of the
 // three channels' coefficients, a shared 5-bit exponent (bias 15) in bits 27-31 and 9-bit mantissas without an

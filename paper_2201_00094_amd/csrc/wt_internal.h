@@ -81,6 +81,35 @@ __host__ __device__ inline float neg_log1m(float al) {
 #endif
 }
 
+// Round an FP64 value to a narrower binary format once, to nearest with ties to even, on its bit pattern (no
+// intermediate FP32 rounding, which could land a value that lies just off a midpoint of the narrow format exactly
+// on it). The format has MB explicit mantissa bits and exponent bias BIAS (its smallest normal exponent is
+// 1 - BIAS); the result is the format's bit pattern: signed zero, subnormals, overflow to infinity, quiet NaN.
+// FP16: MB = 10, BIAS = 15; BF16: MB = 7, BIAS = 127.
+template <int MB, int BIAS>
+__host__ __device__ inline uint16_t round_f64_bits(double v) {
+  uint64_t u;
+  __builtin_memcpy(&u, &v, 8);
+  constexpr int EB = 15 - MB;                                   // exponent bits of the 16-bit format
+  constexpr uint32_t kInf = ((1u << EB) - 1u) << MB;
+  const uint32_t sign = (uint32_t)(u >> 48) & 0x8000u;
+  const uint64_t a = u & 0x7fffffffffffffffull;
+  if (a >= 0x7ff0000000000000ull) return (uint16_t)(sign | kInf | (a > 0x7ff0000000000000ull ? (1u << (MB - 1)) : 0u));
+  if (a < 0x0010000000000000ull) return (uint16_t)sign;         // zero or an FP64 subnormal: far below the format
+  const int e = (int)(a >> 52) - 1023;                          // |v| = m 2^(e - 52), m in [2^52, 2^53)
+  if (e > BIAS) return (uint16_t)(sign | kInf);
+  const uint64_t m = (a & 0x000fffffffffffffull) | 0x0010000000000000ull;
+  const int emin = 1 - BIAS;
+  const int shift = 52 - MB + (e < emin ? emin - e : 0);        // bits of m below the result's last place
+  if (shift >= 64) return (uint16_t)sign;                       // below half the smallest subnormal
+  const uint64_t q0 = m >> shift, rem = m & ((1ull << shift) - 1ull), half = 1ull << (shift - 1);
+  const uint64_t q = q0 + ((rem > half || (rem == half && (q0 & 1ull))) ? 1ull : 0ull);
+  // normal: biased exponent field plus the mantissa without its leading one (a carry out of the mantissa moves
+  // into the exponent); subnormal: q itself (q = 2^MB is the smallest normal)
+  const uint64_t bits = e >= emin ? ((uint64_t)(e + BIAS) << MB) + q - (1ull << MB) : q;
+  return (uint16_t)(sign | (bits >= kInf ? kInf : (uint32_t)bits));
+}
+
 // Frame geometry as the kernels see it.
 struct Geom {
   uint32_t W, H, P;      // frame

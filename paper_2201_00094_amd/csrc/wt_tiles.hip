@@ -247,7 +247,7 @@ __device__ __forceinline__ void coeffs_to_cells(const Geom& g, const TileRef& r,
     TS s[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) {
-      s[m] = narrow<TS>((float)lc64[(c * M + m) * TP + lp]);
+      s[m] = narrow_d<TS>(lc64[(c * M + m) * TP + lp]);
       v[m] = widen<TS>(s[m]);
     }
     uint64_t p;
@@ -361,7 +361,7 @@ __device__ __forceinline__ void ep_render_convert(const Geom& g, const TileRef& 
     TS s[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) {
-      s[m] = narrow<TS>((float)cf[m]);
+      s[m] = narrow_d<TS>(cf[m]);
       v[m] = widen<TS>(s[m]);
     }
     uint64_t p;
@@ -528,7 +528,7 @@ __device__ __forceinline__ void ep_build_store(const Geom& g, const TileRef& r, 
   TS* gp = coeffs + (p * C + c) * M;
   TS s[M];
 #pragma unroll
-  for (int m = 0; m < M; ++m) s[m] = narrow<TS>((float)(cf[m] + (acc_t)widen<TS>(gp[m])));
+  for (int m = 0; m < M; ++m) s[m] = narrow_d<TS>(cf[m] + (acc_t)widen<TS>(gp[m]));
   store_row<TS, M>(gp, s);
 }
 
@@ -625,9 +625,9 @@ __device__ __forceinline__ void coeff_tile_io(const Geom& g, const TileRef& r, T
       if (MODE == 0) {
         *l = in ? (T)widen<TS>(gp[e]) : (T)0;
       } else if (MODE == 1) {
-        if (in) gp[e] = narrow<TS>((float)*l);
+        if (in) gp[e] = narrow_d<TS>((double)*l);
       } else {
-        const TS s = narrow<TS>((float)*l);
+        const TS s = narrow_d<TS>((double)*l);
         *l = (T)widen<TS>(s);
         if (in && gp) gp[e] = s;
       }

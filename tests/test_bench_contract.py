@@ -39,3 +39,23 @@ def test_traffic_is_keyed_to_the_sources():
     """A counter summary taken on other kernel sources is not reported."""
     assert len(bench.sources_digest()) == 64
     assert bench.measured_traffic("k_scatter_staged", "no_such_workload") is None
+
+
+def test_roofline_is_the_path_bytes_over_the_dominant_kernel():
+    """achieved = the path's algorithmic bytes per frame over the dominant kernel's mean launch time; frac = that
+    over 8 TB/s. The smoke frame's 5.134 GB over a 1.705 ms scatter is 0.376 of peak, not the scatter's own
+    48 B/fragment record model (0.47)."""
+    F, P = 132_689_233, 1920 * 1080
+    b_alg = bench.algorithmic_bytes(F, P, 1, 64)
+    r = bench.roofline(b_alg, "k_scatter_staged", 1.705, None)
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s" and r["peak"] == 8000.0
+    assert r["achieved"] == pytest.approx(b_alg / 1.705e-3 / 1e9)
+    assert r["frac"] == pytest.approx(r["achieved"] / 8000.0)
+    assert r["frac"] == pytest.approx(0.376, abs=2e-3)
+    assert r["alg_bytes_per_launch"] == b_alg and r["avg_ms"] == 1.705 and r["traffic"] is None
+    # per-fragment figure of the path: 38.7 B at rank 3, FP32
+    assert b_alg / F == pytest.approx(38.7, abs=0.05)
+
+
+def test_cpu_model_is_named():
+    assert isinstance(bench.cpu_model(), str) and bench.cpu_model()

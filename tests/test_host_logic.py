@@ -34,3 +34,68 @@ def test_neg_log1m_matches_log1p(tmp_path):
     res = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300)
     assert res.returncode == 0, res.stdout
     assert "series: max" in res.stdout
+
+
+def _round_inputs():
+    """FP64 values that exercise the FP16 and BF16 rounding: random magnitudes over both formats' ranges, the
+    midpoints between neighbouring values of each format and the FP64 values one step either side of them, the
+    subnormal ranges, the overflow edges, signed zeros, infinities and NaN."""
+    import numpy as np
+    rng = np.random.default_rng(5)
+    vals = [rng.uniform(-1, 1, 4000) * np.exp2(rng.uniform(-30, 17, 4000)),
+            rng.uniform(-1, 1, 2000) * np.exp2(rng.uniform(-140, -110, 2000))]
+    h = np.arange(0, 0x7c00, 7, dtype=np.uint16).view(np.float16).astype(np.float64)
+    hn = np.nextafter(h.astype(np.float16), np.float16(np.inf)).astype(np.float64)
+    mid16 = (h + hn) / 2
+    b = (np.arange(0, 0x7f80, 5, dtype=np.uint32) << 16).view(np.float32).astype(np.float64)
+    bn = ((np.arange(0, 0x7f80, 5, dtype=np.uint32) + 1) << 16).view(np.float32).astype(np.float64)
+    mid_b = (b + bn) / 2
+    for m in (mid16, mid_b):
+        vals += [m, np.nextafter(m, np.inf), np.nextafter(m, -np.inf), -m]
+    vals.append(np.array([0.0, -0.0, 65504.0, 65519.99, 65520.0, 65536.0, 2.0 ** -24, 2.0 ** -25, 2.0 ** -26,
+                          3 * 2.0 ** -26, 2.0 ** -14, 1e300, -1e300, 5e-324, np.inf, -np.inf, np.nan]))
+    return np.concatenate(vals)
+
+
+def _bf16_nearest(v, table):
+    """Nearest BF16 value to v (ties to the even bit pattern) by search over every finite positive BF16 value,
+    with the distances compared exactly (fractions); inf beyond the overflow threshold."""
+    import bisect
+    import math
+    from fractions import Fraction
+    a = abs(v)
+    sign = 0x8000 if math.copysign(1.0, v) < 0 else 0
+    top = Fraction(table[-1]) + Fraction(2) ** (127 - 8)  # largest finite + half its spacing
+    if math.isinf(a) or Fraction(a) >= top:
+        return 0x7f80 | sign
+    i = bisect.bisect_left(table, a)
+    cands = [k for k in (i - 1, i) if 0 <= k < len(table)]
+    best = min(cands, key=lambda k: (abs(Fraction(table[k]) - Fraction(a)), k & 1))
+    return best | sign
+
+
+@pytest.mark.skipif(not os.path.exists(HIPCC) and shutil.which("hipcc") is None, reason="hipcc not available")
+def test_round_f64_to_f16_bf16(tmp_path):
+    """The library rounds FP64 sums straight to FP16 / BF16 storage: bit-equal to NumPy's binary16 conversion of
+    the FP64 value, and to the exactly nearest BF16 value (ties to even) found by search."""
+    import numpy as np
+    exe = tmp_path / "round_check"
+    subprocess.check_call([HIPCC, "-O2", "-std=c++17", "-I", os.path.join(ROOT, "include"),
+                           "-I", os.path.join(ROOT, "paper_2201_00094_amd", "csrc"),
+                           os.path.join(ROOT, "tests", "host", "round_check.cpp"), "-o", str(exe)],
+                          stderr=subprocess.DEVNULL)
+    x = _round_inputs()
+    inp = "\n".join("%016x" % u for u in x.view(np.uint64)) + "\n"
+    res = subprocess.run([str(exe)], input=inp, capture_output=True, text=True, timeout=300)
+    assert res.returncode == 0
+    got = np.array([[int(w, 16) for w in ln.split()] for ln in res.stdout.split("\n") if ln])
+    assert got.shape == (x.size, 2)
+    with np.errstate(over="ignore"):
+        ref16 = x.astype(np.float16).view(np.uint16)
+    nan = np.isnan(x)
+    assert (got[~nan, 0] == ref16[~nan]).all()
+    assert ((got[nan, 0] & 0x7c00) == 0x7c00).all() and ((got[nan, 0] & 0x3ff) != 0).all()
+    table = list(((np.arange(0, 0x7f80, dtype=np.uint32) << 16).view(np.float32)).astype(np.float64))
+    for v, g in zip(x[~nan], got[~nan, 1]):
+        assert g == _bf16_nearest(float(v), table), (float(v), hex(g))
+    assert ((got[nan, 1] & 0x7f80) == 0x7f80).all() and ((got[nan, 1] & 0x7f) != 0).all()
