@@ -13,7 +13,8 @@
  * Conventions shared by every entry point
  *   - All pointers to per-frame data are DEVICE pointers (HIP device memory of the current device) unless a
  *     parameter says "host". The library never allocates persistent memory and never frees caller memory;
- *     scratch comes from a caller-provided device workspace sized by wt_workspace_bytes().
+ *     scratch comes from a caller-provided device workspace sized by wt_workspace_bytes(), except for
+ *     wt_render_noalloc, which uses a static per-GPU device array instead.
  *   - Every call is asynchronous on the given HIP stream (0 = the null stream) and returns once the work is
  *     enqueued. The return code reports host-side validation and launch failures only.
  *   - Errors: WT_ERR_INVALID (null pointer, bad enum, zero size), WT_ERR_RANGE (size limits: rank > 10,
@@ -162,6 +163,25 @@ wt_status wt_resolve_chromatic(const wt_frame_desc* desc, const float* accum, co
  * build/evaluate pair through a stored coefficient array would. bg_rgb is a HOST array of 3. */
 wt_status wt_render(const wt_frame_desc* desc, const wt_fragments* frags, const float* bg_rgb, void* coeffs,
                     float* out, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Bytes of the per-GPU device array that wt_render_noalloc bins into (256 MiB). */
+#define WT_SCRATCH_BYTES ((size_t)256 << 20)
+
+/* wt_render for callers that cannot allocate device memory: code under HIP graph capture, tight serving loops and
+ * harnesses that forbid hipMalloc. Same arguments, kernels and results as wt_render, without the workspace: the
+ * binned stream and the tile tables go to a static device array of WT_SCRATCH_BYTES that the library holds on every
+ * GPU it runs on until the process ends (its address is looked up once per device, on the first call with that
+ * device current). Nothing is allocated or freed, by the library or by any routine it calls.
+ *   Limit: a frame whose workspace (wt_workspace_bytes(desc, frags->count) without the gradient's layout) exceeds
+ *   WT_SCRATCH_BYTES is refused with WT_ERR_RANGE before anything is enqueued: about 9.5 million fragments at one
+ *   channel (28 bytes per binned fragment) and 7.4 million at three (36 bytes), half as many for frames of more than
+ *   4096 screen tiles (binned in two levels, each with its own copy).
+ *   Sharing: every call on one GPU uses that GPU's one array, which keeps the last call's contents (each call clears
+ *   what it needs zeroed with its own fill kernels). Calls that overlap in time on one GPU (on different streams, or
+ *   from different threads without ordering) race on the array: the caller serialises them, for example on one
+ *   stream. The drop count of such a call is not reported (wt_dropped_count reads a caller's workspace). */
+wt_status wt_render_noalloc(const wt_frame_desc* desc, const wt_fragments* frags, const float* bg_rgb, void* coeffs,
+                            float* out, hipStream_t stream);
 
 /* The build, evaluate and resolve of wt_render over a stream already binned into ws by wt_bin (same desc and
  * ws_bytes). Writes out[P][3] and, if coeffs is not NULL, the coefficients (both overwritten). */

@@ -6,7 +6,6 @@ if the library has not been built.
 """
 from ._lib import WTError, load as load_library  # noqa: F401
 from .wt import (FrameSpec, Fragments, Workspace, backward, bin, bin_count, bin_scatter, build,  # noqa: F401
-                 build_binned, dropped_count,
-                 evaluate, evaluate_binned, render, render_binned, render_temporal, render_temporal_binned,
-                 resolve, resolve_chromatic, workspace_bytes)
+                 build_binned, dropped_count, evaluate, evaluate_binned, render, render_binned, render_noalloc,
+                 render_temporal, render_temporal_binned, resolve, resolve_chromatic, workspace_bytes)
 from .autograd import WaveletComposite, composite  # noqa: F401

@@ -13,6 +13,7 @@ STATUS_NAMES = {0: "WT_OK", -1: "WT_ERR_INVALID", -2: "WT_ERR_RANGE", -3: "WT_ER
 WT_F32, WT_F16, WT_BF16, WT_E5B9G9R9 = 0, 1, 2, 3
 WT_TIGHT_DEPTH = 1
 WT_TEMPORAL = 2
+WT_SCRATCH_BYTES = 256 << 20  # the static device array behind wt_render_noalloc
 
 
 class FrameDesc(C.Structure):
@@ -42,6 +43,7 @@ SIGNATURES = {
     "wt_resolve": (C.c_int, [_D, _vp, C.POINTER(C.c_float), _vp, _st]),
     "wt_resolve_chromatic": (C.c_int, [_D, _vp, _vp, _vp, C.c_float, C.c_uint32, _vp, _st]),
     "wt_render": (C.c_int, [_D, _F, C.POINTER(C.c_float), _vp, _vp, _vp, _sz, _st]),
+    "wt_render_noalloc": (C.c_int, [_D, _F, C.POINTER(C.c_float), _vp, _vp, _st]),
     "wt_render_binned": (C.c_int, [_D, _vp, _sz, C.POINTER(C.c_float), _vp, _vp, _st]),
     "wt_render_temporal": (C.c_int, [_D, _F, C.POINTER(C.c_float), _vp, _vp, _vp, _vp, _vp, _sz, _st]),
     "wt_render_temporal_binned": (C.c_int, [_D, _vp, _sz, C.POINTER(C.c_float), _vp, _vp, _vp, _vp, _st]),

@@ -4,9 +4,14 @@
 #include <stdio.h>
 
 #include <cmath>
+#include <mutex>
 #include <string>
 
 #include "wt_internal.h"
+
+// Workspace of wt_render_noalloc: one copy per GPU, held until the process ends. Host code reaches it only through
+// the device address that hipGetSymbolAddress returns for the current device (scratch_here below).
+static __device__ __align__(256) unsigned char scratch[WT_SCRATCH_BYTES];
 
 namespace {
 
@@ -85,6 +90,30 @@ wt_status check_lds(const wt::Geom& g) {
     wt_status st_ = (expr);          \
     if (st_ != WT_OK) return st_;    \
   } while (0)
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_at[kMaxDevices];  // device address of scratch on device d, once looked up
+
+// Device address of the current device's scratch array, looked up with hipGetSymbolAddress on the first call per
+// device (with that device current) and kept.
+wt_status scratch_here(void** ptr) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "wt_render_noalloc (hipGetDevice)");
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(WT_ERR_UNSUPPORTED, "wt_render_noalloc: device %d is beyond the %d devices tracked", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_at[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "wt_render_noalloc (hipGetSymbolAddress)");
+    if (!p) return fail(WT_ERR_HIP, "wt_render_noalloc: hipGetSymbolAddress gave a null address");
+    g_scratch_at[dev] = p;
+  }
+  *ptr = g_scratch_at[dev];
+  return WT_OK;
+}
 
 }  // namespace
 
@@ -217,6 +246,28 @@ wt_status wt_render(const wt_frame_desc* desc, const wt_fragments* frags, const 
   if (e != hipSuccess) return hip_fail(e, "wt_render (bin)");
   e = wt::launch_render(g, wt::binned_view(g, l, ws, false), bg_rgb, coeffs, out, stream);
   if (e != hipSuccess) return hip_fail(e, "wt_render");
+  return WT_OK;
+}
+
+wt_status wt_render_noalloc(const wt_frame_desc* desc, const wt_fragments* frags, const float* bg_rgb, void* coeffs,
+                            float* out, hipStream_t stream) {
+  WT_TRY(check_desc(desc));
+  WT_TRY(check_frags(frags));
+  if (!bg_rgb || !out) return fail(WT_ERR_INVALID, "bg_rgb or out is NULL");
+  const wt::Geom g = wt::make_geom(*desc);
+  WT_TRY(check_lds(g));
+  const size_t need = wt::make_layout(g, frags->count).total;
+  if (need > WT_SCRATCH_BYTES)
+    return fail(WT_ERR_RANGE, "wt_render_noalloc: %llu fragments need %zu bytes of scratch, the static array holds %zu",
+                (unsigned long long)frags->count, need, (size_t)WT_SCRATCH_BYTES);
+  void* ws = nullptr;
+  WT_TRY(scratch_here(&ws));
+  wt::Layout l;
+  WT_TRY(check_ws(g, ws, WT_SCRATCH_BYTES, frags->count, &l));
+  hipError_t e = wt::launch_bin(g, *frags, ws, l, false, stream);
+  if (e != hipSuccess) return hip_fail(e, "wt_render_noalloc (bin)");
+  e = wt::launch_render(g, wt::binned_view(g, l, ws, false), bg_rgb, coeffs, out, stream);
+  if (e != hipSuccess) return hip_fail(e, "wt_render_noalloc");
   return WT_OK;
 }
 

@@ -247,6 +247,19 @@ def render(spec: FrameSpec, frags: Fragments, bg, ws: Workspace, out: torch.Tens
     return out
 
 
+def render_noalloc(spec: FrameSpec, frags: Fragments, bg, out: torch.Tensor, coeffs: torch.Tensor = None,
+                   stream=None) -> torch.Tensor:
+    """:func:`render` without a workspace: the library bins into its own static per-GPU array (for callers that
+    cannot allocate, e.g. under graph capture). ``out`` is required, so the call allocates nothing."""
+    _check(out, (torch.float32,), (spec.pixels, 3), "out")
+    if coeffs is not None:
+        _check(coeffs, (TORCH_DTYPES[spec.dtype],), spec.coeff_shape(), "coeffs")
+    _lib.check(_lib.load().wt_render_noalloc(C.byref(spec.c_desc()), C.byref(frags.c_struct(spec.channels)),
+                                             _lib.bg3(bg), _ptr(coeffs), _ptr(out), _stream(stream)),
+               "wt_render_noalloc")
+    return out
+
+
 def render_binned(spec: FrameSpec, ws: Workspace, bg, out: torch.Tensor, coeffs: torch.Tensor = None, stream=None):
     """Build, evaluate and resolve of a stream already binned into ``ws`` by :func:`bin`."""
     _require_binned(ws, spec, "render_binned")

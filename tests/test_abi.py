@@ -184,3 +184,23 @@ def test_every_description_sizes_and_validates(lib):
                             st = lib.wt_render_temporal_binned(C.byref(d), ws, 16, bg, None, None, None, ws, None)
                             assert st in errs, (rank, ch, dt, w, h, st, _err(lib))
     assert n_valid > 500
+
+
+def test_noalloc_refuses_frames_beyond_its_array(lib):
+    # validation and the size limit come before the library looks up its static array (no GPU needed)
+    d = _lib.desc(1920, 1080, 3)
+    ok_ptr = C.c_void_p(8)
+    too_many = _lib.Fragments(_lib.WT_SCRATCH_BYTES // 28 + 1, 8, 8, 8, 8)
+    assert lib.wt_render_noalloc(C.byref(d), C.byref(too_many), _lib.bg3((0, 0, 0)), None, ok_ptr,
+                                 None) == _lib.WT_ERR_RANGE
+    assert "scratch" in _err(lib)
+    assert lib.wt_render_noalloc(None, C.byref(too_many), _lib.bg3((0, 0, 0)), None, ok_ptr,
+                                 None) == _lib.WT_ERR_INVALID
+    assert lib.wt_render_noalloc(C.byref(d), C.byref(too_many), None, None, ok_ptr, None) == _lib.WT_ERR_INVALID
+    assert lib.wt_render_noalloc(C.byref(d), C.byref(too_many), _lib.bg3((0, 0, 0)), None, None,
+                                 None) == _lib.WT_ERR_INVALID
+    # three channels at 4K bin in two levels (two record copies): about a quarter of the one-channel limit
+    d3 = _lib.desc(3840, 2160, 3, channels=3)
+    n3 = _lib.Fragments(_lib.WT_SCRATCH_BYTES // 72 + 1, 8, 8, 8, 8)
+    assert lib.wt_render_noalloc(C.byref(d3), C.byref(n3), _lib.bg3((0, 0, 0)), None, ok_ptr,
+                                 None) == _lib.WT_ERR_RANGE
