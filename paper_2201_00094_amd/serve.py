@@ -4,11 +4,17 @@ Frames of different sizes, ranks and coefficient storage types arrive as request
 as soon as an execution slot is free and its HBM footprint fits the remaining budget, launches it on that slot's
 HIP stream, and keeps polling the device: requests that arrive while others run are admitted as slots and memory
 free up, and their work overlaps on the GPU. Per-slot buffers (workspace and coefficient array) stay resident and
-are reused across requests of the same frame description. Latency is measured from arrival (submit) to the moment
-the completion event is observed.
+are reused across requests; the budget counts them as well as the requests in flight. Latency is measured from
+arrival (submit) to the moment the completion event is observed.
+
+A queued request can be cancelled (``Future.cancel()``, until it is admitted) or given an admission deadline
+(``FrameRequest.timeout``: seconds from submit; a request still queued then fails with :class:`RequestTimeout`).
+Work already launched on the GPU runs to completion.
 
 The scheduler is independent of the device: it drives an executor with ``footprint``, ``launch``, ``done`` and
-``finish``. :class:`GpuExecutor` runs the library; tests drive the scheduler with a CPU executor.
+``finish``, and optionally ``prepare`` (called on the submitting thread; its token is passed to ``launch``) and
+``growth`` / ``resident_bytes`` / ``trim`` (resident per-slot buffers). :class:`GpuExecutor` runs the library;
+tests drive the scheduler with CPU executors.
 """
 from __future__ import annotations
 
@@ -32,6 +38,7 @@ class FrameRequest:
     bg: tuple = (0.0, 0.0, 0.0)
     want_coeffs: bool = False
     tag: object = None
+    timeout: float = None         # admission deadline in seconds from submit (None: wait as long as it takes)
 
     @property
     def pixels(self) -> int:
@@ -61,12 +68,17 @@ class RequestTooLarge(RuntimeError):
     pass
 
 
+class RequestTimeout(TimeoutError):
+    pass
+
+
 @dataclass
 class _Pending:
     req: FrameRequest
     fut: Future
     t_submit: float
     footprint: int
+    token: object = None
     bypassed: int = 0
 
 
@@ -83,6 +95,8 @@ class ServerStats:
     completed: int = 0
     rejected: int = 0
     failed: int = 0      # launch or completion raised; reported on the request's future
+    cancelled: int = 0   # cancelled by the client while queued
+    timed_out: int = 0   # still queued at their admission deadline
     fragments: int = 0
     latencies: list = field(default_factory=list)
     waits: list = field(default_factory=list)   # arrival to admission
@@ -96,7 +110,7 @@ class ServerStats:
         span = max(self.last_done - self.first_submit, 1e-12)
         wait = np.array(self.waits) * 1e3 if self.waits else np.zeros(1)
         return {"completed": self.completed, "rejected": self.rejected, "failed": self.failed,
-                "fragments": self.fragments,
+                "cancelled": self.cancelled, "timed_out": self.timed_out, "fragments": self.fragments,
                 "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                 "mean_ms": float(lat.mean()), "fragments_per_s": self.fragments / span,
                 "queued": int((wait > 1.0).sum()), "wait_p50_ms": float(np.percentile(wait, 50)),
@@ -106,7 +120,11 @@ class ServerStats:
 
 class Server:
     """Admission by HBM footprint and free slots; FIFO with bounded back-filling (a request that does not fit
-    may be passed by later, smaller ones at most ``max_bypass`` times, after which admission waits for it)."""
+    may be passed by later, smaller ones at most ``max_bypass`` times, after which admission waits for it).
+
+    The budget holds the footprints of the requests in flight plus the executor's resident per-slot buffers
+    (``resident_bytes``), including what a slot's buffers must grow by to take the request (``growth``). When a
+    request does not fit, the buffers of idle slots are released (``trim``) before it is left waiting."""
 
     def __init__(self, executor, slots: int = 3, budget_bytes: int = 96 << 30, max_bypass: int = 8,
                  poll_interval: float = 0.0002, clock=time.perf_counter):
@@ -121,6 +139,7 @@ class Server:
         self._running: list[_Running] = []
         self._free_slots = list(range(self.slots))
         self._bytes = 0
+        self._prep = hasattr(executor, "prepare")
         self._cv = threading.Condition()
         self._stop = False
         self._thread = threading.Thread(target=self._loop, name="wt-serve", daemon=True)
@@ -128,18 +147,27 @@ class Server:
 
     # -- client side --------------------------------------------------------------------------------------
     def submit(self, req: FrameRequest) -> Future:
+        """Queue a request; the future resolves to its :class:`FrameResult`. The executor's ``prepare`` runs here,
+        on the submitting thread (the GPU executor orders the request after the work this thread's current stream
+        has queued on its inputs)."""
         fut: Future = Future()
         t = self.clock()
         fp = int(self.ex.footprint(req))
+        fresh = int(self._growth(None, req))
         with self._cv:
             if self._stop:
                 raise RuntimeError("the server is closed")
             self.stats.first_submit = min(self.stats.first_submit, t)
-            if fp > self.budget:
+            if fp + fresh > self.budget:
                 self.stats.rejected += 1
-                fut.set_exception(RequestTooLarge("request needs %d bytes, the budget is %d" % (fp, self.budget)))
+                fut.set_exception(RequestTooLarge("request needs %d bytes, the budget is %d" % (fp + fresh,
+                                                                                                self.budget)))
                 return fut
-            self._queue.append(_Pending(req, fut, t, fp))
+        token = self.ex.prepare(req) if self._prep else None
+        with self._cv:
+            if self._stop:
+                raise RuntimeError("the server is closed")
+            self._queue.append(_Pending(req, fut, t, fp, token))
             self._cv.notify()
         return fut
 
@@ -162,17 +190,64 @@ class Server:
             time.sleep(self.poll_interval)
 
     # -- scheduler ----------------------------------------------------------------------------------------
+    def _growth(self, slot, req) -> int:
+        g = getattr(self.ex, "growth", None)
+        return int(g(slot, req)) if g else 0
+
+    def _resident(self) -> int:
+        r = getattr(self.ex, "resident_bytes", None)
+        return int(r()) if r else 0
+
+    def _held(self) -> int:
+        return self._bytes + self._resident()
+
+    def _fit_slot(self, p):
+        """A free slot that can take p within the budget (the one whose buffers grow least), or None. Releases the
+        buffers of other idle slots when that makes the request fit."""
+        slot = min(self._free_slots, key=lambda k: self._growth(k, p.req))
+        need = p.footprint + self._growth(slot, p.req)
+        if self._held() + need <= self.budget:
+            return slot
+        trim = getattr(self.ex, "trim", None)
+        if trim is not None:
+            for k in self._free_slots:
+                if k != slot:
+                    trim(k)
+            need = p.footprint + self._growth(slot, p.req)
+            if self._held() + need <= self.budget:
+                return slot
+        return None
+
+    def _drop_expired_locked(self):
+        now = self.clock()
+        keep = collections.deque()
+        for p in self._queue:
+            if p.fut.cancelled():
+                self.stats.cancelled += 1
+            elif p.req.timeout is not None and now - p.t_submit > p.req.timeout:
+                self.stats.timed_out += 1
+                p.fut.set_exception(RequestTimeout("request still queued %.3f s after submit (timeout %.3f s)" %
+                                                   (now - p.t_submit, p.req.timeout)))
+            else:
+                keep.append(p)
+        self._queue = keep
+
     def _admit_locked(self):
+        self._drop_expired_locked()
         i = 0
         while i < len(self._queue) and self._free_slots:
             p = self._queue[i]
-            if self._bytes + p.footprint <= self.budget:
+            slot = self._fit_slot(p)
+            if slot is not None:
                 del self._queue[i]
-                slot = self._free_slots.pop()
+                if not p.fut.set_running_or_notify_cancel():  # cancelled by the client meanwhile
+                    self.stats.cancelled += 1
+                    continue
+                self._free_slots.remove(slot)
                 self._bytes += p.footprint
                 t = self.clock()
                 try:
-                    handle = self.ex.launch(p.req, slot)
+                    handle = self.ex.launch(p.req, slot, p.token) if self._prep else self.ex.launch(p.req, slot)
                 except Exception as e:  # launch failure: report to the client, release resources
                     self._bytes -= p.footprint
                     self._free_slots.append(slot)
@@ -181,7 +256,7 @@ class Server:
                     continue
                 self._running.append(_Running(p, slot, handle, t))
                 self.stats.max_inflight = max(self.stats.max_inflight, len(self._running))
-                self.stats.max_bytes_inflight = max(self.stats.max_bytes_inflight, self._bytes)
+                self.stats.max_bytes_inflight = max(self.stats.max_bytes_inflight, self._held())
                 # requests ahead of this one were passed over once more
                 for q in list(self._queue)[:i]:
                     q.bypassed += 1
@@ -232,18 +307,13 @@ class Server:
             time.sleep(self.poll_interval)
 
 
-def request_footprint(width, height, rank, channels, dtype, count, stream_bytes=True):
-    """HBM bytes a request holds while it runs: its fragment stream (if counted), the binning workspace, the
-    coefficient array and the composite."""
+def _slot_bytes(spec, count):
+    """(workspace, coefficient) bytes a slot needs for a frame of this description and fragment count."""
     from . import wt as _wt
-    spec = _wt.FrameSpec(width, height, rank, channels, dtype)
-    sbytes = {"f32": 4, "f16": 2, "bf16": 2, "e5b9g9r9": 4}[dtype]
-    ws = _wt.workspace_bytes(spec, max(count, 1))
-    fr = count * (4 + 4 + 4 * channels + 12) if stream_bytes else 0
-    coeff_elems = 1
+    n_el = 1
     for d in spec.coeff_shape():
-        coeff_elems *= d
-    return fr + ws + coeff_elems * sbytes + spec.pixels * 12
+        n_el *= d
+    return _wt.workspace_bytes(spec, max(count, 1)), n_el * _wt.TORCH_DTYPES[spec.dtype].itemsize
 
 
 class _WsView:
@@ -258,8 +328,15 @@ class _WsView:
 
 class GpuExecutor:
     """Runs requests on the GPU: one HIP stream per slot (default priority); per slot one resident workspace and
-    one resident coefficient buffer, grown to the largest request seen and shared by every frame description;
-    completion observed through an event recorded after the request's work."""
+    one resident coefficient buffer, grown to the largest request it has taken (and released by ``trim`` when the
+    scheduler needs the memory), shared by every frame description; completion observed through an event recorded
+    after the request's work.
+
+    Streams: ``prepare`` runs on the submitting thread, allocates the request's result buffers from that thread's
+    current stream and records an event there; the slot stream waits for that event before reading the fragments,
+    so inputs still being produced on the client's stream are complete. The fragment and result tensors are
+    marked as used by the slot stream (``record_stream``), so the caching allocator does not hand their memory to
+    other work before the slot's kernels are done with it, whichever stream frees them."""
 
     def __init__(self, slots: int = 3, device="cuda"):
         import torch
@@ -269,37 +346,76 @@ class GpuExecutor:
         self.ws = [None] * slots
         self.cf = [None] * slots
 
+    def _spec(self, req):
+        from . import wt as _wt
+        return _wt.FrameSpec(req.width, req.height, req.rank, req.channels, req.dtype)
+
     def footprint(self, req: FrameRequest) -> int:
-        return request_footprint(req.width, req.height, req.rank, req.channels, req.dtype, req.count)
+        """Bytes the request holds besides the slot's resident buffers: its fragment stream, its composite and,
+        when asked for, its coefficient copy."""
+        spec = self._spec(req)
+        fr = req.count * (4 + 4 + 4 * req.channels + 12)
+        return fr + spec.pixels * 12 + (_slot_bytes(spec, req.count)[1] if req.want_coeffs else 0)
+
+    def growth(self, slot, req: FrameRequest) -> int:
+        """Bytes slot's resident buffers must grow by to take req (the full need for slot None or an empty slot)."""
+        need_ws, need_cf = _slot_bytes(self._spec(req), req.count)
+        have_ws = 0 if slot is None or self.ws[slot] is None else self.ws[slot].numel()
+        have_cf = 0 if slot is None or self.cf[slot] is None else self.cf[slot].numel()
+        return max(0, need_ws - have_ws) + max(0, need_cf - have_cf)
+
+    def resident_bytes(self) -> int:
+        return sum(b.numel() for b in self.ws + self.cf if b is not None)
+
+    def trim(self, slot: int):
+        """Release an idle slot's buffers (its stream's earlier work is ordered before any reuse of the memory)."""
+        self.ws[slot] = None
+        self.cf[slot] = None
+
+    def prepare(self, req: FrameRequest):
+        torch = self.torch
+        spec = self._spec(req)
+        from . import wt as _wt
+        client = torch.cuda.current_stream(self.device)
+        out = torch.empty((spec.pixels, 3), dtype=torch.float32, device=self.device)
+        kept = torch.empty(spec.coeff_shape(), dtype=_wt.TORCH_DTYPES[spec.dtype], device=self.device) \
+            if req.want_coeffs else None
+        ready = torch.cuda.Event()
+        ready.record(client)
+        return (out, kept, ready)
 
     def _buffers(self, slot, req, spec):
         from . import wt as _wt
         torch = self.torch
-        need_ws = _wt.workspace_bytes(spec, max(req.count, 1))
-        n_el = 1
-        for d in spec.coeff_shape():
-            n_el *= d
-        need_cf = n_el * _wt.TORCH_DTYPES[spec.dtype].itemsize
+        need_ws, need_cf = _slot_bytes(spec, req.count)
         with torch.cuda.stream(self.streams[slot]):
             if self.ws[slot] is None or self.ws[slot].numel() < need_ws:
+                self.ws[slot] = None
                 self.ws[slot] = torch.empty(need_ws, dtype=torch.uint8, device=self.device)
             if self.cf[slot] is None or self.cf[slot].numel() < need_cf:
+                self.cf[slot] = None
                 self.cf[slot] = torch.empty(need_cf, dtype=torch.uint8, device=self.device)
         ws = _WsView(self.ws[slot], self.ws[slot].numel())
         coeffs = self.cf[slot][:need_cf].view(_wt.TORCH_DTYPES[spec.dtype]).view(spec.coeff_shape())
         return ws, coeffs
 
-    def launch(self, req: FrameRequest, slot: int):
+    def launch(self, req: FrameRequest, slot: int, token=None):
         from . import wt as _wt
         torch = self.torch
-        spec = _wt.FrameSpec(req.width, req.height, req.rank, req.channels, req.dtype)
+        if token is None:
+            token = self.prepare(req)
+        out, kept, ready = token
+        spec = self._spec(req)
         s = self.streams[slot]
-        s.wait_stream(torch.cuda.current_stream(self.device))  # inputs produced on the client's stream
+        s.wait_event(ready)  # the inputs as the client's stream left them at submit
+        for t in (req.frags.pixel, req.frags.depth, req.frags.alpha, req.frags.rgb, out, kept):
+            if t is not None:
+                t.record_stream(s)
         ws, coeffs = self._buffers(slot, req, spec)
         with torch.cuda.stream(s):
-            out = torch.empty((spec.pixels, 3), dtype=torch.float32, device=self.device)
             _wt.render(spec, req.frags, req.bg, ws, out=out, coeffs=coeffs, stream=s)
-            kept = coeffs.clone() if req.want_coeffs else None
+            if kept is not None:
+                kept.copy_(coeffs)
             ev = torch.cuda.Event()
             ev.record(s)
         return (ev, out, kept)

@@ -59,3 +59,25 @@ def test_roofline_is_the_path_bytes_over_the_dominant_kernel():
 
 def test_cpu_model_is_named():
     assert isinstance(bench.cpu_model(), str) and bench.cpu_model()
+
+
+def test_overlap_summary_of_a_kernel_trace(tmp_path):
+    """The serving overlap figures from a kernel trace: busy time is the union of kernel intervals, overlap the
+    time kernels of two streams run together; torch's own kernels are left out."""
+    import csv
+    p = tmp_path / "kernel_trace.csv"
+    rows = [("KERNEL_DISPATCH", 1, "void wt::k_render<1, float, true>(x)", 0, 100),
+            ("KERNEL_DISPATCH", 2, "wt::k_scan(x)", 50, 150),
+            ("KERNEL_DISPATCH", 1, "void wt::k_hist_lds<256>(x)", 200, 300),
+            ("KERNEL_DISPATCH", 3, "void at::native::fill(x)", 0, 1000)]
+    with open(p, "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(["Kind", "Stream_Id", "Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        w.writerows(rows)
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--mode", "overlap", "--trace", str(p)],
+                         capture_output=True, text=True, timeout=120)
+    import json
+    r = json.loads(out.stdout)
+    assert r["kernels"] == 3 and r["streams"] == 2 and r["max_streams_at_once"] == 2
+    assert r["busy_ms"] == pytest.approx(250e-6) and r["two_or_more_streams_ms"] == pytest.approx(50e-6)
+    assert r["kernels_overlapping_another_streams_kernel"] == 2

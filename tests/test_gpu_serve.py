@@ -58,3 +58,38 @@ def test_served_results_match_solo(orc):
         (s["completed"], worst, s["max_inflight"], s["p50_ms"], s["p99_ms"]))
     assert s["completed"] == len(futs)
     assert s["max_inflight"] >= 2
+
+
+def test_fragments_produced_on_a_side_stream(orc):
+    """A client that produces a request's fragments on its own stream and submits while that work is still
+    queued: the slot stream is ordered after it (the event recorded at submit on the client's current stream), and
+    the composite matches the frame rendered alone after a synchronisation."""
+    import torch
+    import paper_2201_00094_amd as wt
+    from paper_2201_00094_amd.serve import FrameRequest, GpuExecutor, Server
+
+    f = synth.frame_c4(seed=7, width=320, height=200, rank=3, mean=24.0)
+    src = wt.Fragments.from_numpy(f.pixel, f.depth, f.alpha, f.rgb)
+    spec = wt.FrameSpec(f.width, f.height, f.rank)
+    solo = wt.render(spec, src, f.bg, wt.Workspace(spec, f.count))
+    torch.cuda.synchronize()
+    say("case serving: fragments from a side stream, %d fragments" % f.count)
+    srv = Server(GpuExecutor(slots=2), slots=2, budget_bytes=8 << 30)
+    side = torch.cuda.Stream()
+    futs = []
+    with torch.cuda.stream(side):
+        for rep in range(3):
+            torch.cuda._sleep(20_000_000)  # keeps the copies below queued when submit returns
+            dst = wt.Fragments(torch.empty_like(src.pixel), torch.empty_like(src.depth),
+                               torch.empty_like(src.alpha), torch.empty_like(src.rgb))
+            for a, b in ((dst.pixel, src.pixel), (dst.depth, src.depth), (dst.alpha, src.alpha),
+                         (dst.rgb, src.rgb)):
+                a.copy_(b, non_blocking=True)
+            futs.append(srv.submit(FrameRequest(f.width, f.height, f.rank, dst, bg=f.bg, tag=rep)))
+            del dst
+    results = [fu.result(timeout=120) for fu in futs]
+    srv.close()
+    torch.cuda.synchronize()
+    for r in results:
+        d = float((r.out - solo).abs().max())
+        assert d <= 1e-5, (r.tag, d)

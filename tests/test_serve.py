@@ -185,3 +185,117 @@ def test_poisson_trace_generator():
     assert (np.diff(t) > 0).all()
     assert 1.0 < t[-1] < 4.0  # about 2 s of arrivals at 100/s
     assert {r["rank"] for r in tr} == {3, 4} and {r["dtype"] for r in tr} == {"f32", "f16"}
+
+
+def test_cancelled_request_is_never_launched(orc):
+    ex = OracleExecutor(orc, delay=0.2)
+    srv = Server(ex, slots=1, budget_bytes=10 ** 9)
+    f_run = srv.submit(_req(1, 8, 8, tag="running"))
+    time.sleep(0.05)  # the first request holds the only slot
+    f_cancel = srv.submit(_req(2, 8, 8, tag="cancelled"))
+    f_next = srv.submit(_req(3, 8, 8, tag="next"))
+    assert f_cancel.cancel()
+    assert f_run.result(timeout=30).tag == "running"
+    assert f_next.result(timeout=30).tag == "next"
+    srv.drain(timeout=30)
+    srv.close()
+    assert f_cancel.cancelled()
+    assert srv.stats.cancelled == 1 and srv.stats.completed == 2
+    # an admitted request can no longer be cancelled
+    srv2 = Server(OracleExecutor(orc, delay=0.1), slots=1, budget_bytes=10 ** 9)
+    f = srv2.submit(_req(4, 8, 8, tag="admitted"))
+    t0 = time.time()
+    while not f.running() and time.time() - t0 < 10:
+        time.sleep(0.005)
+    assert not f.cancel()
+    assert f.result(timeout=30).tag == "admitted"
+    srv2.close()
+
+
+def test_admission_deadline_fails_a_request_still_queued(orc):
+    from paper_2201_00094_amd.serve import RequestTimeout
+    ex = OracleExecutor(orc, delay=0.3)
+    srv = Server(ex, slots=1, budget_bytes=10 ** 9)
+    f_run = srv.submit(_req(1, 8, 8, tag="running"))
+    time.sleep(0.02)
+    q = _req(2, 8, 8, tag="late")
+    q.timeout = 0.05
+    f_late = srv.submit(q)
+    patient = _req(3, 8, 8, tag="patient")
+    patient.timeout = 30.0
+    f_patient = srv.submit(patient)
+    with pytest.raises(RequestTimeout):
+        f_late.result(timeout=30)
+    assert f_run.result(timeout=30).tag == "running"
+    assert f_patient.result(timeout=30).tag == "patient"
+    srv.close()
+    assert srv.stats.timed_out == 1 and srv.stats.completed == 2
+
+
+class ResidentExecutor(OracleExecutor):
+    """Fake device whose slots keep resident buffers (as the GPU executor's workspace and coefficient arrays do):
+    a launch grows its slot to the request's need; trim releases an idle slot. Records the largest amount of
+    memory held (resident + in flight) at any launch."""
+
+    def __init__(self, orc, slots, need, **kw):
+        super().__init__(orc, **kw)
+        self.have = [0] * slots
+        self.need = need          # tag -> resident bytes the request needs
+        self.trimmed = []
+        self.inflight = 0
+        self.peak = 0
+
+    def footprint(self, req):
+        return 10
+
+    def growth(self, slot, req):
+        return max(0, self.need[req.tag] - (0 if slot is None else self.have[slot]))
+
+    def resident_bytes(self):
+        return sum(self.have)
+
+    def trim(self, slot):
+        self.trimmed.append(slot)
+        self.have[slot] = 0
+
+    def launch(self, req, slot):
+        self.have[slot] = max(self.have[slot], self.need[req.tag])
+        with self.lock:
+            self.inflight += 1
+            self.peak = max(self.peak, sum(self.have) + 10 * self.inflight)
+        fut = super().launch(req, slot)
+        fut.add_done_callback(lambda _: self._done())
+        return fut
+
+    def _done(self):
+        with self.lock:
+            self.inflight -= 1
+
+
+def test_resident_slot_buffers_count_against_the_budget(orc):
+    B = 1000
+    need = {"a": 600, "b": 450, "c": 450, "big": 2000}
+    ex = ResidentExecutor(orc, slots=2, need=need, delay=0.05)
+    srv = Server(ex, slots=2, budget_bytes=B)
+    # "a" leaves 600 bytes resident in its slot; "b" then reuses that slot, and "c" cannot take the other slot
+    # (600 + 450 + in-flight bytes > 1000) until a slot with room is free
+    fa = srv.submit(_req(1, 8, 8, tag="a"))
+    fa.result(timeout=30)
+    fb, fc = srv.submit(_req(2, 8, 8, tag="b")), srv.submit(_req(3, 8, 8, tag="c"))
+    rb, rc = fb.result(timeout=30), fc.result(timeout=30)
+    assert rc.t_admit >= rb.t_done - 1e-3 or rb.t_admit >= rc.t_done - 1e-3  # they did not overlap
+    fbig = srv.submit(_req(4, 8, 8, tag="big"))
+    with pytest.raises(RequestTooLarge):
+        fbig.result(timeout=10)
+    srv.close()
+    assert ex.peak <= B and srv.stats.max_bytes_inflight <= B
+
+
+def test_idle_slot_buffers_are_released_when_a_request_needs_the_room(orc):
+    need = {"x": 700}
+    ex = ResidentExecutor(orc, slots=2, need=need)
+    ex.have = [600, 500]  # both slots idle, left large by earlier requests
+    srv = Server(ex, slots=2, budget_bytes=1000)
+    r = srv.submit(_req(1, 8, 8, tag="x")).result(timeout=30)
+    srv.close()
+    assert r.slot == 0 and ex.trimmed == [1] and ex.peak <= 1000
