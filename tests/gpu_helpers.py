@@ -79,15 +79,17 @@ def oracle_frame(orc, f, rank=None, storage="exact", mask=None, want=("coeffs", 
                        bg=f.bg, channels=f.channels, mask=mask, want=want, storage=storage, tight=tight)
 
 
-def assert_coeffs(g, o, rel=1e-5, sel=None, what="coeffs"):
-    """Every element within rel * |oracle|; exact zeros stay zero."""
+def assert_coeffs(g, o, rel=1e-5, sel=None, what="coeffs", atol=0.0):
+    """Every element within rel * |oracle| + atol; exact zeros stay zero. atol is the storage format's smallest
+    step (its subnormal spacing) where a reduced storage is compared: below the smallest normal value one step is
+    that absolute spacing, not a fixed fraction of the value."""
     g = g.reshape(o.shape)
     if sel is not None:
         g, o = g[sel], o[sel]
     zero = o == 0
     assert (g[zero] == 0).all(), "%s: %d oracle zeros are non-zero on the GPU" % (what, int((g[zero] != 0).sum()))
     err = np.abs(g - o)
-    bad = err > rel * np.abs(o)
+    bad = err > rel * np.abs(o) + atol
     if bad.any():
         i = np.unravel_index(np.argmax(err / np.maximum(np.abs(o), 1e-300)), o.shape)
         raise AssertionError("%s: %d elements beyond %.1e relative; worst at %s: gpu %r oracle %r" %
@@ -113,22 +115,26 @@ def accum_to_oracle_layout(acc, channels):
     return acc[:, :3], acc[:, 4:7]
 
 
-def storage_out_bound(orc, rank, coeffs, accum, channels, rel, floor=1e-4):
+def storage_out_bound(orc, rank, coeffs, accum, channels, rel, floor=1e-4, atol=0.0):
     """Per-pixel bound on |composite(GPU) - composite(oracle)| when both store coefficients at reduced precision
     and may round one coefficient to neighbouring storage values (FP32 accumulation on one side, FP64 on the other,
     straddling a rounding midpoint). The composite is S + bg exp(-sum a) (section 2.1, steps 3-4); the sum of
     absorbances is exact on both sides, so storage reaches it only through each fragment's visibility
     V = exp(-A~(z)). A~ interpolates between 0 and the cell averages (section 2.3.2), so |dA~| is at most
-    E = max_j sum_m |dAbar_j/dc_m| |dc_m| with |dc_m| <= rel |c_m|, and every V, hence S, moves by a factor within
+    E = max_j sum_m |dAbar_j/dc_m| |dc_m| with |dc_m| <= rel |c_m| + atol, and every V, hence S, moves by a factor within
     exp(+-E): |d out_q| <= (exp(E) - 1) S_q. ``floor`` covers FP32 arithmetic. coeffs [P][C*M] or [P][C][M]
     (oracle, at the reduced storage), accum [P][3] (oracle); returns [P][3]."""
     M = 1 << (rank + 1)
     jac = np.abs(np.stack([orc.cells_one(rank, np.eye(M)[m]) for m in range(M)], axis=1))  # [j][m]
     c = np.abs(np.asarray(coeffs, dtype=np.float64).reshape(-1, channels, M))
-    E = (c @ jac.T).max(axis=2) * rel  # [P][C]
+    E = ((c * rel + atol) @ jac.T).max(axis=2)  # [P][C]
     if channels == 1:
         E = np.repeat(E, 3, axis=1)
     return np.expm1(E) * np.abs(np.asarray(accum, dtype=np.float64).reshape(-1, 3)) + floor
+
+
+# smallest step of each reduced storage format (its subnormal spacing)
+STORAGE_ATOL = {"f32": 0.0, "f16": 2.0 ** -24, "bf16": 2.0 ** -133}
 
 
 def assert_within(g, o, tol, sel=None, what="out"):

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_helpers import assert_close_abs, assert_coeffs, device_frags, e5_decode, say
+from gpu_helpers import STORAGE_ATOL, assert_close_abs, assert_coeffs, device_frags, e5_decode, say
 
 pytestmark = pytest.mark.gpu
 
@@ -86,7 +86,7 @@ def _check_coeffs(orc, g, f, dtype):
         tmax = np.abs(ex).max(axis=1, keepdims=True)
         assert np.all(np.abs(e5_decode(orc, g["words"]) - o) <= tmax / 255.0 * (1 + 1e-6) + 1e-30)
     else:
-        assert_coeffs(g["coeffs"], o, rel=2 * STEP[dtype] + 1e-5, what=dtype + " coeffs")
+        assert_coeffs(g["coeffs"], o, rel=2 * STEP[dtype] + 1e-5, what=dtype + " coeffs", atol=STORAGE_ATOL[dtype])
 
 
 @pytest.mark.parametrize("channels,rank,dtype", [(1, 3, "f32"), (1, 0, "f32"), (1, 4, "f16"), (1, 2, "bf16"),
