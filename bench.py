@@ -14,6 +14,7 @@ frame on the host cores.
 from __future__ import annotations
 
 import argparse
+import collections
 import csv
 import glob
 import hashlib
@@ -184,7 +185,8 @@ def main():
     ap.add_argument("--cpu-fraction", type=float, default=1.0,
                     help="share of the frame's pixels the CPU oracle baseline resolves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="frame", choices=("frame", "serve", "copy", "traffic", "precision", "chromatic"),
+    ap.add_argument("--mode", default="frame",
+                    choices=("frame", "serve", "copy", "traffic", "precision", "chromatic", "overlap"),
                     help="frame: the headline single-frame step (default); serve: the continuous-batching trace; "
                          "copy: a plain device copy of known size (calibrates the HBM byte counters); traffic: "
                          "turn rocprofv3 FETCH_SIZE / WRITE_SIZE collections into the committed traffic summary; "
@@ -203,6 +205,7 @@ def main():
                     help="traffic mode: rocprofv3 output folders of the frame and copy runs")
     ap.add_argument("--pmc-command", default="", help="traffic mode: the command the counters were taken with")
     ap.add_argument("--requests", type=int, default=500, help="serve mode: requests per trace")
+    ap.add_argument("--trace", help="overlap mode: kernel_trace.csv of a rocprofv3 --kernel-trace run of --mode serve")
     ap.add_argument("--load", default="0.5,0.8,0.95",
                     help="serve mode: arrival rates as shares of the solo capacity (comma-separated sweep)")
     ap.add_argument("--budget-gb", type=float, default=96.0,
@@ -220,6 +223,8 @@ def main():
         return run_serve(args)
     if args.mode == "copy":
         return run_copy(args)
+    if args.mode == "overlap":
+        return run_overlap(args)
     if args.mode == "traffic":
         return run_traffic(args)
     if args.mode == "precision":
@@ -402,64 +407,78 @@ def run_chromatic(args):
 
 
 def run_precision(args):
-    """Glass + particles (3840x2160, 2-4 glass layers with per-channel alpha plus Poisson(24) particles, three
-    visibility channels): one frame per coefficient storage (f32, f16, bf16, e5b9g9r9), timed, and checked on a
-    seeded pixel sample against the FP64 oracle at exact storage and against the exact A-buffer."""
+    """One frame per coefficient storage, timed, with the composite's error against the FP64 oracle at exact storage,
+    against the exact A-buffer, and against the plain FP32 storage form, over the whole frame or a seeded pixel
+    sample (``--sample-pixels``; 0 = every pixel). ``--workload smoke``: the headline frame (1920x1080, one
+    channel), storage f32/f16/bf16. ``--workload glass``: glass + particles, 3840x2160, 2-4 glass layers with
+    per-channel alpha plus Poisson(24) particles, three visibility channels, storage f32/f16/bf16/e5b9g9r9."""
     import torch
 
     import oracle
     import paper_2201_00094_amd as wt
     import synth
 
+    smoke = args.workload == "smoke"
     t0 = time.perf_counter()
-    f = synth.frame_c3(seed=args.seed, rank=args.rank)
+    f = synth.frame_c2(seed=args.seed, rank=args.rank) if smoke else synth.frame_c3(seed=args.seed, rank=args.rank)
     print("precision: generated %s, %d fragments in %.1f s" % (f.name, f.count, time.perf_counter() - t0),
           file=sys.stderr, flush=True)
-    rng = np.random.default_rng(args.seed + 5)
-    sel = np.unique(rng.choice(f.pixels, args.sample_pixels, replace=False))
-    mask = np.zeros(f.pixels, bool)
-    mask[sel] = True
-    ex = oracle.resolve(f.width, f.height, f.rank, f.pixel, f.depth, f.alpha, f.rgb, bg=f.bg, channels=3, mask=mask,
+    if args.sample_pixels <= 0 or args.sample_pixels >= f.pixels:
+        sel, mask = np.arange(f.pixels), None
+    else:
+        rng = np.random.default_rng(args.seed + 5)
+        sel = np.unique(rng.choice(f.pixels, args.sample_pixels, replace=False))
+        mask = np.zeros(f.pixels, bool)
+        mask[sel] = True
+    C = f.channels
+    t0 = time.perf_counter()
+    ex = oracle.resolve(f.width, f.height, f.rank, f.pixel, f.depth, f.alpha, f.rgb, bg=f.bg, channels=C, mask=mask,
                         want=("out",), tight=args.tight)["out"][sel]
-    ab = oracle.abuffer(f.width, f.height, f.pixel, f.depth, f.alpha, f.rgb, bg=f.bg, channels=3, mask=mask)["out"][sel]
+    ab = oracle.abuffer(f.width, f.height, f.pixel, f.depth, f.alpha, f.rgb, bg=f.bg, channels=C, mask=mask)["out"][sel]
+    print("precision: oracle and A-buffer on %d pixels in %.1f s" % (sel.size, time.perf_counter() - t0),
+          file=sys.stderr, flush=True)
     fr = wt.Fragments.from_numpy(f.pixel, f.depth, f.alpha, f.rgb)
+
+    def err(a, b):
+        e = np.abs(a - b)
+        return {"max": float(e.max()), "mean": float(e.mean()), "p99": float(np.percentile(e, 99))}
+
     res = {}
-    for dt in ("f32", "f16", "bf16", "e5b9g9r9"):
-        spec = wt.FrameSpec(f.width, f.height, f.rank, 3, dt, args.tight)
+    ref32 = None
+    for dt in (("f32", "f16", "bf16") if smoke else ("f32", "f16", "bf16", "e5b9g9r9")):
+        spec = wt.FrameSpec(f.width, f.height, f.rank, C, dt, args.tight)
         ws = wt.Workspace(spec, f.count)
         coeffs = spec.new_coeffs()
         out = torch.empty((spec.pixels, 3), dtype=torch.float32, device="cuda")
         for _ in range(2):
             wt.render(spec, fr, f.bg, ws, out=out, coeffs=coeffs)
         torch.cuda.synchronize()
-        K = max(1, args.steps // 4)
+        K = max(1, args.steps // 2)
         t1 = time.perf_counter()
         for _ in range(K):
             wt.render(spec, fr, f.bg, ws, out=out, coeffs=coeffs)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t1) * 1e3 / K
         g = out.cpu().double().numpy()[sel]
-        e_or = np.abs(g - ex)
-        e_ab = np.abs(g - ab)
+        if dt == "f32":
+            ref32 = g
         res[dt] = {"ms_per_frame": ms, "fragments_per_s": f.count / (ms * 1e-3),
                    "coeff_bytes_per_px": int(coeffs.element_size() * coeffs[0].numel()),
-                   "vs_oracle_exact": {"max": float(e_or.max()), "mean": float(e_or.mean()),
-                                       "p99": float(np.percentile(e_or, 99))},
-                   "vs_abuffer": {"max": float(e_ab.max()), "mean": float(e_ab.mean()),
-                                  "p99": float(np.percentile(e_ab, 99))}}
-        print("precision: %s %.3f ms/frame" % (dt, ms), file=sys.stderr, flush=True)
+                   "vs_oracle_exact": err(g, ex), "vs_abuffer": err(g, ab), "vs_f32_storage": err(g, ref32)}
+        print("precision: %s %.3f ms/frame, max |out - oracle| %.2e" % (dt, ms, res[dt]["vs_oracle_exact"]["max"]),
+              file=sys.stderr, flush=True)
         del ws, coeffs, out
         torch.cuda.empty_cache()
-    e_wt = np.abs(ex - ab)
-    line = {"metric": "glass + particles resolve: ms/frame and composite error per coefficient storage",
+    line = {"metric": "%s resolve: ms/frame and composite error per coefficient storage" % ("smoke" if smoke else
+                                                                                            "glass + particles"),
             "mode": "precision", "n_gpus": 1, "data": "synthetic", "fragments": f.count,
-            "sample_pixels": int(sel.size), "tight": bool(args.tight),
-            "oracle_exact_vs_abuffer": {"max": float(e_wt.max()), "mean": float(e_wt.mean()),
-                                        "p99": float(np.percentile(e_wt, 99))},
-            "storage": res,
-            "config": {"workload": "glass + particles %dx%d, 2-4 glass layers (per-channel alpha) + Poisson(24) "
-                                   "particles per px, rank %d, three visibility channels" % (f.width, f.height,
-                                                                                              f.rank)}}
+            "pixels_checked": int(sel.size), "tight": bool(args.tight),
+            "oracle_exact_vs_abuffer": err(ex, ab), "storage": res,
+            "config": {"workload": ("smoke %dx%d, Poisson(64 g) fragments/px, rank %d, one visibility channel" %
+                                    (f.width, f.height, f.rank)) if smoke else
+                                   ("glass + particles %dx%d, 2-4 glass layers (per-channel alpha) + Poisson(24) "
+                                    "particles per px, rank %d, three visibility channels" % (f.width, f.height,
+                                                                                              f.rank))}}
     print(json.dumps(line))
 
 
@@ -536,6 +555,53 @@ def run_traffic(args):
                  "| --- | --- | --- | --- | --- |\n")
         fh.write("\n".join(rows) + "\n")
     print(json.dumps(t["workloads"][key]))
+
+
+def run_overlap(args):
+    """Device overlap of the serving slots from a rocprofv3 kernel trace (``--trace``: the kernel_trace.csv of a
+    ``--mode serve`` run): kernels grouped by HIP stream; a sweep over their start/end times gives the time any
+    kernel runs, the time kernels of two or more streams run together, and how many kernels overlap a kernel of
+    another stream."""
+    rows = []
+    with open(args.trace) as fh:
+        for r in csv.DictReader(fh):
+            if r.get("Kind", "KERNEL_DISPATCH") != "KERNEL_DISPATCH":
+                continue
+            name = r["Kernel_Name"]
+            if not name.startswith(("void wt::", "wt::")):
+                continue  # library kernels only (the trace also holds torch's set-up kernels)
+            rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), int(r["Stream_Id"]), name))
+    rows.sort()
+    events = sorted([(b, 1, s) for b, e, s, _ in rows] + [(e, -1, s) for b, e, s, _ in rows])
+    active = collections.Counter()
+    busy = multi = 0
+    last = events[0][0] if events else 0
+    peak = 0
+    for t, d, s in events:
+        n_streams = sum(1 for v in active.values() if v > 0)
+        if n_streams >= 1:
+            busy += t - last
+        if n_streams >= 2:
+            multi += t - last
+        active[s] += d
+        peak = max(peak, sum(1 for v in active.values() if v > 0))
+        last = t
+    # kernels that run at the same time as at least one kernel of another stream (every overlapping pair has one
+    # kernel starting inside the other, so a scan forward from each start-sorted kernel finds it)
+    hit = [False] * len(rows)
+    for i, (b, e, s, _) in enumerate(rows):
+        for j in range(i + 1, len(rows)):
+            if rows[j][0] >= e:
+                break
+            if rows[j][2] != s:
+                hit[i] = hit[j] = True
+    overlapped = sum(hit)
+    streams = sorted({r[2] for r in rows})
+    span = (max(e for _, e, _, _ in rows) - rows[0][0]) if rows else 0
+    res = {"kernels": len(rows), "streams": len(streams), "span_ms": span * 1e-6, "busy_ms": busy * 1e-6,
+           "two_or_more_streams_ms": multi * 1e-6, "share_of_busy_time_with_overlap": multi / busy if busy else 0.0,
+           "max_streams_at_once": peak, "kernels_overlapping_another_streams_kernel": overlapped}
+    print(json.dumps(res))
 
 
 def run_serve(args):

@@ -24,6 +24,13 @@
  *     alpha. Their number is read back with wt_dropped_count(). Depth is clamped to [0, 1]; alpha to
  *     [0, 1 - 2^-24].
  *   - The library is stateless and re-entrant; calls that share a workspace must be ordered on one stream.
+ *   - A workspace records on the device what was binned into it. A call over a binned stream (wt_*_binned, and
+ *     the passes inside wt_build, wt_evaluate, wt_render, wt_backward) checks, before it reads a table or a record,
+ *     that the workspace holds a complete binning made under the same description and ws_bytes, with the record
+ *     format it reads; otherwise it computes nothing and leaves its outputs untouched. wt_bin_scatter writes only
+ *     after a wt_bin_count of the same stream (count and the four array addresses) under the same description
+ *     and ws_bytes, and stops writing if a tile would receive more fragments than were counted (the stream's
+ *     contents changed in between). Such refusals happen on the device; wt_dropped_count reports them.
  *
  * Data layout (row-major, little endian)
  *   fragments  structure of arrays, F = count entries:
@@ -78,6 +85,12 @@ typedef enum { WT_F32 = 0, WT_F16 = 1, WT_BF16 = 2, WT_E5B9G9R9 = 3 } wt_dtype;
  * WT_TEMPORAL description serves wt_render_temporal_binned; the other entry points accept the flag as well (smaller
  * tiles, same results). Requires rank <= 4 and excludes WT_TIGHT_DEPTH (WT_ERR_UNSUPPORTED). */
 #define WT_TEMPORAL 2u
+/* WT_DETERMINISTIC: a debug mode whose results are bit-identical from run to run for the same stream. The binning
+ * copies the stream in stream order with a single thread, and each tile's fragments are applied one after another,
+ * in that order, by a single thread of the tile's workgroup (no two updates of a sum race). Much slower than the
+ * default; meant for tests and for telling a race from rounding (results differ from the default mode only in the
+ * order of the FP64 on-chip sums). Combines with the other flags. */
+#define WT_DETERMINISTIC 4u
 
 typedef struct {
   uint32_t width;       /* pixels per row, >= 1 */
@@ -85,7 +98,7 @@ typedef struct {
   uint32_t rank;        /* N in 0..10: levels n = 0..N, M = 2^(N+1) coefficients per channel */
   uint32_t channels;    /* 1 (one visibility for r, g, b) or 3 (per-channel transmittance) */
   uint32_t coeff_dtype; /* wt_dtype */
-  uint32_t flags;       /* 0, WT_TIGHT_DEPTH or WT_TEMPORAL */
+  uint32_t flags;       /* 0 or WT_TIGHT_DEPTH or WT_TEMPORAL, optionally with WT_DETERMINISTIC */
 } wt_frame_desc;
 
 typedef struct {
@@ -110,7 +123,8 @@ wt_status wt_bin(const wt_frame_desc* desc, const wt_fragments* frags, void* ws,
 
 /* The two halves of wt_bin, for callers that time or schedule them separately: wt_bin_count zeroes the
  * drop counter, counts fragments per screen tile and lays out the tile segments; wt_bin_scatter then copies
- * the stream into them. wt_bin_scatter must follow wt_bin_count on the same stream with the same arguments. */
+ * the stream into them. wt_bin_scatter must follow wt_bin_count on the same stream with the same arguments and
+ * unchanged fragment arrays (checked on the device, see the conventions above). */
 wt_status wt_bin_count(const wt_frame_desc* desc, const wt_fragments* frags, void* ws, size_t ws_bytes,
                        hipStream_t stream);
 wt_status wt_bin_scatter(const wt_frame_desc* desc, const wt_fragments* frags, void* ws, size_t ws_bytes,
@@ -226,7 +240,10 @@ wt_status wt_backward(const wt_frame_desc* desc, const wt_fragments* frags, cons
                       const float* bg_rgb, const float* grad_out, float* grad_alpha, float* grad_rgb, void* ws,
                       size_t ws_bytes, hipStream_t stream);
 
-/* Number of fragments dropped by the last binning in this workspace. Synchronises the given stream. */
+/* Number of fragments dropped by the last binning in this workspace. Synchronises the given stream. Returns
+ * WT_ERR_INVALID (with *count still written) when a call on this workspace was refused on the device since the last
+ * report: a call over the binned stream that found no complete binning for its description and ws_bytes, or a
+ * scatter that did not belong to the count before it; wt_last_error() names which, and the report is cleared. */
 wt_status wt_dropped_count(const void* ws, size_t ws_bytes, uint64_t* count, hipStream_t stream);
 
 /* Thread-local message describing the last non-OK status returned on this thread ("" if none). */

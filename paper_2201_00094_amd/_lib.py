@@ -13,6 +13,7 @@ STATUS_NAMES = {0: "WT_OK", -1: "WT_ERR_INVALID", -2: "WT_ERR_RANGE", -3: "WT_ER
 WT_F32, WT_F16, WT_BF16, WT_E5B9G9R9 = 0, 1, 2, 3
 WT_TIGHT_DEPTH = 1
 WT_TEMPORAL = 2
+WT_DETERMINISTIC = 4
 WT_SCRATCH_BYTES = 256 << 20  # the static device array behind wt_render_noalloc
 
 

@@ -43,7 +43,8 @@ wt_status check_desc(const wt_frame_desc* d) {
     return fail(WT_ERR_INVALID, "E5B9G9R9 storage packs three channels (channels = %u)", d->channels);
   if (d->coeff_dtype == WT_E5B9G9R9 && d->rank > 4)
     return fail(WT_ERR_UNSUPPORTED, "E5B9G9R9 storage supports rank <= 4 (rank = %u)", d->rank);
-  if (d->flags & ~(WT_TIGHT_DEPTH | WT_TEMPORAL)) return fail(WT_ERR_INVALID, "unknown flags 0x%x", d->flags);
+  if (d->flags & ~(WT_TIGHT_DEPTH | WT_TEMPORAL | WT_DETERMINISTIC))
+    return fail(WT_ERR_INVALID, "unknown flags 0x%x", d->flags);
   if ((d->flags & WT_TEMPORAL) && (d->flags & WT_TIGHT_DEPTH))
     return fail(WT_ERR_UNSUPPORTED, "WT_TEMPORAL excludes WT_TIGHT_DEPTH");
   if ((d->flags & WT_TEMPORAL) && d->rank > 4)
@@ -336,11 +337,31 @@ wt_status wt_backward(const wt_frame_desc* desc, const wt_fragments* frags, cons
 wt_status wt_dropped_count(const void* ws, size_t ws_bytes, uint64_t* count, hipStream_t stream) {
   if (!ws || !count) return fail(WT_ERR_INVALID, "ws or count is NULL");
   if (ws_bytes < 256) return fail(WT_ERR_RANGE, "workspace of %zu bytes has no header", ws_bytes);
-  unsigned long long v = 0;
-  hipError_t e = hipMemcpyAsync(&v, ws, sizeof v, hipMemcpyDeviceToHost, stream);
+  wt::WsHeader h{};
+  hipError_t e = hipMemcpyAsync(&h, ws, sizeof h, hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return hip_fail(e, "wt_dropped_count");
-  *count = v;
+  if (h.magic != wt::kWsMagic) {  // nothing has been binned into this workspace yet
+    *count = 0;
+    return WT_OK;
+  }
+  *count = h.dropped;
+  if (h.errors) {
+    wt::WsHeader* dh = (wt::WsHeader*)const_cast<void*>(ws);
+    e = wt::launch_fill_u32(&dh->errors, 1, 0u, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "wt_dropped_count (clearing the error bits)");
+    return fail(WT_ERR_INVALID, "workspace misuse detected on the device since the last report (bits 0x%x):%s%s",
+                h.errors,
+                (h.errors & wt::kWsErrMismatch)
+                    ? " a call over the binned stream found no complete binning for its description and workspace "
+                      "size, and computed nothing;"
+                    : "",
+                (h.errors & wt::kWsErrScatter)
+                    ? " a scatter did not follow a count of the same stream under the same layout, or its stream held "
+                      "more fragments for a tile than were counted, and nothing was binned;"
+                    : "");
+  }
   return WT_OK;
 }
 

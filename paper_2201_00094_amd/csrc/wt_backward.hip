@@ -110,7 +110,8 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(Binned b, Geom g, cons
   float* lg = lc + per * TP;
   float* lT = lg + 3 * TP;
   uint32_t* lb = g.tight ? (uint32_t*)(lT + C * TP) : nullptr;  // per-pixel depth bounds
-  const uint32_t t = b.order[blockIdx.x];
+  uint32_t t;
+  if (!binned_ok(b, g, t)) return;
   const uint32_t x0 = (t % g.tilesX) * g.TW, y0 = (t / g.tilesX) * g.TH;
   for (uint32_t lp = threadIdx.x; lp < TP; lp += blockDim.x) {
     const uint32_t px = x0 + (lp & (g.TW - 1)), py = y0 + (lp >> g.lTW);
@@ -155,8 +156,9 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(Binned b, Geom g, cons
     }
     __syncthreads();
   }
-  // pass 1: cell adjoints
-  for (uint32_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
+  // pass 1: cell adjoints (one thread in binned order under WT_DETERMINISTIC)
+  const uint32_t i1 = g.serial ? (threadIdx.x ? end : beg) : beg + threadIdx.x, di1 = g.serial ? 1 : blockDim.x;
+  for (uint32_t i = i1; i < end; i += di1) {
     BFrag<C> f;
     if (!load_bfrag<C>(b, i, f)) continue;
     uint32_t j;

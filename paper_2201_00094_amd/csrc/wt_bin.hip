@@ -60,6 +60,7 @@ Geom make_geom(const wt_frame_desc& d, bool backward) {
   uint32_t px;
   g.ep = 0;
   g.tight = (d.flags & WT_TIGHT_DEPTH) ? 1 : 0;
+  g.serial = (d.flags & WT_DETERMINISTIC) ? 1 : 0;
   const uint32_t bpx = g.tight ? 8 : 0;  // per-pixel depth bounds (two FP32) in LDS
   if (backward) {
     px = tile_for(12 * g.C * g.M + 4 * (3 + g.C) + bpx);
@@ -165,9 +166,11 @@ Layout make_layout(const Geom& g, uint64_t cap) {
   l.offsets = o;
   o = align256(o + 4ull * (g.NX * (uint64_t)g.ntiles + 1));
   l.cursors = o;
-  o = align256(o + 4ull * g.NX * g.ntiles);
+  o = align256(o + 4ull * g.NX * g.ntiles * kCursorPad);
   l.order = o;
   o = align256(o + 4ull * g.ntiles);
+  l.scan = o;
+  o = align256(o + 4ull * 257 * ((g.NX * (uint64_t)g.ntiles + kScanRange - 1) / kScanRange));
   l.heads = o;
   o = align256(o + 4ull * head_dwords(g.C) * cap);
   l.tails = o;
@@ -179,7 +182,7 @@ Layout make_layout(const Geom& g, uint64_t cap) {
     l.offsets1 = o;
     o = align256(o + 4ull * (g.NX * (uint64_t)g.nsuper + 1));
     l.cursors1 = o;
-    o = align256(o + 4ull * g.NX * g.nsuper);
+    o = align256(o + 4ull * g.NX * g.nsuper * kCursorPad);
     l.order1 = o;
     o = align256(o + 4ull * g.nsuper);
     l.heads1 = o;
@@ -210,12 +213,83 @@ Binned binned_view(const Geom& g, const Layout& l, const void* ws, bool with_ind
   v.tail = (const uint32_t*)(b + l.tails);
   v.DH = head_dwords(g.C);
   v.DT = tail_dwords(with_index);
+  v.hdr = (WsHeader*)(b + l.header);
+  v.stamp = layout_stamp(g, l, with_index);
+  v.cap = l.cap;
   return v;
 }
+
+// The stamp covers everything the tile kernels index by: frame, channels, rank, tile and super-tile geometry, write
+// classes, record capacity and format, and the layout's size.
+unsigned long long layout_stamp(const Geom& g, const Layout& l, bool with_index) {
+  const uint32_t w[] = {0x57544c31u, g.W, g.H, g.C, g.rank, g.TW, g.TH, g.NX, g.two, g.SW, g.SH, g.lds_bins, g.serial,
+                        (uint32_t)l.cap, (uint32_t)(l.cap >> 32), (uint32_t)l.total, (uint32_t)(l.total >> 32),
+                        with_index ? 1u : 0u};
+  return stamp_words(w, (int)(sizeof w / sizeof w[0]));
+}
+
+// A count is stamped with the layout and the stream it counted (size and the four array addresses), so that a
+// scatter of another stream, or under another layout, refuses to write.
+unsigned long long count_stamp(const Geom& g, const Layout& l, const wt_fragments& f) {
+  const unsigned long long ls = layout_stamp(g, l, false);
+  const uintptr_t a[4] = {(uintptr_t)f.pixel, (uintptr_t)f.depth, (uintptr_t)f.alpha, (uintptr_t)f.rgb};
+  uint32_t w[12] = {(uint32_t)ls, (uint32_t)(ls >> 32), (uint32_t)f.count, (uint32_t)(f.count >> 32)};
+  for (int i = 0; i < 4; ++i) {
+    w[4 + 2 * i] = (uint32_t)a[i];
+    w[5 + 2 * i] = (uint32_t)((uint64_t)a[i] >> 32);
+  }
+  return stamp_words(w, 12);
+}
+
+// Start of a count: no complete binning and no count in the workspace any more; the drop counter and the scatter
+// fault restart. The sticky error bits stay until wt_dropped_count reports them.
+__global__ void k_header_reset(WsHeader* h) {
+  if (h->magic != kWsMagic) {  // a workspace the device has not written yet: no errors to keep
+    h->errors = 0;
+    h->magic = kWsMagic;
+  }
+  h->dropped = 0;
+  h->fault = 0;
+  h->counted = 0;
+  h->binned = 0;
+}
+
+// End of a scatter: the binning is complete when the count before it was this stream's under this layout, the
+// scatter did not refuse, and every write cursor reached the end of its segment (so each segment holds exactly the
+// records counted for it). Then the header gets `stamp`, else 0.
+// One workgroup. cursors are [NX][nt] (row stride kCursorPad words), offsets [nt * NX + 1].
+__global__ __launch_bounds__(1024) void k_seal(WsHeader* h, const uint32_t* __restrict__ cursors,
+                                                const uint32_t* __restrict__ offsets, uint32_t NX, uint32_t nt,
+                                                unsigned long long cstamp, unsigned long long stamp) {
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  int mine = 0;
+  for (uint32_t e = threadIdx.x; e < NX * nt; e += blockDim.x) {
+    const uint32_t x = e / nt, t = e - x * nt;
+    mine |= cursors[(size_t)e * kCursorPad] != offsets[t * NX + x + 1];
+  }
+  if (mine) bad = 1;
+  __syncthreads();
+  if (threadIdx.x == 0) h->binned = (!bad && h->fault == 0 && h->counted == cstamp) ? stamp : 0ull;
+}
+
+// After the split of a two-level binning: complete when the first level was (the split only moves its records).
+__global__ void k_seal_split(WsHeader* h, unsigned long long level1, unsigned long long stamp) {
+  h->binned = h->binned == level1 ? stamp : 0ull;
+}
+
+// A first-level binning of a two-level layout carries this stamp until its split has run.
+static unsigned long long level1_stamp(unsigned long long s) { return s ^ 0x9e3779b97f4a7c15ull; }
 
 __global__ void k_fill_u32(uint32_t* __restrict__ p, uint64_t n, uint32_t v) {
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
     p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<uint64_t>((n + 255) / 256, 4096)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------------------------------------------ histogram
@@ -310,6 +384,8 @@ __global__ __launch_bounds__(256) void k_hist_global(const uint32_t* __restrict_
 constexpr int kScanThreads = 1024;
 constexpr int kScanItems = 16;
 constexpr uint32_t kOrderBuckets = 256;  // size classes of the heaviest-first tile order
+static_assert(kScanRange == (uint32_t)kScanThreads * kScanItems, "a scan workgroup covers one pass of k_scan");
+static_assert(kScanRange % kClasses == 0, "scan ranges hold whole tiles");
 
 // Exclusive prefix of s over the workgroup (wavefront shuffles, then the wave totals); *total receives the sum.
 // wsum holds kScanThreads / 64 + 1 entries. Ends with a barrier.
@@ -357,7 +433,9 @@ __device__ __forceinline__ uint32_t size_class(uint32_t c) {
 __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t* __restrict__ counts, Geom g,
                                                        uint32_t* __restrict__ offsets,
                                                        uint32_t* __restrict__ cursors,
-                                                       uint32_t* __restrict__ order, int with_order) {
+                                                       uint32_t* __restrict__ order, int with_order,
+                                                       WsHeader* hdr, unsigned long long stamp) {
+  if (hdr && threadIdx.x == 0) hdr->counted = stamp;  // the last scan of a count (seen by later kernels)
   __shared__ uint32_t wsum[kScanThreads / 64 + 1];
   __shared__ uint32_t bucket[kOrderBuckets];
   const uint64_t n = (uint64_t)g.ntiles * g.NX;
@@ -384,7 +462,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t* __restric
       if (e < n) {
         const uint32_t t = (uint32_t)(e / g.NX), x = (uint32_t)(e % g.NX);
         offsets[e] = run;
-        cursors[x * g.ntiles + t] = run;
+        cursors[(x * g.ntiles + t) * kCursorPad] = run;
       }
       run += v[k];
     }
@@ -410,6 +488,105 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t* __restric
     uint32_t c = 0;
     for (uint32_t x = 0; x < g.NX; ++x) c += counts[x * g.ntiles + t];
     order[atomicAdd(&bucket[kOrderBuckets - 1 - size_class(c)], 1u)] = t;
+  }
+}
+
+// The same scan and tile order for frames with many segments, over several workgroups: workgroup w owns the
+// segments [w R, (w + 1) R) (R = kScanRange, whole tiles since R is a multiple of NX). Pass one: each workgroup's
+// segment total and the size classes of its tiles (part[w][0], part[w][1 + k] for reversed class k). Pass two:
+// each workgroup adds the totals of the workgroups before it, scans its range, and places its tiles in the
+// heaviest-first order after every heavier class and after its class's tiles of earlier workgroups.
+__global__ __launch_bounds__(kScanThreads) void k_scan_part(const uint32_t* __restrict__ counts, Geom g,
+                                                            uint32_t* __restrict__ part) {
+  __shared__ uint32_t wsum[kScanThreads / 64 + 1];
+  __shared__ uint32_t bucket[kOrderBuckets];
+  const uint64_t n = (uint64_t)g.ntiles * g.NX;
+  const uint64_t e0 = (uint64_t)blockIdx.x * kScanRange;
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t b = tid; b < kOrderBuckets; b += kScanThreads) bucket[b] = 0;
+  uint32_t s = 0;
+  for (uint32_t k = tid; k < kScanRange; k += kScanThreads) {
+    const uint64_t e = e0 + k;
+    if (e < n) {
+      const uint32_t t = (uint32_t)(e / g.NX), x = (uint32_t)(e % g.NX);
+      s += counts[x * g.ntiles + t];
+    }
+  }
+  uint32_t total;
+  block_exclusive(s, wsum, &total);
+  __syncthreads();
+  const uint32_t t0 = (uint32_t)(e0 / g.NX), t1 = (uint32_t)std::min<uint64_t>((e0 + kScanRange) / g.NX, g.ntiles);
+  for (uint32_t t = t0 + tid; t < t1; t += kScanThreads) {
+    uint32_t c = 0;
+    for (uint32_t x = 0; x < g.NX; ++x) c += counts[x * g.ntiles + t];
+    atomicAdd(&bucket[kOrderBuckets - 1 - size_class(c)], 1u);
+  }
+  __syncthreads();
+  uint32_t* mine = part + (size_t)blockIdx.x * (1 + kOrderBuckets);
+  if (tid == 0) mine[0] = total;
+  for (uint32_t b = tid; b < kOrderBuckets; b += kScanThreads) mine[1 + b] = bucket[b];
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const uint32_t* __restrict__ counts, Geom g,
+                                                             const uint32_t* __restrict__ part,
+                                                             uint32_t* __restrict__ offsets,
+                                                             uint32_t* __restrict__ cursors,
+                                                             uint32_t* __restrict__ order, int with_order,
+                                                             WsHeader* hdr, unsigned long long stamp) {
+  __shared__ uint32_t wsum[kScanThreads / 64 + 1];
+  __shared__ uint32_t start[kOrderBuckets];
+  const uint64_t n = (uint64_t)g.ntiles * g.NX;
+  const uint32_t G = gridDim.x, w = blockIdx.x, tid = threadIdx.x;
+  const uint64_t e0 = (uint64_t)w * kScanRange;
+  if (hdr && w == 0 && tid == 0) hdr->counted = stamp;
+  // segments of the workgroups before this one
+  uint32_t c = 0;
+  for (uint32_t v = tid; v < w; v += kScanThreads) c += part[(size_t)v * (1 + kOrderBuckets)];
+  uint32_t carry;
+  block_exclusive(c, wsum, &carry);
+  // this range's segments, kScanItems consecutive per thread
+  uint32_t v[kScanItems];
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const uint64_t e = e0 + (uint64_t)tid * kScanItems + k;
+    v[k] = 0;
+    if (e < n) v[k] = counts[(uint32_t)(e % g.NX) * g.ntiles + (uint32_t)(e / g.NX)];
+    s += v[k];
+  }
+  uint32_t total;
+  uint32_t run = carry + block_exclusive(s, wsum, &total);
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const uint64_t e = e0 + (uint64_t)tid * kScanItems + k;
+    if (e < n) {
+      const uint32_t t = (uint32_t)(e / g.NX), x = (uint32_t)(e % g.NX);
+      offsets[e] = run;
+      cursors[(x * g.ntiles + t) * kCursorPad] = run;
+    }
+    run += v[k];
+  }
+  if (w == G - 1 && tid == 0) offsets[n] = carry + total;
+  if (!with_order) return;
+  // start of this workgroup's tiles in each size class: all heavier classes, then earlier workgroups' tiles of
+  // the same class
+  uint32_t tot = 0, pre = 0;
+  if (tid < kOrderBuckets) {
+    for (uint32_t u = 0; u < G; ++u) {
+      const uint32_t b = part[(size_t)u * (1 + kOrderBuckets) + 1 + tid];
+      tot += b;
+      if (u < w) pre += b;
+    }
+  }
+  uint32_t all;
+  const uint32_t base = block_exclusive(tid < kOrderBuckets ? tot : 0u, wsum, &all);
+  if (tid < kOrderBuckets) start[tid] = base + pre;
+  __syncthreads();
+  const uint32_t t0 = (uint32_t)(e0 / g.NX), t1 = (uint32_t)std::min<uint64_t>((e0 + kScanRange) / g.NX, g.ntiles);
+  for (uint32_t t = t0 + tid; t < t1; t += kScanThreads) {
+    uint32_t cnt = 0;
+    for (uint32_t x = 0; x < g.NX; ++x) cnt += counts[x * g.ntiles + t];
+    order[atomicAdd(&start[kOrderBuckets - 1 - size_class(cnt)], 1u)] = t;
   }
 }
 
@@ -629,13 +806,21 @@ __device__ __forceinline__ void lds_get(const uint32_t* d, uint32_t* w) {
 // rounds of S records (S = stage, a power of two chosen by the host to fit the LDS).
 // PER = 4 is meant for two workgroups per compute unit (LDS <= 80 KB, <= 64 VGPRs at eight waves per SIMD):
 // one workgroup's loads and stores overlap the other's ranking and staging.
+// Refusal of a scatter that does not belong to the count before it, or whose stream puts more records in a segment
+// than were counted: nothing more is written and the binning is not sealed.
+__device__ __forceinline__ void scatter_refuse(WsHeader* hdr) {
+  atomicOr(&hdr->fault, 1u);
+  ws_raise(hdr, kWsErrScatter);
+}
+
 template <int C, bool IDX, int THREADS, int PER>
 __global__ __launch_bounds__(THREADS, PER == 4 ? 8 : 1) void k_scatter_staged(wt_fragments f, Geom g, int vec,
                                                                     uint32_t stage,
                                                                     uint32_t* __restrict__ cursors,
                                                                     uint32_t* __restrict__ head,
                                                                     uint32_t* __restrict__ tail,
-                                                                    unsigned long long* __restrict__ dropped) {
+                                                                    WsHeader* hdr, unsigned long long cstamp,
+                                                                    uint32_t cap) {
   constexpr uint32_t DH = head_dwords(C), DT = tail_dwords(IDX), HW = DH + 1;
   extern __shared__ uint4 sm4[];
   uint32_t* sh = (uint32_t*)sm4;               // [stage][HW]: head words, then the tile
@@ -643,16 +828,22 @@ __global__ __launch_bounds__(THREADS, PER == 4 ? 8 : 1) void k_scatter_staged(wt
   uint32_t* cnt = st + (size_t)stage * DT;
   uint32_t* gb = cnt + g.ntiles;
   __shared__ uint32_t wsum[THREADS / 64];
-  __shared__ uint32_t nvalid;
+  __shared__ uint32_t nvalid, refused;
   const uint32_t F = (uint32_t)f.count;
   const uint32_t cls = blockIdx.x % g.NX;
   const uint32_t base = blockIdx.x * g.chunk;
   const uint32_t n = std::min<uint32_t>(g.chunk, F - base);
   for (uint32_t t = threadIdx.x; t < g.ntiles; t += blockDim.x) cnt[t] = 0;
-  if (threadIdx.x == 0) nvalid = 0;
+  if (threadIdx.x == 0) nvalid = refused = 0;
   ChunkRegs<C, PER> r;
   const uint32_t i0 = threadIdx.x * PER;
   load_chunk<C, PER>(f, base, i0, n, vec, r);
+  // only the stream the preceding count counted, under the same layout, is scattered into its segments (the
+  // stamp is loaded behind the chunk, so the check adds no wait of its own)
+  if (__hip_atomic_load(&hdr->counted, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != cstamp) {
+    if (threadIdx.x == 0) scatter_refuse(hdr);
+    return;
+  }
   if constexpr (!IDX) to_absorbance<C, PER>(r);
   __syncthreads();
   uint32_t tile[PER], rank[PER], local[PER];
@@ -699,9 +890,19 @@ __global__ __launch_bounds__(THREADS, PER == 4 ? 8 : 1) void k_scatter_staged(wt
     for (uint32_t t = threadIdx.x; t < g.ntiles; t += THREADS) {
       const uint32_t p0 = cnt[t], p1 = t + 1 < g.ntiles ? cnt[t + 1] : total;
       const uint32_t lo = std::max(p0, r0), hi = std::min(p1, r1);
-      if (hi > lo) gb[t] = atomicAdd(&cursors[cls * g.ntiles + t], hi - lo) - lo;
+      if (hi > lo) {
+        const uint32_t got = atomicAdd(&cursors[(cls * g.ntiles + t) * kCursorPad], hi - lo);
+        gb[t] = got - lo;
+        // writes stay inside the record arrays whatever the cursors hold; a stream that changed since its count
+        // and overruns a segment into its neighbour leaves cursors off their segment ends, which the seal sees
+        if (got > cap || cap - got < hi - lo) refused = 1;
+      }
     }
     __syncthreads();
+    if (refused) {
+      if (threadIdx.x == 0) scatter_refuse(hdr);
+      return;
+    }
     const uint32_t ns = std::min(stage, total - r0);
     for (uint32_t sidx = threadIdx.x; sidx < ns; sidx += blockDim.x) {
       uint32_t hw[HW], tw[DT];
@@ -720,7 +921,7 @@ __global__ __launch_bounds__(THREADS, PER == 4 ? 8 : 1) void k_scatter_staged(wt
     __syncthreads();
   }
   nan_count = wave_sum(nan_count);
-  if ((threadIdx.x & 63) == 0 && nan_count) atomicAdd(dropped, (unsigned long long)nan_count);
+  if ((threadIdx.x & 63) == 0 && nan_count) atomicAdd(&hdr->dropped, (unsigned long long)nan_count);
 }
 
 template <int C, bool IDX, int THREADS>
@@ -728,8 +929,13 @@ __global__ __launch_bounds__(THREADS) void k_scatter_global(wt_fragments f, Geom
                                                                     uint32_t* __restrict__ cursors,
                                                                     uint32_t* __restrict__ head,
                                                                     uint32_t* __restrict__ tail,
-                                                                    unsigned long long* __restrict__ dropped) {
+                                                                    WsHeader* hdr, unsigned long long cstamp,
+                                                                    uint32_t cap) {
   constexpr uint32_t DH = head_dwords(C), DT = tail_dwords(IDX);
+  if (__hip_atomic_load(&hdr->counted, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != cstamp) {
+    if (threadIdx.x == 0) scatter_refuse(hdr);
+    return;
+  }
   const uint32_t F = (uint32_t)f.count;
   const uint32_t base = blockIdx.x * g.chunk;
   const uint32_t n = std::min<uint32_t>(g.chunk, F - base);
@@ -744,14 +950,62 @@ __global__ __launch_bounds__(THREADS) void k_scatter_global(wt_fragments f, Geom
     uint32_t tile, local;
     tile_locate(g, r.p[k], tile, local);
     nan_count += has_nan<C, kPer>(r, k) ? 1u : 0u;
-    const uint64_t pos = atomicAdd(&cursors[tile], 1u);
+    const uint64_t pos = atomicAdd(&cursors[tile * kCursorPad], 1u);
+    if (pos >= cap) {  // inside the record arrays whatever the cursors hold (the seal checks the segments)
+      scatter_refuse(hdr);
+      continue;
+    }
 #pragma unroll
     for (uint32_t j = 0; j < DH; ++j) head[pos * DH + j] = record_word<C, kPer>(r, k, local, base + i0 + k, j);
 #pragma unroll
     for (uint32_t j = 0; j < DT; ++j) tail[pos * DT + j] = record_word<C, kPer>(r, k, local, base + i0 + k, DH + j);
   }
   nan_count = wave_sum(nan_count);
-  if ((threadIdx.x & 63) == 0 && nan_count) atomicAdd(dropped, (unsigned long long)nan_count);
+  if ((threadIdx.x & 63) == 0 && nan_count) atomicAdd(&hdr->dropped, (unsigned long long)nan_count);
+}
+
+// WT_DETERMINISTIC binning: one thread copies the stream in stream order straight into the tile segments (the
+// class of fragment i is that of its chunk, as in the count), so every segment holds its records in stream order.
+template <int C, bool IDX>
+__global__ void k_scatter_serial(wt_fragments f, Geom g, uint32_t* __restrict__ cursors,
+                                 const uint32_t* __restrict__ offsets, uint32_t* __restrict__ head,
+                                 uint32_t* __restrict__ tail, WsHeader* hdr, unsigned long long cstamp) {
+  constexpr uint32_t DH = head_dwords(C), DT = tail_dwords(IDX);
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (hdr->counted != cstamp) {
+    scatter_refuse(hdr);
+    return;
+  }
+  unsigned long long nan_count = 0;
+  for (uint64_t i = 0; i < f.count; ++i) {
+    const uint32_t p = f.pixel[i];
+    if (p >= g.P) continue;
+    uint32_t tile, local;
+    tile_locate(g, p, tile, local);
+    const uint32_t cls = (uint32_t)((i / g.chunk) % g.NX);
+    uint32_t* cur = &cursors[(cls * g.ntiles + tile) * kCursorPad];
+    const uint32_t pos = *cur;
+    if (pos >= offsets[tile * g.NX + cls + 1]) {
+      scatter_refuse(hdr);
+      return;
+    }
+    *cur = pos + 1;
+    const float x = f.depth[i];
+    bool bad = isnan(x);
+    uint32_t* h = head + (uint64_t)pos * DH;
+    h[0] = local;
+    h[1] = __float_as_uint(x);
+    for (int c = 0; c < C; ++c) {
+      const float al = f.alpha[i * C + c];
+      bad |= isnan(al);
+      h[2 + c] = __float_as_uint(IDX ? al : binned_absorbance(al));
+    }
+    uint32_t* t = tail + (uint64_t)pos * DT;
+    for (int q = 0; q < 3; ++q) t[q] = __float_as_uint(f.rgb[i * 3 + q]);
+    if (IDX) t[3] = (uint32_t)i;
+    nan_count += bad ? 1 : 0;
+  }
+  if (nan_count) atomicAdd(&hdr->dropped, nan_count);
 }
 
 // Second level of two-level binning: one workgroup per super-tile moves its records (all classes, contiguous in
@@ -767,8 +1021,11 @@ __global__ __launch_bounds__(kSplitThreads) void k_split(Geom g, const uint32_t*
                                                          const uint32_t* __restrict__ offsets,
                                                          const uint32_t* __restrict__ head1,
                                                          const uint32_t* __restrict__ tail1,
-                                                         uint32_t* __restrict__ head, uint32_t* __restrict__ tail) {
+                                                         uint32_t* __restrict__ head, uint32_t* __restrict__ tail,
+                                                         const WsHeader* hdr, unsigned long long level1) {
   constexpr uint32_t DH = head_dwords(C), DT = tail_dwords(IDX);
+  // only a complete first level is split (its records then hold valid super-tile-local pixels)
+  if (__hip_atomic_load(&hdr->binned, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != level1) return;
   constexpr uint32_t SH = staged_head_units(C), ST = staged_tail_units(IDX), SU = SH + ST;
   extern __shared__ uint4 srec[];                // [kSplitRecs][SU]
   __shared__ uint32_t cur[kMaxSub], cnt[kMaxSub], pre[kMaxSub];
@@ -864,8 +1121,9 @@ static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 constexpr uint32_t kStageTwoWg = 1024;
 
 template <int C, bool IDX, int PER>
-static hipError_t launch_scatter_t(const Geom& g, const wt_fragments& f, int vec, uint32_t* cursors, uint32_t* head,
-                                   uint32_t* tail, unsigned long long* dropped, uint32_t nchunks, hipStream_t s) {
+static hipError_t launch_scatter_t(const Geom& g, const wt_fragments& f, int vec, uint32_t* cursors,
+                                   uint32_t* head, uint32_t* tail, WsHeader* hdr,
+                                   unsigned long long cstamp, uint32_t cap, uint32_t nchunks, hipStream_t s) {
   constexpr int THREADS = 1024;
   if (g.lds_bins) {
     constexpr uint32_t RB = staged_record_bytes(C, IDX);
@@ -880,19 +1138,22 @@ static hipError_t launch_scatter_t(const Geom& g, const wt_fragments& f, int vec
       hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k, dim3(nchunks), dim3(THREADS), lds, s, f, g, vec, stage, cursors, head, tail, dropped);
+    hipLaunchKernelGGL(k, dim3(nchunks), dim3(THREADS), lds, s, f, g, vec, stage, cursors, head, tail, hdr, cstamp,
+                       cap);
   } else {
     hipLaunchKernelGGL((k_scatter_global<C, IDX, THREADS>), dim3(nchunks), dim3(THREADS), 0, s, f, g, vec, cursors,
-                       head, tail, dropped);
+                       head, tail, hdr, cstamp, cap);
   }
   return hipGetLastError();
 }
 
 template <int C, bool IDX>
-static hipError_t launch_scatter(const Geom& g, const wt_fragments& f, int vec, uint32_t* cursors, uint32_t* head,
-                                 uint32_t* tail, unsigned long long* dropped, uint32_t nchunks, hipStream_t s) {
-  if (g.kper == 4) return launch_scatter_t<C, IDX, 4>(g, f, vec, cursors, head, tail, dropped, nchunks, s);
-  return launch_scatter_t<C, IDX, 8>(g, f, vec, cursors, head, tail, dropped, nchunks, s);
+static hipError_t launch_scatter(const Geom& g, const wt_fragments& f, int vec, uint32_t* cursors,
+                                 uint32_t* head, uint32_t* tail, WsHeader* hdr,
+                                 unsigned long long cstamp, uint32_t cap, uint32_t nchunks, hipStream_t s) {
+  if (g.kper == 4)
+    return launch_scatter_t<C, IDX, 4>(g, f, vec, cursors, head, tail, hdr, cstamp, cap, nchunks, s);
+  return launch_scatter_t<C, IDX, 8>(g, f, vec, cursors, head, tail, hdr, cstamp, cap, nchunks, s);
 }
 
 hipError_t launch_bin_count(const Geom& g, const wt_fragments& f, void* ws, const Layout& l, hipStream_t s) {
@@ -900,10 +1161,11 @@ hipError_t launch_bin_count(const Geom& g, const wt_fragments& f, void* ws, cons
   uint32_t* counts = (uint32_t*)(b + l.counts);
   uint32_t* offsets = (uint32_t*)(b + l.offsets);
   uint32_t* cursors = (uint32_t*)(b + l.cursors);
-  unsigned long long* dropped = (unsigned long long*)(b + l.header);
+  WsHeader* hdr = (WsHeader*)(b + l.header);
+  unsigned long long* dropped = &hdr->dropped;
   const uint64_t ncount = (uint64_t)g.NX * g.ntiles;
-  // zero the header's counters and the tile counts (fill kernels: safe inside captured graphs)
-  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t*)(b + l.header), (uint64_t)4, 0u);
+  // reset the header and zero the tile counts (kernels, not memsets: safe inside captured graphs)
+  hipLaunchKernelGGL(k_header_reset, dim3(1), dim3(1), 0, s, hdr);
   hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<uint64_t>((ncount + 255) / 256, 4096)), dim3(256), 0, s,
                      counts, ncount, 0u);
   const uint32_t F = (uint32_t)f.count;
@@ -930,8 +1192,19 @@ hipError_t launch_bin_count(const Geom& g, const wt_fragments& f, void* ws, cons
       hipLaunchKernelGGL(k_hist_global, dim3(2048), dim3(256), 0, s, f.pixel, F, g, counts, dropped);
     }
   }
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, counts, g, offsets, cursors,
-                     (uint32_t*)(b + l.order), 1);
+  const unsigned long long cstamp = count_stamp(g, l, f);
+  const uint64_t nseg = (uint64_t)g.NX * g.ntiles;
+  if (nseg <= 2 * (uint64_t)kScanRange) {
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, counts, g, offsets, cursors,
+                       (uint32_t*)(b + l.order), 1, g.two ? nullptr : hdr, cstamp);
+  } else {
+    // many segments (two-level and global-atomic binnings): the scan over several workgroups
+    uint32_t* part = (uint32_t*)(b + l.scan);
+    const uint32_t G = (uint32_t)((nseg + kScanRange - 1) / kScanRange);
+    hipLaunchKernelGGL(k_scan_part, dim3(G), dim3(kScanThreads), 0, s, counts, g, part);
+    hipLaunchKernelGGL(k_scan_apply, dim3(G), dim3(kScanThreads), 0, s, counts, g, part, offsets, cursors,
+                       (uint32_t*)(b + l.order), 1, g.two ? nullptr : hdr, cstamp);
+  }
   if (g.two) {
     // first level: per-class super-tile counts, and their segments and cursors
     const Geom gs = super_geom(g);
@@ -939,7 +1212,7 @@ hipError_t launch_bin_count(const Geom& g, const wt_fragments& f, void* ws, cons
     const uint32_t n1 = g.NX * g.nsuper;
     hipLaunchKernelGGL(k_super_counts, dim3((n1 + 255) / 256), dim3(256), 0, s, counts, g, counts1);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, counts1, gs, (uint32_t*)(b + l.offsets1),
-                       (uint32_t*)(b + l.cursors1), (uint32_t*)(b + l.order1), 0);
+                       (uint32_t*)(b + l.cursors1), (uint32_t*)(b + l.order1), 0, hdr, cstamp);
   }
   return hipGetLastError();
 }
@@ -948,19 +1221,37 @@ hipError_t launch_bin_scatter(const Geom& g, const wt_fragments& f, void* ws, co
                               hipStream_t s) {
   char* b = (char*)ws;
   uint32_t* cursors = (uint32_t*)(b + l.cursors);
+  const uint32_t* offsets = (const uint32_t*)(b + l.offsets);
   uint32_t* head = (uint32_t*)(b + l.heads);
   uint32_t* tail = (uint32_t*)(b + l.tails);
-  unsigned long long* dropped = (unsigned long long*)(b + l.header);
+  WsHeader* hdr = (WsHeader*)(b + l.header);
+  const unsigned long long cstamp = count_stamp(g, l, f);
+  const unsigned long long stamp = layout_stamp(g, l, record_index);
+  const uint32_t cap = (uint32_t)std::min<uint64_t>(l.cap, 0xffffffffull);  // records each array holds
   const uint32_t F = (uint32_t)f.count;
-  if (F == 0) return hipSuccess;
   const uint32_t nchunks = (uint32_t)(((uint64_t)F + g.chunk - 1) / g.chunk);
   const int vec = aligned16(f.pixel) && aligned16(f.depth) && aligned16(f.alpha) && aligned16(f.rgb);
+  hipError_t e = hipSuccess;
+  if (g.serial) {
+    // deterministic: straight into the tile segments, whatever the number of levels
+    auto k = g.C == 1 ? (record_index ? k_scatter_serial<1, true> : k_scatter_serial<1, false>)
+                      : (record_index ? k_scatter_serial<3, true> : k_scatter_serial<3, false>);
+    hipLaunchKernelGGL(k, dim3(1), dim3(64), 0, s, f, g, cursors, offsets, head, tail, hdr, cstamp);
+    hipLaunchKernelGGL(k_seal, dim3(1), dim3(1024), 0, s, hdr, cursors, offsets, g.NX, g.ntiles, cstamp, stamp);
+    return hipGetLastError();
+  }
   if (!g.two) {
-    if (g.C == 1)
-      return record_index ? launch_scatter<1, true>(g, f, vec, cursors, head, tail, dropped, nchunks, s)
-                          : launch_scatter<1, false>(g, f, vec, cursors, head, tail, dropped, nchunks, s);
-    return record_index ? launch_scatter<3, true>(g, f, vec, cursors, head, tail, dropped, nchunks, s)
-                        : launch_scatter<3, false>(g, f, vec, cursors, head, tail, dropped, nchunks, s);
+    if (F > 0) {
+      if (g.C == 1)
+        e = record_index ? launch_scatter<1, true>(g, f, vec, cursors, head, tail, hdr, cstamp, cap, nchunks, s)
+                         : launch_scatter<1, false>(g, f, vec, cursors, head, tail, hdr, cstamp, cap, nchunks, s);
+      else
+        e = record_index ? launch_scatter<3, true>(g, f, vec, cursors, head, tail, hdr, cstamp, cap, nchunks, s)
+                         : launch_scatter<3, false>(g, f, vec, cursors, head, tail, hdr, cstamp, cap, nchunks, s);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_seal, dim3(1), dim3(1024), 0, s, hdr, cursors, offsets, g.NX, g.ntiles, cstamp, stamp);
+    return hipGetLastError();
   }
   // two levels: the stream into super-tiles (first-level arrays), then each super-tile into its tiles
   const Geom gs = super_geom(g);
@@ -968,15 +1259,17 @@ hipError_t launch_bin_scatter(const Geom& g, const wt_fragments& f, void* ws, co
   uint32_t* head1 = (uint32_t*)(b + l.heads1);
   uint32_t* tail1 = (uint32_t*)(b + l.tails1);
   const uint32_t* offsets1 = (const uint32_t*)(b + l.offsets1);
-  const uint32_t* offsets = (const uint32_t*)(b + l.offsets);
-  hipError_t e;
-  if (g.C == 1)
-    e = record_index ? launch_scatter<1, true>(gs, f, vec, cursors1, head1, tail1, dropped, nchunks, s)
-                     : launch_scatter<1, false>(gs, f, vec, cursors1, head1, tail1, dropped, nchunks, s);
-  else
-    e = record_index ? launch_scatter<3, true>(gs, f, vec, cursors1, head1, tail1, dropped, nchunks, s)
-                     : launch_scatter<3, false>(gs, f, vec, cursors1, head1, tail1, dropped, nchunks, s);
-  if (e != hipSuccess) return e;
+  const unsigned long long stamp1 = level1_stamp(stamp);
+  if (F > 0) {
+    if (g.C == 1)
+      e = record_index ? launch_scatter<1, true>(gs, f, vec, cursors1, head1, tail1, hdr, cstamp, cap, nchunks, s)
+                       : launch_scatter<1, false>(gs, f, vec, cursors1, head1, tail1, hdr, cstamp, cap, nchunks, s);
+    else
+      e = record_index ? launch_scatter<3, true>(gs, f, vec, cursors1, head1, tail1, hdr, cstamp, cap, nchunks, s)
+                       : launch_scatter<3, false>(gs, f, vec, cursors1, head1, tail1, hdr, cstamp, cap, nchunks, s);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_seal, dim3(1), dim3(1024), 0, s, hdr, cursors1, offsets1, gs.NX, g.nsuper, cstamp, stamp1);
   auto split = [&](auto kern, uint32_t su) -> hipError_t {
     const size_t lds = (size_t)kSplitRecs * su * 16;
     if (lds > 65536) {
@@ -984,14 +1277,18 @@ hipError_t launch_bin_scatter(const Geom& g, const wt_fragments& f, void* ws, co
       if (e2 != hipSuccess) return e2;
     }
     hipLaunchKernelGGL(kern, dim3(g.nsuper), dim3(kSplitThreads), lds, s, g, offsets1, offsets, head1, tail1, head,
-                       tail);
+                       tail, hdr, stamp1);
     return hipGetLastError();
   };
   if (g.C == 1)
-    return record_index ? split(k_split<1, true>, staged_head_units(1) + staged_tail_units(true))
-                        : split(k_split<1, false>, staged_head_units(1) + staged_tail_units(false));
-  return record_index ? split(k_split<3, true>, staged_head_units(3) + staged_tail_units(true))
-                      : split(k_split<3, false>, staged_head_units(3) + staged_tail_units(false));
+    e = record_index ? split(k_split<1, true>, staged_head_units(1) + staged_tail_units(true))
+                     : split(k_split<1, false>, staged_head_units(1) + staged_tail_units(false));
+  else
+    e = record_index ? split(k_split<3, true>, staged_head_units(3) + staged_tail_units(true))
+                     : split(k_split<3, false>, staged_head_units(3) + staged_tail_units(false));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_seal_split, dim3(1), dim3(1), 0, s, hdr, stamp1, stamp);
+  return hipGetLastError();
 }
 
 hipError_t launch_bin(const Geom& g, const wt_fragments& f, void* ws, const Layout& l, bool record_index,

@@ -81,6 +81,35 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
   return v;
 }
 
+// Whether this workgroup may read the binned stream: the workspace header carries the stamp of a complete binning
+// under the caller's layout and record format, and the tile the workgroup takes and that tile's record range lie
+// inside the layout. Otherwise the first thread raises kWsErrMismatch (reported by wt_dropped_count) and the
+// workgroup returns before it reads a record or writes an output. Uniform across the workgroup.
+__device__ __forceinline__ bool binned_ok(const Binned& b, const Geom& g, uint32_t& tile) {
+  // the stamp and the tile index are loaded together (order[] lies inside the layout, which the host checked
+  // against the workspace size; its value is used only once the stamp matched and it is a tile of the layout)
+  const unsigned long long st = __hip_atomic_load(&b.hdr->binned, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  tile = b.order[blockIdx.x];
+  bool ok = st == b.stamp && tile < g.ntiles;
+  if (ok) {
+    const uint32_t beg = b.offsets[tile * g.NX], end = b.offsets[(tile + 1) * g.NX];
+    ok = beg <= end && end <= b.cap;
+  }
+  if (!ok && threadIdx.x == 0) ws_raise(b.hdr, kWsErrMismatch);
+  return ok;
+}
+
+// WT_DETERMINISTIC: the first thread applies records [beg, end) one after another in binned order (no two updates
+// of an on-chip sum race, so every sum is taken in the same order on every run). Returns true when it did, so the
+// caller skips its parallel loop; the caller's barrier follows as usual.
+template <typename Fn>
+__device__ __forceinline__ bool serial_records(const Geom& g, uint32_t beg, uint32_t end, Fn&& fn) {
+  if (!g.serial) return false;
+  if (threadIdx.x == 0)
+    for (uint32_t i = beg; i < end; ++i) fn(i);
+  return true;
+}
+
 // Tile of pixel p and its index inside the tile (row-major within the tile).
 __device__ __forceinline__ void tile_locate(const Geom& g, uint32_t p, uint32_t& tile, uint32_t& local) {
   const uint32_t y = fastdiv(p, g.divW);

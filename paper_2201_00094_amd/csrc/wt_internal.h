@@ -13,6 +13,7 @@ namespace wt {
 // and each XCD has its own L2. The binning keeps one write frontier per (tile, XCD class) so that the
 // partial cache lines of a frontier are filled inside a single L2 before they are written back.
 constexpr uint32_t kClasses = 8;
+constexpr uint32_t kCursorPad = 1;  // words per write cursor in the workspace's cursor tables
 constexpr uint32_t kPer = 8;               // fragments per scatter thread (held in registers)
 constexpr uint32_t kMaxLdsBins = 8192;     // bins one scatter table holds (super-tiles of a two-level binning)
 constexpr uint32_t kMaxHistBins = 36864;   // tiles one histogram table holds (144 KB of LDS)
@@ -22,6 +23,7 @@ constexpr uint32_t kMaxSub = 64;           // tiles per super-tile at most
 constexpr uint32_t kLdsBytes = 160 * 1024; // LDS of one CDNA4 compute unit (also the per-workgroup limit)
 constexpr uint32_t kMaxTilePx = 2048;
 constexpr uint32_t kTileThreads = 1024;    // workgroup size of the per-tile kernels
+constexpr uint32_t kScanRange = 16384;     // segments one scan workgroup covers (a multiple of kClasses)
 constexpr float kAlphaMax = 0.99999994f;   // 1 - 2^-24
 
 // Division of 32-bit values by a divisor fixed per frame, without a hardware divide (Granlund and Montgomery,
@@ -130,6 +132,7 @@ struct Geom {
   uint32_t ep;           // 1: the build accumulates endpoint masses (M <= 32, one pixel/channel per thread)
   uint32_t tight;        // 1: per-pixel depth bounds (WT_TIGHT_DEPTH); the tile kernels keep them in LDS
   uint32_t temporal;     // 1: tiles sized for the one-pass render against the previous frame (WT_TEMPORAL)
+  uint32_t serial;       // 1: WT_DETERMINISTIC (stream-order binning by one thread, one thread per tile's records)
   uint32_t sthreads;     // scatter workgroup size
   uint32_t kper;         // fragments per scatter thread (4 or kPer)
   uint32_t chunk;        // fragments per scatter workgroup = sthreads * kPer (also the class granularity)
@@ -143,13 +146,50 @@ constexpr uint32_t head_dwords(uint32_t C) { return 2 + C; }
 constexpr uint32_t tail_dwords(bool with_index) { return 3 + (with_index ? 1 : 0); }
 constexpr uint32_t record_dwords(uint32_t C, bool with_index) { return head_dwords(C) + tail_dwords(with_index); }
 
+// The first bytes of every workspace: what the binning left there, so that each later call over the binned stream
+// can check that the stream was binned completely, under its own layout, before it reads a table or a record.
+struct WsHeader {
+  unsigned long long dropped;  // fragments dropped by the last binning (pixel out of range, NaN)
+  uint32_t errors;             // sticky kWsErr* bits, reported and cleared by wt_dropped_count
+  uint32_t fault;              // the current binning's scatter refused to write (cleared by the count)
+  unsigned long long counted;  // stamp of the last count: layout, record format and the stream counted
+  unsigned long long binned;   // stamp of the last complete binning (layout and record format), or 0
+  unsigned long long magic;    // kWsMagic once the device has written this header (fresh memory holds anything)
+};
+constexpr unsigned long long kWsMagic = 0x5754776f726b7370ull;
+constexpr uint32_t kWsErrMismatch = 1u;  // a call over the binned stream found no complete binning in its layout
+constexpr uint32_t kWsErrScatter = 2u;   // a scatter did not follow a count of the same stream and layout, or its
+                                         // stream put more fragments in a tile than were counted
+
+// Raise an error bit in a header, starting the error word from zero if the device never wrote this header.
+__device__ __forceinline__ void ws_raise(WsHeader* h, uint32_t bit) {
+  if (h->magic != kWsMagic) {
+    h->errors = 0;
+    h->magic = kWsMagic;
+  }
+  atomicOr(&h->errors, bit);
+}
+
+// 64-bit FNV-1a over 32-bit words; never 0 (0 marks "no binning").
+__host__ __device__ inline unsigned long long stamp_words(const uint32_t* w, int n) {
+  unsigned long long h = 0xcbf29ce484222325ull;
+  for (int i = 0; i < n; ++i) {
+    for (int b = 0; b < 4; ++b) {
+      h ^= (w[i] >> (8 * b)) & 0xffu;
+      h *= 0x100000001b3ull;
+    }
+  }
+  return h ? h : 1ull;
+}
+
 // Device workspace: a header, the tile tables and the binned records.
 struct Layout {
-  size_t header;   // uint64 dropped counter + spare
+  size_t header;   // WsHeader (256 bytes reserved)
   size_t counts;   // uint32 [NX][ntiles]
   size_t offsets;  // uint32 [ntiles * NX + 1], tile-major: segment (t, x) = [off[t*NX+x], off[t*NX+x+1])
   size_t cursors;  // uint32 [NX][ntiles]
   size_t order;    // uint32 [ntiles]: tiles by descending fragment count (heaviest first)
+  size_t scan;     // uint32 [G][1 + 256]: per-workgroup totals and size-class counts of a multi-workgroup scan
   size_t heads;    // uint32 [cap][head_dwords(C)]
   size_t tails;    // uint32 [cap][tail_dwords(true)]
   // two-level binning only: the first level over super-tiles
@@ -169,7 +209,10 @@ struct Binned {
   const uint32_t* order;  // workgroup b processes tile order[b]
   const uint32_t* head;
   const uint32_t* tail;
-  uint32_t DH, DT; // dwords per head / tail entry
+  uint32_t DH, DT;        // dwords per head / tail entry
+  WsHeader* hdr;          // checked by every tile kernel before it reads a table: hdr->binned == stamp
+  unsigned long long stamp;
+  uint64_t cap;           // records the layout holds
 };
 
 // backward = true picks tiles for the gradient kernel, which holds cell values and their adjoints.
@@ -182,6 +225,11 @@ size_t lds_tile_bytes(const Geom& g, bool with_accum);
 size_t lds_backward_bytes(const Geom& g);
 size_t lds_temporal_bytes(const Geom& g);
 Binned binned_view(const Geom& g, const Layout& l, const void* ws, bool with_index);
+// Stamp of a complete binning under this layout and record format, and of a count of this stream under it.
+unsigned long long layout_stamp(const Geom& g, const Layout& l, bool with_index);
+unsigned long long count_stamp(const Geom& g, const Layout& l, const wt_fragments& f);
+// Fill n words at p with v (a kernel: safe inside captured graphs).
+hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
 
 // Launchers (return hipError_t of the launch).
 hipError_t launch_bin(const Geom& g, const wt_fragments& f, void* ws, const Layout& l, bool record_index,

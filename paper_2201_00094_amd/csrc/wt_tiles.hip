@@ -143,6 +143,11 @@ __device__ __forceinline__ void build_add(acc_t* lc, const Geom& g, const Frag<C
 template <int C>
 __device__ __forceinline__ void build_tile(const Binned& b, const Geom& g, const TileRef& r, acc_t* lc,
                                            const uint32_t* lb) {
+  if (serial_records(g, r.beg, r.end, [&](uint32_t i) {
+        Frag<C> f;
+        if (load_head<C>(b, i, f)) build_add<C>(lc, g, f, lb);
+      }))
+    return;
   uint32_t i = r.beg + threadIdx.x;
   // two records per thread per step keep more loads in flight
   for (; i + blockDim.x < r.end; i += 2 * blockDim.x) {
@@ -302,6 +307,11 @@ __device__ __forceinline__ void build_ep_add(acc_t* le, const Geom& g, const Fra
 template <int C>
 __device__ __forceinline__ void build_ep_tile(const Binned& b, const Geom& g, const TileRef& r, acc_t* le,
                                               const uint32_t* lb) {
+  if (serial_records(g, r.beg, r.end, [&](uint32_t i) {
+        Frag<C> f;
+        if (load_head<C>(b, i, f)) build_ep_add<C>(le, g, f, lb);
+      }))
+    return;
   uint32_t i = r.beg + threadIdx.x;
   // kBuildUnroll 12-byte head records per thread in flight per step
   for (; i + (kBuildUnroll - 1) * blockDim.x < r.end; i += kBuildUnroll * blockDim.x) {
@@ -584,6 +594,11 @@ __device__ __forceinline__ void eval_add(const T* lc, acc_t* la, const Geom& g, 
 template <int C, bool CELLS, typename T, bool SUMA = true>
 __device__ __forceinline__ void eval_tile(const Binned& b, const Geom& g, const TileRef& r, const T* lc,
                                           acc_t* la, const uint32_t* lb) {
+  if (serial_records(g, r.beg, r.end, [&](uint32_t i) {
+        Frag<C> f;
+        if (load_full<C>(b, i, f)) eval_add<C, CELLS, T, SUMA>(lc, la, g, f, lb);
+      }))
+    return;
   uint32_t i = r.beg + threadIdx.x;
   // kEvalUnroll 24-byte records per thread in flight per step
   for (; i + (kEvalUnroll - 1) * blockDim.x < r.end; i += kEvalUnroll * blockDim.x) {
@@ -643,7 +658,9 @@ template <int C, typename TS>
 __global__ __launch_bounds__(kTileThreads) void k_build(Binned b, Geom g, TS* __restrict__ coeffs) {
   extern __shared__ acc_t smem_d[];
   acc_t* lc = smem_d;
-  const TileRef r = tile_ref(g, b, b.order[blockIdx.x]);
+  uint32_t tile;
+  if (!binned_ok(b, g, tile)) return;
+  const TileRef r = tile_ref(g, b, tile);
   // per-pixel depth bounds after the coefficient region
   uint32_t* lb = g.tight ? (uint32_t*)(smem_d + (g.ep ? C * (g.M + 1) : C * g.M) * g.tile_px) : nullptr;
   if (lb) bounds_tile<C>(b, g, r, lb);
@@ -673,7 +690,9 @@ __global__ __launch_bounds__(kTileThreads) void k_evaluate(Binned b, Geom g, con
   acc_t* la = smem_d;                              // [AL][TP] FP64
   float* lc = (float*)(smem_d + g.AL * TP);        // [C*M][TP] FP32
   uint32_t* lb = g.tight ? (uint32_t*)(lc + C * g.M * TP) : nullptr;  // per-pixel depth bounds
-  const TileRef r = tile_ref(g, b, b.order[blockIdx.x]);
+  uint32_t tile;
+  if (!binned_ok(b, g, tile)) return;
+  const TileRef r = tile_ref(g, b, tile);
   if (lb) bounds_tile<C>(b, g, r, lb);
   coeff_tile_io<C, TS, 0>(g, r, lc, const_cast<TS*>(coeffs));
   for (uint32_t lp = threadIdx.x; lp < TP; lp += blockDim.x) {
@@ -701,7 +720,9 @@ __global__ __launch_bounds__(kTileThreads) void k_render(Binned b, Geom g, TS* _
                                                          float bg1, float bg2, float* __restrict__ out) {
   extern __shared__ acc_t smem_d[];
   const uint32_t TP = g.tile_px;
-  const TileRef r = tile_ref(g, b, b.order[blockIdx.x]);
+  uint32_t tile;
+  if (!binned_ok(b, g, tile)) return;
+  const TileRef r = tile_ref(g, b, tile);
   const float bg[3] = {bg0, bg1, bg2};
   if (g.ep) {
     // LDS: endpoint masses [C*(M+1)][TP] FP64 (then FP32 cells [C*M][TP] and sums of a [C][TP] in their
@@ -860,7 +881,9 @@ __global__ __launch_bounds__(kTileThreads) void k_render_temporal(Binned b, Geom
                                                                   float* __restrict__ out) {
   extern __shared__ acc_t smem_d[];
   const uint32_t TP = g.tile_px;
-  const TileRef r = tile_ref(g, b, b.order[blockIdx.x]);
+  uint32_t tile;
+  if (!binned_ok(b, g, tile)) return;
+  const TileRef r = tile_ref(g, b, tile);
   const float bg[3] = {bg0, bg1, bg2};
   acc_t* le = smem_d;
   acc_t* la = smem_d + C * (g.M + 1) * TP;
@@ -868,7 +891,11 @@ __global__ __launch_bounds__(kTileThreads) void k_render_temporal(Binned b, Geom
   for (uint32_t e = threadIdx.x; e < (C * (g.M + 1) + 3) * TP; e += blockDim.x) smem_d[e] = 0.0;
   with_m(g, [&](auto mm) { prev_cells<C, TS, decltype(mm)::value>(g, r, prev, map, lc); });
   __syncthreads();
-  uint32_t i = r.beg + threadIdx.x;
+  const bool serial = serial_records(g, r.beg, r.end, [&](uint32_t i) {
+    Frag<C> f;
+    if (load_full<C>(b, i, f)) temporal_add<C>(le, lc, la, g, f);
+  });
+  uint32_t i = serial ? r.end : r.beg + threadIdx.x;
   for (; i + (kEvalUnroll - 1) * blockDim.x < r.end; i += kEvalUnroll * blockDim.x) {
     Frag<C> f[kEvalUnroll];
     bool ok[kEvalUnroll];

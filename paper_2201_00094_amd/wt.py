@@ -27,6 +27,7 @@ class FrameSpec:
     dtype: str = "f32"
     tight: bool = False   # per-pixel depth bounds (WT_TIGHT_DEPTH): pass each frame's stream whole
     temporal: bool = False  # one-pass render against the previous frame (WT_TEMPORAL): tiles sized for it
+    deterministic: bool = False  # WT_DETERMINISTIC debug mode: bit-identical results run to run (slow)
 
     @property
     def pixels(self) -> int:
@@ -43,7 +44,8 @@ class FrameSpec:
     def c_desc(self) -> _lib.FrameDesc:
         if self.dtype not in DTYPES:
             raise ValueError("unknown coefficient storage %r" % self.dtype)
-        flags = (_lib.WT_TIGHT_DEPTH if self.tight else 0) | (_lib.WT_TEMPORAL if self.temporal else 0)
+        flags = (_lib.WT_TIGHT_DEPTH if self.tight else 0) | (_lib.WT_TEMPORAL if self.temporal else 0) | \
+            (_lib.WT_DETERMINISTIC if self.deterministic else 0)
         return _lib.desc(self.width, self.height, self.rank, self.channels, DTYPES[self.dtype], flags)
 
     def coeff_shape(self):

@@ -80,7 +80,7 @@ def test_validation_errors_before_any_launch(lib):
     assert lib.wt_bin(C.byref(_lib.desc(8, 8, 5, 3, e5)), C.byref(ok), ws, 1 << 30, None) == _lib.WT_ERR_UNSUPPORTED
     assert lib.wt_workspace_bytes(C.byref(_lib.desc(8, 8, 4, 3, e5)), 10) > 0
     # flags: WT_TIGHT_DEPTH and WT_TEMPORAL are defined, and exclude each other
-    assert lib.wt_bin(C.byref(_lib.desc(8, 8, 3, 1, 0, 4)), C.byref(ok), ws, 1 << 30, None) == _lib.WT_ERR_INVALID
+    assert lib.wt_bin(C.byref(_lib.desc(8, 8, 3, 1, 0, 8)), C.byref(ok), ws, 1 << 30, None) == _lib.WT_ERR_INVALID
     assert lib.wt_workspace_bytes(C.byref(_lib.desc(8, 8, 3, 1, 0, _lib.WT_TIGHT_DEPTH)), 10) > 0
     assert lib.wt_workspace_bytes(C.byref(_lib.desc(8, 8, 3, 1, 0, _lib.WT_TEMPORAL)), 10) > 0
     both = _lib.WT_TIGHT_DEPTH | _lib.WT_TEMPORAL

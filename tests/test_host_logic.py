@@ -99,3 +99,18 @@ def test_round_f64_to_f16_bf16(tmp_path):
     for v, g in zip(x[~nan], got[~nan, 1]):
         assert g == _bf16_nearest(float(v), table), (float(v), hex(g))
     assert ((got[nan, 1] & 0x7f80) == 0x7f80).all() and ((got[nan, 1] & 0x7f) != 0).all()
+
+
+@pytest.mark.skipif(not os.path.exists(HIPCC) and shutil.which("hipcc") is None, reason="hipcc not available")
+def test_workspace_stamps_tell_layouts_and_streams_apart(tmp_path):
+    """The stamps the binning leaves in the workspace header: every description a caller could confuse with the
+    one a stream was binned under (rank, frame size, channels, depth bounds, one-pass tiles, gradient records,
+    workspace size) stamps differently, and a count is tied to the stream it counted (size and array addresses)."""
+    exe = tmp_path / "stamp_check"
+    subprocess.check_call([HIPCC, "-O2", "-std=c++17", "-I", os.path.join(ROOT, "include"),
+                           "-I", os.path.join(ROOT, "paper_2201_00094_amd", "csrc"),
+                           os.path.join(ROOT, "tests", "host", "stamp_check.cpp"), "-o", str(exe)],
+                          stderr=subprocess.DEVNULL)
+    res = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300)
+    assert res.returncode == 0, res.stdout
+    assert "bad 0" in res.stdout
