@@ -271,7 +271,12 @@ __global__ __launch_bounds__(1024) void k_seal(WsHeader* h, const uint32_t* __re
   }
   if (mine) bad = 1;
   __syncthreads();
-  if (threadIdx.x == 0) h->binned = (!bad && h->fault == 0 && h->counted == cstamp) ? stamp : 0ull;
+  if (threadIdx.x == 0) {
+    const bool ok = !bad && h->fault == 0 && h->counted == cstamp;
+    h->binned = ok ? stamp : 0ull;
+    // a scatter that did not belong to its count (another stream, arrays changed since the count, run twice)
+    if (!ok) ws_raise(h, kWsErrScatter);
+  }
 }
 
 // After the split of a two-level binning: complete when the first level was (the split only moves its records).
@@ -292,10 +297,15 @@ hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Streaming 16-byte loads (non-temporal: each fragment is read once), defined with the scatter below.
+template <bool NT>
+__device__ __forceinline__ uint4 load_stream_u4(const uint32_t* p);
+
 // ------------------------------------------------------------------------------------------------ histogram
 
 // Workgroups of 256 threads, or of 1024 when the tile table is large (up to 144 KB of LDS leaves one workgroup per
-// compute unit, which then still has sixteen waves of loads in flight).
+// compute unit, which then still has sixteen waves of loads in flight). The pixel ids are read with non-temporal
+// loads (smoke frame: 0.132 -> 0.121 ms for the count).
 
 template <int kHistThreads>
 __global__ __launch_bounds__(kHistThreads) void k_hist_lds(const uint32_t* __restrict__ pixel, uint32_t F, Geom g,
@@ -323,7 +333,7 @@ __global__ __launch_bounds__(kHistThreads) void k_hist_lds(const uint32_t* __res
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const uint32_t iv = v0 + v * kHistThreads + threadIdx.x;
-          q[v] = iv < nv ? q4[iv] : make_uint4(0u, 0u, 0u, 0u);
+          q[v] = iv < nv ? load_stream_u4<true>((const uint32_t*)(q4 + iv)) : make_uint4(0u, 0u, 0u, 0u);
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -840,7 +850,7 @@ __global__ __launch_bounds__(THREADS, PER == 4 ? 8 : 1) void k_scatter_staged(wt
   load_chunk<C, PER>(f, base, i0, n, vec, r);
   // only the stream the preceding count counted, under the same layout, is scattered into its segments (the
   // stamp is loaded behind the chunk, so the check adds no wait of its own)
-  if (__hip_atomic_load(&hdr->counted, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != cstamp) {
+  if (hdr->counted != cstamp) {
     if (threadIdx.x == 0) scatter_refuse(hdr);
     return;
   }
@@ -932,7 +942,7 @@ __global__ __launch_bounds__(THREADS) void k_scatter_global(wt_fragments f, Geom
                                                                     WsHeader* hdr, unsigned long long cstamp,
                                                                     uint32_t cap) {
   constexpr uint32_t DH = head_dwords(C), DT = tail_dwords(IDX);
-  if (__hip_atomic_load(&hdr->counted, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != cstamp) {
+  if (hdr->counted != cstamp) {
     if (threadIdx.x == 0) scatter_refuse(hdr);
     return;
   }
@@ -1025,7 +1035,7 @@ __global__ __launch_bounds__(kSplitThreads) void k_split(Geom g, const uint32_t*
                                                          const WsHeader* hdr, unsigned long long level1) {
   constexpr uint32_t DH = head_dwords(C), DT = tail_dwords(IDX);
   // only a complete first level is split (its records then hold valid super-tile-local pixels)
-  if (__hip_atomic_load(&hdr->binned, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != level1) return;
+  if (hdr->binned != level1) return;
   constexpr uint32_t SH = staged_head_units(C), ST = staged_tail_units(IDX), SU = SH + ST;
   extern __shared__ uint4 srec[];                // [kSplitRecs][SU]
   __shared__ uint32_t cur[kMaxSub], cnt[kMaxSub], pre[kMaxSub];

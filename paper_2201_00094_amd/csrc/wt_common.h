@@ -87,8 +87,9 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 // workgroup returns before it reads a record or writes an output. Uniform across the workgroup.
 __device__ __forceinline__ bool binned_ok(const Binned& b, const Geom& g, uint32_t& tile) {
   // the stamp and the tile index are loaded together (order[] lies inside the layout, which the host checked
-  // against the workspace size; its value is used only once the stamp matched and it is a tile of the layout)
-  const unsigned long long st = __hip_atomic_load(&b.hdr->binned, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // against the workspace size; its value is used only once the stamp matched and it is a tile of the layout).
+  // Plain loads: the header was written by earlier kernels, and this kernel only raises error bits in it.
+  const unsigned long long st = b.hdr->binned;
   tile = b.order[blockIdx.x];
   bool ok = st == b.stamp && tile < g.ntiles;
   if (ok) {
