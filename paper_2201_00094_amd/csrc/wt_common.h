@@ -23,15 +23,15 @@ template <>
 __device__ __forceinline__ float widen<bf16_t>(bf16_t v) { return __uint_as_float((uint32_t)v.u << 16); }
 
 // Round an FP64 on-chip sum to the storage type once, to nearest even (FP32 by the hardware conversion, FP16 and
-// BF16 on the FP64 bit pattern).
+// BF16 through FP32 rounded to odd).
 template <typename T>
 __device__ __forceinline__ T narrow_d(double v);
 template <>
 __device__ __forceinline__ float narrow_d<float>(double v) { return (float)v; }
 template <>
-__device__ __forceinline__ __half narrow_d<__half>(double v) { return __ushort_as_half(round_f64_bits<10, 15>(v)); }
+__device__ __forceinline__ __half narrow_d<__half>(double v) { return __ushort_as_half(f64_to_f16_bits(v)); }
 template <>
-__device__ __forceinline__ bf16_t narrow_d<bf16_t>(double v) { return bf16_t{round_f64_bits<7, 127>(v)}; }
+__device__ __forceinline__ bf16_t narrow_d<bf16_t>(double v) { return bf16_t{f64_to_bf16_bits(v)}; }
 
 
 // E5B9G9R9 coefficient storage (section 2.1): one 32-bit word per coefficient index holds the magnitudes of the

@@ -83,33 +83,43 @@ __host__ __device__ inline float neg_log1m(float al) {
 #endif
 }
 
-// Round an FP64 value to a narrower binary format once, to nearest with ties to even, on its bit pattern (no
-// intermediate FP32 rounding, which could land a value that lies just off a midpoint of the narrow format exactly
-// on it). The format has MB explicit mantissa bits and exponent bias BIAS (its smallest normal exponent is
-// 1 - BIAS); the result is the format's bit pattern: signed zero, subnormals, overflow to infinity, quiet NaN.
-// FP16: MB = 10, BIAS = 15; BF16: MB = 7, BIAS = 127.
-template <int MB, int BIAS>
-__host__ __device__ inline uint16_t round_f64_bits(double v) {
-  uint64_t u;
-  __builtin_memcpy(&u, &v, 8);
-  constexpr int EB = 15 - MB;                                   // exponent bits of the 16-bit format
-  constexpr uint32_t kInf = ((1u << EB) - 1u) << MB;
-  const uint32_t sign = (uint32_t)(u >> 48) & 0x8000u;
-  const uint64_t a = u & 0x7fffffffffffffffull;
-  if (a >= 0x7ff0000000000000ull) return (uint16_t)(sign | kInf | (a > 0x7ff0000000000000ull ? (1u << (MB - 1)) : 0u));
-  if (a < 0x0010000000000000ull) return (uint16_t)sign;         // zero or an FP64 subnormal: far below the format
-  const int e = (int)(a >> 52) - 1023;                          // |v| = m 2^(e - 52), m in [2^52, 2^53)
-  if (e > BIAS) return (uint16_t)(sign | kInf);
-  const uint64_t m = (a & 0x000fffffffffffffull) | 0x0010000000000000ull;
-  const int emin = 1 - BIAS;
-  const int shift = 52 - MB + (e < emin ? emin - e : 0);        // bits of m below the result's last place
-  if (shift >= 64) return (uint16_t)sign;                       // below half the smallest subnormal
-  const uint64_t q0 = m >> shift, rem = m & ((1ull << shift) - 1ull), half = 1ull << (shift - 1);
-  const uint64_t q = q0 + ((rem > half || (rem == half && (q0 & 1ull))) ? 1ull : 0ull);
-  // normal: biased exponent field plus the mantissa without its leading one (a carry out of the mantissa moves
-  // into the exponent); subnormal: q itself (q = 2^MB is the smallest normal)
-  const uint64_t bits = e >= emin ? ((uint64_t)(e + BIAS) << MB) + q - (1ull << MB) : q;
-  return (uint16_t)(sign | (bits >= kInf ? kInf : (uint32_t)bits));
+// FP64 -> FP32 rounded to odd, as a bit pattern: the nearest FP32 value toward zero, with its last bit set when the
+// conversion is inexact (NaN stays NaN; beyond the FP32 range the largest finite value, odd). Rounding that value
+// once more, to nearest, into a format whose significand is at least two bits shorter at every magnitude (FP16 and
+// BF16, subnormals included) gives the FP64 value rounded once: the odd last bit keeps a value that lies off a
+// midpoint of the narrow format off it (Boldo and Melquiond, "Emulation of FMA and correctly rounded sums: proved
+// algorithms using rounding to odd", IEEE Transactions on Computers, 2008). Two hardware conversions and a compare,
+// where rounding the FP64 bit pattern with integer operations takes some fifty instructions.
+__host__ __device__ inline uint32_t f64_to_f32_odd_bits(double v) {
+  const float f = (float)v;
+  uint32_t u;
+  __builtin_memcpy(&u, &f, 4);
+  const double b = (double)f;
+  if (b != v) {
+    if (__builtin_fabs(b) > __builtin_fabs(v)) u -= 1u;  // rounded away from zero: one place back toward it
+    u |= 1u;
+  }
+  return u;
+}
+
+// FP64 -> FP16 bit pattern, rounded once to nearest even: round to odd in FP32, then the FP32 -> FP16 conversion
+// (to nearest even; one instruction on the GPU).
+__host__ __device__ inline uint16_t f64_to_f16_bits(double v) {
+  const uint32_t u = f64_to_f32_odd_bits(v);
+  float f;
+  __builtin_memcpy(&f, &u, 4);
+  const _Float16 h = (_Float16)f;
+  uint16_t r;
+  __builtin_memcpy(&r, &h, 2);
+  return r;
+}
+
+// FP64 -> BF16 bit pattern, rounded once to nearest even: round to odd in FP32, then to nearest even on the FP32
+// bit pattern (a carry out of the mantissa moves into the exponent, up to infinity); NaN stays a quiet NaN.
+__host__ __device__ inline uint16_t f64_to_bf16_bits(double v) {
+  const uint32_t u = f64_to_f32_odd_bits(v);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
 }
 
 // Frame geometry as the kernels see it.

@@ -1,5 +1,6 @@
-// Host build of the library's FP64 -> FP16 / BF16 rounding (wt_internal.h: round_f64_bits). Reads FP64 bit
-// patterns (hex, one per line) on stdin and prints "f16 bf16" result bit patterns (hex), one line each.
+// Host build of the library's FP64 -> FP16 / BF16 rounding (wt_internal.h: f64_to_f16_bits, f64_to_bf16_bits,
+// FP32 rounded to odd and then to nearest). Reads FP64 bit patterns (hex, one per line) on stdin and prints
+// "f16 bf16" result bit patterns (hex), one line each.
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
@@ -9,7 +10,7 @@ int main() {
   while (scanf("%llx", &u) == 1) {
     double v;
     std::memcpy(&v, &u, 8);
-    printf("%04x %04x\n", (unsigned)wt::round_f64_bits<10, 15>(v), (unsigned)wt::round_f64_bits<7, 127>(v));
+    printf("%04x %04x\n", (unsigned)wt::f64_to_f16_bits(v), (unsigned)wt::f64_to_bf16_bits(v));
   }
   return 0;
 }

@@ -106,6 +106,46 @@ def test_reduced_precision_storage(orc, dtype, step, channels):
     np.testing.assert_allclose(p["out"], g["out"], rtol=0, atol=1e-3)
 
 
+def _midpoint_picks(x32, xn, dtype):
+    """Elements whose FP32 storage value x32 lies exactly halfway between two neighbouring values of the narrow
+    format: (number of such elements, how many of them the narrow storage xn holds as the odd neighbour). Raises if
+    a narrow value there is not one of the two neighbours."""
+    u = x32.astype(np.float32).view(np.uint32).astype(np.int64)
+    mag = np.abs(x32)
+    if dtype == "bf16":
+        mid = ((u & 0xffff) == 0x8000) & (mag < 3.3e38)
+        nb = xn[mid].astype(np.float32).view(np.uint32).astype(np.int64)
+        assert ((nb & 0xffff) == 0).all()
+        hi = nb >> 16
+        lo = u[mid] >> 16
+        assert np.isin(hi - lo, [0, 1]).all(), "a narrow value at a midpoint is not one of its neighbours"
+        return int(mid.sum()), int((hi & 1).sum())
+    normal = mag >= 2.0 ** -14
+    mid = np.where(normal, (u & 0x1fff) == 0x1000, np.mod(mag * 2.0 ** 25, 2.0) == 1.0) & (mag < 65504)
+    half = np.where(normal, np.exp2(np.floor(np.log2(np.maximum(mag, 2.0 ** -14))) - 11), 2.0 ** -25)[mid]
+    assert np.allclose(np.abs(xn[mid] - x32[mid]), half, rtol=0, atol=0), \
+        "a narrow value at a midpoint is not one of its neighbours"
+    bits = xn[mid].astype(np.float16).view(np.uint16)
+    return int(mid.sum()), int((bits & 1).sum())
+
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+def test_storage_rounds_once(dtype):
+    """Reduced storage holds the FP64 on-chip sum rounded once. Where the FP32 storage of the same frame holds a
+    value exactly halfway between two neighbouring values of the narrow format, the FP64 sum lay within half an
+    FP32 step of that midpoint, on either side of it, so a single rounding picks the odd neighbour about as often as
+    the even one; rounding through FP32 would pick the even one every time. 1024 x 512 pixels, rank 3: 8.4 M
+    coefficients, about a thousand such midpoints for FP16 and a hundred for BF16."""
+    f = synth.frame_c1(seed=31, width=1024, height=512, mean=16.0)
+    say("case storage rounds once", dtype, "F", f.count)
+    x32 = gpu_render(f, dtype="f32")["coeffs"]
+    xn = gpu_render(f, dtype=dtype)["coeffs"]
+    n, odd = _midpoint_picks(x32.ravel(), xn.ravel(), dtype)
+    say("  %s: %d FP32 values on a midpoint, %d stored as the odd neighbour" % (dtype, n, odd))
+    assert n >= (400 if dtype == "f16" else 40)
+    assert 0.2 * n <= odd <= 0.8 * n
+
+
 @pytest.mark.parametrize("rank", [1, 3, 4])
 def test_e5b9g9r9_storage(orc, rank):
     """Packed three-channel storage (section 2.1): the decoded coefficients are within one step of the shared

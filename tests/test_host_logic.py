@@ -52,8 +52,13 @@ def _round_inputs():
     mid_b = (b + bn) / 2
     for m in (mid16, mid_b):
         vals += [m, np.nextafter(m, np.inf), np.nextafter(m, -np.inf), -m]
+    # midpoints moved by less than half an FP32 step, where an intermediate FP32 rounding lands on the midpoint
+    for m in (mid16, mid_b):
+        vals += [m * (1 + 2.0 ** -30), m * (1 - 2.0 ** -30), -m * (1 + 2.0 ** -40)]
     vals.append(np.array([0.0, -0.0, 65504.0, 65519.99, 65520.0, 65536.0, 2.0 ** -24, 2.0 ** -25, 2.0 ** -26,
-                          3 * 2.0 ** -26, 2.0 ** -14, 1e300, -1e300, 5e-324, np.inf, -np.inf, np.nan]))
+                          3 * 2.0 ** -26, 2.0 ** -14, 1e300, -1e300, 5e-324, 3.3e38, 3.39e38, 3.402823e38, 3.5e38,
+                          -3.5e38, 2.0 ** -149, 2.0 ** -150, 3 * 2.0 ** -151, 2.0 ** -133, 1.5 * 2.0 ** -133,
+                          np.inf, -np.inf, np.nan]))
     return np.concatenate(vals)
 
 
@@ -76,8 +81,10 @@ def _bf16_nearest(v, table):
 
 @pytest.mark.skipif(not os.path.exists(HIPCC) and shutil.which("hipcc") is None, reason="hipcc not available")
 def test_round_f64_to_f16_bf16(tmp_path):
-    """The library rounds FP64 sums straight to FP16 / BF16 storage: bit-equal to NumPy's binary16 conversion of
-    the FP64 value, and to the exactly nearest BF16 value (ties to even) found by search."""
+    """The library rounds FP64 sums to FP16 / BF16 storage once (FP32 rounded to odd, then to nearest): bit-equal
+    to NumPy's binary16 conversion of the FP64 value, and to the exactly nearest BF16 value (ties to even) found by
+    search, also for values one FP64 step off a midpoint of either format, which a plain FP64 -> FP32 -> narrow
+    conversion would round the wrong way."""
     import numpy as np
     exe = tmp_path / "round_check"
     subprocess.check_call([HIPCC, "-O2", "-std=c++17", "-I", os.path.join(ROOT, "include"),
