@@ -123,14 +123,20 @@ Geom make_geom(const wt_frame_desc& d, bool backward) {
   g.sY = (g.tilesY + g.SH - 1) / g.SH;
   g.nsuper = g.sX * g.sY;
   g.NX = g.lds_bins ? kClasses : 1;
-  // Scatter: 1024 threads, 8 fragments per thread (one workgroup per compute unit), or 4 per thread where the
-  // tile tables (of the binning level that scatters) and a 1024-record round fit half the LDS, so that two
-  // workgroups share a compute unit.
+  // Scatter: two workgroups per compute unit where the tile tables (of the binning level that scatters) and a
+  // 1024-record round fit half the LDS, so that one workgroup's loads overlap the other's ranking, staging and
+  // writes: one channel, 1024 threads with 4 fragments each (64 registers, eight waves per SIMD); three channels,
+  // 512 threads with 8 fragments each (the three-channel fragment needs about 110 registers: four waves per SIMD).
+  // Otherwise one workgroup of 1024 threads with 8 fragments each per compute unit. Chunks are powers of two.
+  // (Glass 3840x2160: the three-channel form took the scatter phases from 7.86 to 7.22 ms.)
+  // (a one-channel record stages in at most 32 bytes, index or not, a three-channel one in at most 40: 1024 of
+  // them take 32 or 40 KB)
   g.sthreads = 1024;
+  g.kper = kPer;
   const uint32_t bins = g.two ? g.nsuper : g.rb;
-  // (one channel only: the three-channel fragment does not fit the 64 registers of eight waves per SIMD)
-  // (a one-channel record stages in at most 32 bytes, index or not: 1024 of them take 32 KB)
-  g.kper = (g.C == 1 && g.lds_bins && 8ull * bins + 1024ull * 32 <= kLdsBytes / 2 - 1024) ? 4 : kPer;
+  const bool two_wg = g.lds_bins && 8ull * bins + 1024ull * (g.C == 1 ? 32 : 40) <= kLdsBytes / 2 - 1024;
+  if (two_wg && g.C == 1) g.kper = 4;
+  if (two_wg && g.C == 3) g.sthreads = 512;
   g.chunk = g.sthreads * g.kper;
   return g;
 }
@@ -321,44 +327,48 @@ __global__ __launch_bounds__(kHistThreads) void k_hist_lds(const uint32_t* __res
   const bool first = t0 == 0;
   for (uint32_t t = threadIdx.x; t < nt; t += blockDim.x) lh[t] = 0;
   __syncthreads();
-  for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
-    const uint32_t base = c * g.chunk;
-    const uint32_t n = std::min<uint32_t>(g.chunk, F - base);
-    if (vec && n == g.chunk) {
-      // chunk / 4 uint4 per chunk; up to four per thread in flight at a time
-      const uint4* q4 = (const uint4*)(pixel + base);
-      const uint32_t nv = g.chunk / 4;
-      for (uint32_t v0 = 0; v0 < nv; v0 += 4 * kHistThreads) {
-        uint4 q[4];
+  // The workgroup's whole chunks (chunk k of the workgroup is c = blockIdx.x + k gridDim.x, all of its class) as one
+  // flat range of 16-byte units, so that every thread has four loads in flight whatever the chunk size; chunk sizes
+  // are powers of two (threads per scatter workgroup times fragments per thread).
+  const uint32_t nfull = vec ? F / g.chunk : 0;
+  const uint32_t kfull = blockIdx.x < nfull ? (nfull - 1 - blockIdx.x) / gridDim.x + 1 : 0;
+  const uint32_t nv = g.chunk / 4, lnv = __builtin_ctz(nv);
+  const uint32_t units = kfull * nv;
+  for (uint32_t u0 = 0; u0 < units; u0 += 4 * kHistThreads) {
+    uint4 q[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const uint32_t iv = v0 + v * kHistThreads + threadIdx.x;
-          q[v] = iv < nv ? load_stream_u4<true>((const uint32_t*)(q4 + iv)) : make_uint4(0u, 0u, 0u, 0u);
-        }
+    for (int v = 0; v < 4; ++v) {
+      const uint32_t u = u0 + v * kHistThreads + threadIdx.x;
+      const uint32_t c = blockIdx.x + (u >> lnv) * gridDim.x;
+      q[v] = u < units ? load_stream_u4<true>(pixel + (uint64_t)c * g.chunk + 4 * (u & (nv - 1)))
+                       : make_uint4(0u, 0u, 0u, 0u);
+    }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          if (v0 + v * kHistThreads + threadIdx.x >= nv) continue;
-          const uint32_t ps[4] = {q[v].x, q[v].y, q[v].z, q[v].w};
+    for (int v = 0; v < 4; ++v) {
+      if (u0 + v * kHistThreads + threadIdx.x >= units) continue;
+      const uint32_t ps[4] = {q[v].x, q[v].y, q[v].z, q[v].w};
 #pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            if (ps[k] < g.P) {
-              const uint32_t t = tile_of(g, ps[k]) - t0;
-              if (t < nt) atomicAdd(&lh[t], 1u);
-            } else if (first) {
-              ++nd;
-            }
-          }
-        }
-      }
-    } else {
-      for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-        const uint32_t p = pixel[base + i];
-        if (p < g.P) {
-          const uint32_t t = tile_of(g, p) - t0;
+      for (int k = 0; k < 4; ++k) {
+        if (ps[k] < g.P) {
+          const uint32_t t = tile_of(g, ps[k]) - t0;
           if (t < nt) atomicAdd(&lh[t], 1u);
         } else if (first) {
           ++nd;
         }
+      }
+    }
+  }
+  // the rest: the partial last chunk, or every chunk of an unaligned stream
+  for (uint32_t c = blockIdx.x + kfull * gridDim.x; c < nchunks; c += gridDim.x) {
+    const uint32_t base = c * g.chunk;
+    const uint32_t n = std::min<uint32_t>(g.chunk, F - base);
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+      const uint32_t p = pixel[base + i];
+      if (p < g.P) {
+        const uint32_t t = tile_of(g, p) - t0;
+        if (t < nt) atomicAdd(&lh[t], 1u);
+      } else if (first) {
+        ++nd;
       }
     }
   }
@@ -824,7 +834,7 @@ __device__ __forceinline__ void scatter_refuse(WsHeader* hdr) {
 }
 
 template <int C, bool IDX, int THREADS, int PER>
-__global__ __launch_bounds__(THREADS, PER == 4 ? 8 : 1) void k_scatter_staged(wt_fragments f, Geom g, int vec,
+__global__ __launch_bounds__(THREADS, PER == 4 ? 8 : (THREADS == 512 ? 4 : 1)) void k_scatter_staged(wt_fragments f, Geom g, int vec,
                                                                     uint32_t stage,
                                                                     uint32_t* __restrict__ cursors,
                                                                     uint32_t* __restrict__ head,
@@ -1130,17 +1140,17 @@ static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 // more often: 512, 2.07 ms).
 constexpr uint32_t kStageTwoWg = 1024;
 
-template <int C, bool IDX, int PER>
+template <int C, bool IDX, int PER, int THREADS>
 static hipError_t launch_scatter_t(const Geom& g, const wt_fragments& f, int vec, uint32_t* cursors,
                                    uint32_t* head, uint32_t* tail, WsHeader* hdr,
                                    unsigned long long cstamp, uint32_t cap, uint32_t nchunks, hipStream_t s) {
-  constexpr int THREADS = 1024;
   if (g.lds_bins) {
     constexpr uint32_t RB = staged_record_bytes(C, IDX);
     // largest power-of-two round beside the tile tables (1 KB left for static LDS), within half the LDS when two
     // workgroups share a compute unit
-    const size_t budget = (PER == 4 ? kLdsBytes / 2 : kLdsBytes) - 1024;
-    uint32_t stage = std::min<uint32_t>(g.chunk, PER == 4 ? kStageTwoWg : g.chunk);
+    constexpr bool kTwoWg = PER == 4 || THREADS == 512;
+    const size_t budget = (kTwoWg ? kLdsBytes / 2 : kLdsBytes) - 1024;
+    uint32_t stage = std::min<uint32_t>(g.chunk, kTwoWg ? kStageTwoWg : g.chunk);
     while (stage > 256 && (size_t)stage * RB + 8ull * g.rb > budget) stage >>= 1;
     const size_t lds = (size_t)stage * RB + 8ull * g.rb;
     auto k = k_scatter_staged<C, IDX, THREADS, PER>;
@@ -1162,8 +1172,10 @@ static hipError_t launch_scatter(const Geom& g, const wt_fragments& f, int vec, 
                                  uint32_t* head, uint32_t* tail, WsHeader* hdr,
                                  unsigned long long cstamp, uint32_t cap, uint32_t nchunks, hipStream_t s) {
   if (g.kper == 4)
-    return launch_scatter_t<C, IDX, 4>(g, f, vec, cursors, head, tail, hdr, cstamp, cap, nchunks, s);
-  return launch_scatter_t<C, IDX, 8>(g, f, vec, cursors, head, tail, hdr, cstamp, cap, nchunks, s);
+    return launch_scatter_t<C, IDX, 4, 1024>(g, f, vec, cursors, head, tail, hdr, cstamp, cap, nchunks, s);
+  if (g.sthreads == 512)
+    return launch_scatter_t<C, IDX, kPer, 512>(g, f, vec, cursors, head, tail, hdr, cstamp, cap, nchunks, s);
+  return launch_scatter_t<C, IDX, kPer, 1024>(g, f, vec, cursors, head, tail, hdr, cstamp, cap, nchunks, s);
 }
 
 hipError_t launch_bin_count(const Geom& g, const wt_fragments& f, void* ws, const Layout& l, hipStream_t s) {

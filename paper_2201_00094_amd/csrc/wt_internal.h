@@ -18,7 +18,7 @@ constexpr uint32_t kPer = 8;               // fragments per scatter thread (held
 constexpr uint32_t kMaxLdsBins = 8192;     // bins one scatter table holds (super-tiles of a two-level binning)
 constexpr uint32_t kMaxHistBins = 36864;   // tiles one histogram table holds (144 KB of LDS)
 constexpr uint32_t kTwoLevelTiles = 4096;  // frames with more tiles are binned in two levels (super-tiles, then tiles)
-constexpr uint32_t kMaxSupers = 2048;      // super-tiles of the first level at most
+constexpr uint32_t kMaxSupers = 1024;      // super-tiles of the first level at most
 constexpr uint32_t kMaxSub = 64;           // tiles per super-tile at most
 constexpr uint32_t kLdsBytes = 160 * 1024; // LDS of one CDNA4 compute unit (also the per-workgroup limit)
 constexpr uint32_t kMaxTilePx = 2048;
@@ -145,7 +145,7 @@ struct Geom {
   uint32_t serial;       // 1: WT_DETERMINISTIC (stream-order binning by one thread, one thread per tile's records)
   uint32_t sthreads;     // scatter workgroup size
   uint32_t kper;         // fragments per scatter thread (4 or kPer)
-  uint32_t chunk;        // fragments per scatter workgroup = sthreads * kPer (also the class granularity)
+  uint32_t chunk;        // fragments per scatter workgroup = sthreads * kper (also the class granularity)
 };
 
 // Binned fragment records, two arrays of structures in the same order:
