@@ -777,11 +777,8 @@ struct Words {
   uint32_t w[N];
 };
 
-// Staged record in LDS: the head dwords followed by the record's global slot, padded to whole 16-byte units
-// (SH of them), then the tail dwords padded likewise (ST units).
-constexpr uint32_t staged_head_units(uint32_t C) { return (head_dwords(C) + 1 + 3) / 4; }
-constexpr uint32_t staged_tail_units(bool idx) { return (tail_dwords(idx) + 3) / 4; }
-// Bytes of one record staged by the chunk scatter: its head words plus the tile, and its tail words, unpadded.
+// Bytes of one record staged in LDS by the chunk scatter (its head words plus the tile, and its tail words) or by
+// the split (head words plus the record's slot, and tail words), unpadded.
 constexpr uint32_t staged_record_bytes(uint32_t C, bool idx) { return 4 * (head_dwords(C) + 1 + tail_dwords(idx)); }
 
 // N words to or from LDS with the widest accesses the address allows (d holds N-word records back to back, at a
@@ -1029,12 +1026,15 @@ __global__ void k_scatter_serial(wt_fragments f, Geom g, uint32_t* __restrict__ 
 }
 
 // Second level of two-level binning: one workgroup per super-tile moves its records (all classes, contiguous in
-// the first-level arrays) into the tiles' segments of the final arrays. Rounds of kSplitRecs records: rank by tile
-// in LDS, place in tile order in LDS, write with consecutive lanes on consecutive records. The workgroup owns
-// its tiles, so their write cursors live in LDS; runs are about kSplitRecs / (SW SH) records long.
+// the first-level arrays) into the tiles' segments of the final arrays. Rounds of split_per(C, IDX) records per
+// thread: rank by tile in LDS, place in tile order in LDS (head words plus the record's slot, then the tail words,
+// unpadded), write with consecutive lanes on consecutive records. The workgroup owns its tiles, so their write
+// cursors live in LDS; runs are about kSplitThreads * split_per / (SW SH) records long, so each round takes as many
+// records as the LDS holds (glass 3840x2160, 32 tiles per super-tile: two records per thread 3.35 ms, three 3.28).
 constexpr uint32_t kSplitThreads = 1024;
-constexpr uint32_t kSplitPer = 2;
-constexpr uint32_t kSplitRecs = kSplitThreads * kSplitPer;
+constexpr uint32_t split_per(uint32_t C, bool idx) {
+  return (kLdsBytes - 2048) / (kSplitThreads * staged_record_bytes(C, idx));
+}
 
 template <int C, bool IDX>
 __global__ __launch_bounds__(kSplitThreads) void k_split(Geom g, const uint32_t* __restrict__ offsets1,
@@ -1043,11 +1043,13 @@ __global__ __launch_bounds__(kSplitThreads) void k_split(Geom g, const uint32_t*
                                                          const uint32_t* __restrict__ tail1,
                                                          uint32_t* __restrict__ head, uint32_t* __restrict__ tail,
                                                          const WsHeader* hdr, unsigned long long level1) {
-  constexpr uint32_t DH = head_dwords(C), DT = tail_dwords(IDX);
+  constexpr uint32_t DH = head_dwords(C), DT = tail_dwords(IDX), HW = DH + 1;
+  constexpr uint32_t PER = split_per(C, IDX), RECS = kSplitThreads * PER;
   // only a complete first level is split (its records then hold valid super-tile-local pixels)
   if (hdr->binned != level1) return;
-  constexpr uint32_t SH = staged_head_units(C), ST = staged_tail_units(IDX), SU = SH + ST;
-  extern __shared__ uint4 srec[];                // [kSplitRecs][SU]
+  extern __shared__ uint4 sm4[];
+  uint32_t* sh = (uint32_t*)sm4;  // [RECS][HW]: head words, then the record's slot
+  uint32_t* st = sh + RECS * HW;  // [RECS][DT]: tail words
   __shared__ uint32_t cur[kMaxSub], cnt[kMaxSub], pre[kMaxSub];
   const uint32_t sidx = blockIdx.x;
   const uint32_t sx = sidx % g.sX, sy = sidx / g.sX;
@@ -1059,12 +1061,12 @@ __global__ __launch_bounds__(kSplitThreads) void k_split(Geom g, const uint32_t*
     const uint32_t tx = (sx << g.lSW) + (j & (g.SW - 1)), ty = (sy << g.lSH) + (j >> g.lSW);
     cur[j] = (tx < g.tilesX && ty < g.tilesY) ? offsets[(ty * g.tilesX + tx) * g.NX] : 0u;
   }
-  for (uint32_t c0 = beg; c0 < end; c0 += kSplitRecs) {
+  for (uint32_t c0 = beg; c0 < end; c0 += RECS) {
     if (threadIdx.x < nsub) cnt[threadIdx.x] = 0;
     __syncthreads();
-    uint32_t hw[kSplitPer][DH], tw[kSplitPer][DT], sub[kSplitPer], rank[kSplitPer];
+    uint32_t hw[PER][HW], tw[PER][DT], sub[PER], rank[PER];
 #pragma unroll
-    for (uint32_t k = 0; k < kSplitPer; ++k) {
+    for (uint32_t k = 0; k < PER; ++k) {
       const uint32_t i = c0 + k * kSplitThreads + threadIdx.x;
       sub[k] = 0xffffffffu;
       if (i < end) {
@@ -1089,41 +1091,26 @@ __global__ __launch_bounds__(kSplitThreads) void k_split(Geom g, const uint32_t*
     }
     __syncthreads();
 #pragma unroll
-    for (uint32_t k = 0; k < kSplitPer; ++k) {
+    for (uint32_t k = 0; k < PER; ++k) {
       if (sub[k] == 0xffffffffu) continue;
-      uint32_t h4[4 * SH], t4[4 * ST];
-#pragma unroll
-      for (uint32_t w = 0; w < 4 * SH; ++w) h4[w] = w < DH ? hw[k][w] : cur[sub[k]] + rank[k];
-#pragma unroll
-      for (uint32_t w = 0; w < 4 * ST; ++w) t4[w] = w < DT ? tw[k][w] : 0u;
-      uint4* d = srec + (size_t)(pre[sub[k]] + rank[k]) * SU;
-#pragma unroll
-      for (uint32_t u = 0; u < SH; ++u) d[u] = make_uint4(h4[4 * u], h4[4 * u + 1], h4[4 * u + 2], h4[4 * u + 3]);
-#pragma unroll
-      for (uint32_t u = 0; u < ST; ++u) d[SH + u] = make_uint4(t4[4 * u], t4[4 * u + 1], t4[4 * u + 2], t4[4 * u + 3]);
+      hw[k][DH] = cur[sub[k]] + rank[k];
+      const uint32_t pos = pre[sub[k]] + rank[k];
+      lds_put<HW>(sh + (size_t)pos * HW, hw[k]);
+      lds_put<DT>(st + (size_t)pos * DT, tw[k]);
     }
     __syncthreads();
-    const uint32_t ns = std::min(kSplitRecs, end - c0);
+    const uint32_t ns = std::min(RECS, end - c0);
     for (uint32_t q = threadIdx.x; q < ns; q += kSplitThreads) {
-      const uint4* r = srec + (size_t)q * SU;
-      uint32_t h4[4 * SH], t4[4 * ST];
-#pragma unroll
-      for (uint32_t u = 0; u < SH; ++u) {
-        const uint4 v = r[u];
-        h4[4 * u] = v.x; h4[4 * u + 1] = v.y; h4[4 * u + 2] = v.z; h4[4 * u + 3] = v.w;
-      }
-#pragma unroll
-      for (uint32_t u = 0; u < ST; ++u) {
-        const uint4 v = r[SH + u];
-        t4[4 * u] = v.x; t4[4 * u + 1] = v.y; t4[4 * u + 2] = v.z; t4[4 * u + 3] = v.w;
-      }
-      const uint64_t slot = h4[DH];
+      uint32_t h[HW], t[DT];
+      lds_get<HW>(sh + (size_t)q * HW, h);
+      lds_get<DT>(st + (size_t)q * DT, t);
+      const uint64_t slot = h[DH];
       Words<DH> hh;
 #pragma unroll
-      for (uint32_t w = 0; w < DH; ++w) hh.w[w] = h4[w];
+      for (uint32_t w = 0; w < DH; ++w) hh.w[w] = h[w];
       Words<DT> tt;
 #pragma unroll
-      for (uint32_t w = 0; w < DT; ++w) tt.w[w] = t4[w];
+      for (uint32_t w = 0; w < DT; ++w) tt.w[w] = t[w];
       *(Words<DH>*)(head + slot * DH) = hh;
       *(Words<DT>*)(tail + slot * DT) = tt;
     }
@@ -1292,8 +1279,8 @@ hipError_t launch_bin_scatter(const Geom& g, const wt_fragments& f, void* ws, co
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_seal, dim3(1), dim3(1024), 0, s, hdr, cursors1, offsets1, gs.NX, g.nsuper, cstamp, stamp1);
-  auto split = [&](auto kern, uint32_t su) -> hipError_t {
-    const size_t lds = (size_t)kSplitRecs * su * 16;
+  auto split = [&](auto kern, uint32_t rb, uint32_t per) -> hipError_t {
+    const size_t lds = (size_t)kSplitThreads * per * rb;
     if (lds > 65536) {
       hipError_t e2 = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e2 != hipSuccess) return e2;
@@ -1303,11 +1290,11 @@ hipError_t launch_bin_scatter(const Geom& g, const wt_fragments& f, void* ws, co
     return hipGetLastError();
   };
   if (g.C == 1)
-    e = record_index ? split(k_split<1, true>, staged_head_units(1) + staged_tail_units(true))
-                     : split(k_split<1, false>, staged_head_units(1) + staged_tail_units(false));
+    e = record_index ? split(k_split<1, true>, staged_record_bytes(1, true), split_per(1, true))
+                     : split(k_split<1, false>, staged_record_bytes(1, false), split_per(1, false));
   else
-    e = record_index ? split(k_split<3, true>, staged_head_units(3) + staged_tail_units(true))
-                     : split(k_split<3, false>, staged_head_units(3) + staged_tail_units(false));
+    e = record_index ? split(k_split<3, true>, staged_record_bytes(3, true), split_per(3, true))
+                     : split(k_split<3, false>, staged_record_bytes(3, false), split_per(3, false));
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_seal_split, dim3(1), dim3(1), 0, s, hdr, stamp1, stamp);
   return hipGetLastError();
