@@ -52,8 +52,9 @@ struct is_e5<e5_t> {
 // Shared-exponent encoding: clamp to [0, 511/512 * 2^16] (NaN and negatives to 0); exponent from the largest,
 // e = max(-16, floor(log2 max)) + 16, bumped by one if the largest rounds to 512 at e; each mantissa is
 // floor(v * 2^(24 - e) + 1/2). The scaled values are exact in FP32 (power-of-two scaling) and the rounding is
-// taken in FP64, where adding 1/2 is exact.
-__device__ __forceinline__ uint32_t e5_pack(float r, float g, float b) {
+// taken in FP64, where adding 1/2 is exact. (The same rounding done exactly in FP32, as trunc(x) plus
+// x - trunc(x) >= 1/2, made the glass frame's tile kernel slower: 3.25 -> 3.30 ms.)
+__host__ __device__ __forceinline__ uint32_t e5_pack(float r, float g, float b) {
   float v[3] = {r, g, b};
   float mx = 0.f;
 #pragma unroll
@@ -62,7 +63,11 @@ __device__ __forceinline__ uint32_t e5_pack(float r, float g, float b) {
     mx = fmaxf(mx, v[q]);
   }
   int lead = -16;
-  if (mx >= 0x1p-16f) lead = (int)((__float_as_uint(mx) >> 23) & 255u) - 127;
+  if (mx >= 0x1p-16f) {
+    uint32_t u;
+    __builtin_memcpy(&u, &mx, 4);
+    lead = (int)((u >> 23) & 255u) - 127;
+  }
   int es = lead + 16;
   if (floor((double)ldexpf(mx, 24 - es) + 0.5) == 512.0) ++es;
   uint32_t w = (uint32_t)es << 27;

@@ -108,6 +108,58 @@ def test_round_f64_to_f16_bf16(tmp_path):
     assert ((got[nan, 1] & 0x7f80) == 0x7f80).all() and ((got[nan, 1] & 0x7f) != 0).all()
 
 
+def _e5_inputs():
+    """FP32 triples that exercise the shared-exponent packing: random magnitudes over the format's range and beyond,
+    triples whose largest value rounds up to the next exponent, values exactly halfway between two mantissas (and
+    one FP32 step either side), the smallest exponent's range and FP32 subnormals, the clamp at 65408, zeros,
+    negatives, infinities and NaN."""
+    import numpy as np
+    rng = np.random.default_rng(11)
+    n = 6000
+    mag = np.exp2(rng.uniform(-30, 18, (n, 3))) * rng.uniform(0.5, 1.0, (n, 3))
+    spread = np.exp2(rng.uniform(-30, 18, (n, 1))) * np.exp2(-rng.uniform(0, 12, (n, 3)))
+    t = [mag, spread]
+    e = rng.integers(-16, 16, 2000)
+    m = rng.integers(0, 512, (2000, 3)).astype(np.float64)
+    half = (m + 0.5) * np.exp2(e[:, None] - 8.0)
+    t += [half, np.nextafter(half.astype(np.float32), np.float32(np.inf)).astype(np.float64),
+          np.nextafter(half.astype(np.float32), np.float32(0)).astype(np.float64)]
+    top = (511.5 + rng.uniform(-0.01, 0.01, (2000, 1))) * np.exp2(e[:, None] - 8.0) * np.array([1.0, 0.3, 0.01])
+    t.append(top)
+    t.append(rng.uniform(0, 2.0 ** -16, (1000, 3)))
+    t.append(rng.uniform(0, 1, (500, 3)) * 2.0 ** -130)
+    sign = np.where(rng.random((3000, 3)) < 0.3, -1.0, 1.0)
+    t.append(sign * np.exp2(rng.uniform(-20, 17, (3000, 3))))
+    t.append(np.array([[0.0, 0.0, 0.0], [-0.0, 1.0, 2.0], [65408.0, 1.0, 0.5], [65409.0, 65535.0, 1e30],
+                       [np.inf, 1.0, 2.0], [-np.inf, 3.0, np.nan], [np.nan, np.nan, np.nan], [2.0 ** -16, 0, 0],
+                       [2.0 ** -16 * 511.5 / 512, 0, 0], [511.5 * 2.0 ** -24, 1e-45, 0], [1.0, 1.0, 1.0]]))
+    return np.concatenate(t).astype(np.float32)
+
+
+@pytest.mark.skipif(not os.path.exists(HIPCC) and shutil.which("hipcc") is None, reason="hipcc not available")
+def test_e5_pack_matches_the_oracle(tmp_path):
+    """The kernels' E5B9G9R9 packing (FP32 scaling, FP64 round-half-up, exponent from the FP32 bit pattern) gives,
+    word for word, the oracle's packing (FP64 scaling, exponent by frexp), over the format's whole range and its
+    rounding and clamping edges."""
+    import numpy as np
+    import oracle
+    exe = tmp_path / "e5_check"
+    subprocess.check_call([HIPCC, "-O2", "-std=c++17", "-I", os.path.join(ROOT, "include"),
+                           "-I", os.path.join(ROOT, "paper_2201_00094_amd", "csrc"),
+                           os.path.join(ROOT, "tests", "host", "e5_check.cpp"), "-o", str(exe)],
+                          stderr=subprocess.DEVNULL)
+    x = _e5_inputs()
+    bits = x.view(np.uint32)
+    inp = "\n".join("%08x %08x %08x" % tuple(r) for r in bits) + "\n"
+    res = subprocess.run([str(exe)], input=inp, capture_output=True, text=True, timeout=300)
+    assert res.returncode == 0
+    got = [int(w, 16) for w in res.stdout.split()]
+    assert len(got) == len(x)
+    want = [oracle.pack_e5b9g9r9(*(float(v) for v in r)) for r in x]
+    bad = [(tuple(x[i]), hex(got[i]), hex(want[i])) for i in range(len(x)) if got[i] != want[i]]
+    assert not bad, bad[:5]
+
+
 @pytest.mark.skipif(not os.path.exists(HIPCC) and shutil.which("hipcc") is None, reason="hipcc not available")
 def test_workspace_stamps_tell_layouts_and_streams_apart(tmp_path):
     """The stamps the binning leaves in the workspace header: every description a caller could confuse with the
