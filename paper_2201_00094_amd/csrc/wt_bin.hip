@@ -124,17 +124,20 @@ Geom make_geom(const wt_frame_desc& d, bool backward) {
   g.nsuper = g.sX * g.sY;
   g.NX = g.lds_bins ? kClasses : 1;
   // Scatter: two workgroups per compute unit where the tile tables (of the binning level that scatters) and a
-  // 1024-record round fit half the LDS, so that one workgroup's loads overlap the other's ranking, staging and
-  // writes: one channel, 1024 threads with 4 fragments each (64 registers, eight waves per SIMD); three channels,
-  // 512 threads with 8 fragments each (the three-channel fragment needs about 110 registers: four waves per SIMD).
-  // Otherwise one workgroup of 1024 threads with 8 fragments each per compute unit. Chunks are powers of two.
-  // (Glass 3840x2160: the three-channel form took the scatter phases from 7.86 to 7.22 ms.)
+  // 1024-record round fit half the LDS and a 4096-fragment chunk still holds two records per bin on average, so
+  // that one workgroup's loads overlap the other's ranking, staging and writes: one channel, 1024 threads with 4
+  // fragments each (64 registers, eight waves per SIMD); three channels, 512 threads with 8 fragments each (the
+  // three-channel fragment needs about 110 registers: four waves per SIMD). Otherwise one workgroup of 1024 threads
+  // with 8 fragments each per compute unit. Chunks are powers of two.
+  // (Glass 3840x2160: the three-channel form took the scatter phases from 7.86 to 7.22 ms. Smoke frame at rank 4,
+  // 4,080 tiles: one workgroup per compute unit, two records per bin and chunk, 2.10 -> 2.07 ms.)
   // (a one-channel record stages in at most 32 bytes, index or not, a three-channel one in at most 40: 1024 of
   // them take 32 or 40 KB)
   g.sthreads = 1024;
   g.kper = kPer;
   const uint32_t bins = g.two ? g.nsuper : g.rb;
-  const bool two_wg = g.lds_bins && 8ull * bins + 1024ull * (g.C == 1 ? 32 : 40) <= kLdsBytes / 2 - 1024;
+  const bool two_wg = g.lds_bins && bins <= 2048 &&
+                      8ull * bins + 1024ull * (g.C == 1 ? 32 : 40) <= kLdsBytes / 2 - 1024;
   if (two_wg && g.C == 1) g.kper = 4;
   if (two_wg && g.C == 3) g.sthreads = 512;
   g.chunk = g.sthreads * g.kper;
