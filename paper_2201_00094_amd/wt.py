@@ -132,10 +132,19 @@ class Workspace:
 # The tile kernels read a binned workspace under the tile geometry of the description they are given, so a call
 # over an already binned stream must use the description it was binned with. The binding records that description
 # on the workspace object (``binned_spec``: set by a binning, cleared when the workspace is reused otherwise) and
-# refuses a mismatch before anything reaches the library.
-def _binned_as(ws, spec, counted=None):
+# refuses a mismatch before anything reaches the library. A scatter must follow the count of the same stream: the
+# count records the stream's size and array addresses (``counted_stream``) beside its description. (The library
+# checks the same on the device, from stamps the count leaves in the workspace; this refuses it earlier, with a
+# clearer message.)
+def _binned_as(ws, spec, counted=None, stream=None):
     ws.binned_spec = spec
     ws.counted_spec = counted
+    ws.counted_stream = stream
+
+
+def _stream_id(frags: "Fragments"):
+    return (frags.count, frags.pixel.data_ptr(), frags.depth.data_ptr(), frags.alpha.data_ptr(),
+            frags.rgb.data_ptr())
 
 
 def _require_binned(ws, spec, name, attr="binned_spec"):
@@ -160,13 +169,15 @@ def bin_count(spec: FrameSpec, frags: Fragments, ws: Workspace, stream=None):
     _binned_as(ws, None)
     _lib.check(_lib.load().wt_bin_count(C.byref(spec.c_desc()), C.byref(frags.c_struct(spec.channels)), ws.ptr,
                                         ws.nbytes, _stream(stream)), "wt_bin_count")
-    _binned_as(ws, None, counted=spec)
+    _binned_as(ws, None, counted=spec, stream=_stream_id(frags))
 
 
 def bin_scatter(spec: FrameSpec, frags: Fragments, ws: Workspace, stream=None):
     """Second half of :func:`bin`: copy the stream into its tile segments (after :func:`bin_count` with the same
     arguments)."""
     _require_binned(ws, spec, "bin_scatter", attr="counted_spec")
+    if getattr(ws, "counted_stream", None) != _stream_id(frags):
+        raise ValueError("bin_scatter: the workspace was counted for another fragment stream (size or arrays differ)")
     _lib.check(_lib.load().wt_bin_scatter(C.byref(spec.c_desc()), C.byref(frags.c_struct(spec.channels)), ws.ptr,
                                           ws.nbytes, _stream(stream)), "wt_bin_scatter")
     _binned_as(ws, spec)

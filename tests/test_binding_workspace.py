@@ -76,6 +76,25 @@ def test_scatter_needs_a_count_with_the_same_description(fake):
     assert fake.calls == ["wt_bin_count"]
 
 
+def test_scatter_needs_a_count_of_the_same_stream(fake):
+    """A count records the stream it counted (size and array addresses); a scatter of another stream under the same
+    description is refused before the library is called, and the counted stream still scatters afterwards."""
+    ws, fr, other, longer = FakeWs(), _frags(), _frags(), _frags(5)
+    wt.bin_count(A, fr, ws)
+    with pytest.raises(ValueError, match="another fragment stream"):
+        wt.bin_scatter(A, other, ws)
+    with pytest.raises(ValueError, match="another fragment stream"):
+        wt.bin_scatter(A, longer, ws)
+    wt.bin_scatter(A, fr, ws)
+    wt.render_binned(A, ws, (0, 0, 0), OUT)
+    assert fake.calls == ["wt_bin_count", "wt_bin_scatter", "wt_render_binned"]
+    # the same arrays under a new count: the identity follows the latest count
+    wt.bin_count(A, other, ws)
+    with pytest.raises(ValueError, match="another fragment stream"):
+        wt.bin_scatter(A, fr, ws)
+    wt.bin_scatter(A, other, ws)
+
+
 def test_temporal_binning_serves_only_the_temporal_description(fake):
     ws, fr = FakeWs(), _frags()
     wt.bin(T, fr, ws)
