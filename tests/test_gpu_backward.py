@@ -52,6 +52,29 @@ def test_backward_matches_oracle_gradient(orc, channels, rank, tight):
     np.testing.assert_allclose(gr, orgb, rtol=1e-5, atol=1e-7 * sr)
 
 
+@pytest.mark.parametrize("channels", [1, 3])
+def test_backward_two_level_binning(orc, channels):
+    """Frames whose gradient binning has more than 4096 tiles, so that the records that keep the stream index go
+    through the two-level binning (super-tiles, then the split): 2100 x 1100 at one channel (512-pixel gradient
+    tiles, 66 x 69 of them) and 1100 x 1000 at three (256-pixel tiles, 69 x 63). Every gradient element against the
+    oracle's, as for the small frames."""
+    if channels == 1:
+        f = synth.frame_c5(seed=11, width=2100, height=1100, rank=3, mean=6.0)
+    else:
+        f = synth.frame_c3(seed=11, width=1100, height=1000, rank=3, particles=8.0)
+    say("case backward two-level channels", channels, "F", f.count)
+    target = synth.target_image(11, f.width, f.height)
+    out, ga, gr = _gpu_grads(f, 3, target)
+    o = orc.resolve(f.width, f.height, 3, f.pixel, f.depth, f.alpha, f.rgb, bg=f.bg, channels=channels,
+                    want=("out",))
+    np.testing.assert_allclose(out, o["out"], atol=1e-4, rtol=0)
+    oa, orgb = orc.backward(f.width, f.height, 3, f.pixel, f.depth, f.alpha, f.rgb, 2.0 * (out - target), bg=f.bg,
+                            channels=channels)
+    sa, sr = np.abs(oa).max(), np.abs(orgb).max()
+    np.testing.assert_allclose(ga, oa, rtol=1e-4, atol=2e-6 * sa)
+    np.testing.assert_allclose(gr, orgb, rtol=1e-5, atol=1e-7 * sr)
+
+
 def test_backward_finite_differences_512(orc):
     """512 x 512, Poisson(32) fragments/px, loss = squared error against a seeded target: gradients of 64 sampled
     fragments against FP64 central differences of the oracle (step 1e-6, the fragment's pixel re-resolved)."""
