@@ -1033,7 +1033,8 @@ __global__ void k_scatter_serial(wt_fragments f, Geom g, uint32_t* __restrict__ 
 // thread: rank by tile in LDS, place in tile order in LDS (head words plus the record's slot, then the tail words,
 // unpadded), write with consecutive lanes on consecutive records. The workgroup owns its tiles, so their write
 // cursors live in LDS; runs are about kSplitThreads * split_per / (SW SH) records long, so each round takes as many
-// records as the LDS holds (glass 3840x2160, 32 tiles per super-tile: two records per thread 3.35 ms, three 3.28).
+// records as the LDS holds (glass 3840x2160, 32 tiles per super-tile: two records per thread 3.35 ms, three 3.28,
+// four 3.18).
 constexpr uint32_t kSplitThreads = 1024;
 constexpr uint32_t split_per(uint32_t C, bool idx) {
   return (kLdsBytes - 2048) / (kSplitThreads * staged_record_bytes(C, idx));
