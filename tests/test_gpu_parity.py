@@ -326,15 +326,15 @@ def test_many_tiles(orc, width, height):
 def test_glass_4k_full(orc):
     """The glass + particles workload at full size (3840x2160, rank 3, 2-4 glass layers with per-channel alpha plus
     Poisson(24) particles per pixel, about 224 M fragments) in the benchmark's launch configuration (bin count,
-    bin scatter, render over the binned stream; two-level binning), FP32 and FP16 storage: every coefficient and
-    every composite pixel against the oracle (FP16 against the oracle at the same storage precision)."""
+    bin scatter, render over the binned stream; two-level binning), FP32, FP16 and BF16 storage: every coefficient
+    and every composite pixel against the oracle (FP16 and BF16 against the oracle at the same storage precision)."""
     import torch
     import paper_2201_00094_amd as wt
     f = synth.frame_c3(seed=0, rank=3)
     say("case glass 4K F", f.count)
     fr = wt.Fragments.from_numpy(f.pixel, f.depth, f.alpha, f.rgb)
     sel = None
-    for dtype, rel in (("f32", 1e-5), ("f16", 2 * 2.0 ** -11 + 1e-5)):
+    for dtype, rel in (("f32", 1e-5), ("f16", 2 * 2.0 ** -11 + 1e-5), ("bf16", 2 * 2.0 ** -8 + 1e-5)):
         say("  storage", dtype)
         spec = wt.FrameSpec(f.width, f.height, 3, 3, dtype)
         ws = wt.Workspace(spec, f.count)
