@@ -211,6 +211,9 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=96.0,
                     help="serve mode: HBM admission budget (default: room for five 3840x2160 requests)")
     ap.add_argument("--slots", type=int, default=3, help="serve mode: concurrent requests (HIP streams)")
+    ap.add_argument("--policy", choices=("fifo", "sjf"), default="sjf",
+                    help="serve mode: admission order (fewest fragments first with a bounded bypass, the default; or "
+                         "first come first)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -649,7 +652,13 @@ def run_serve(args):
         rate = load / mean_service
         trace = synth.poisson_arrivals(args.seed + k, args.requests, rate)
         ex = GpuExecutor(slots=args.slots, device=dev)
-        srv = Server(ex, slots=args.slots, budget_bytes=int(args.budget_gb * (1 << 30)))
+        # the slots' resident buffers sized for the largest request, and every request's composite buffer, before
+        # the trace starts: no allocation while it runs
+        big_w, big_h = max(synth.REQUEST_RESOLUTIONS, key=lambda wh: wh[0] * wh[1])
+        ex.reserve(big_w, big_h, 4, max(q.count for kk, q in pool.items() if kk[:2] == (big_w, big_h)))
+        outs = [torch.empty((r["width"] * r["height"], 3), dtype=torch.float32, device=dev) for r in trace]
+        torch.cuda.synchronize()
+        srv = Server(ex, slots=args.slots, budget_bytes=int(args.budget_gb * (1 << 30)), policy=args.policy)
         futs = []
         t0 = time.perf_counter()
         for i, r in enumerate(trace):
@@ -658,7 +667,7 @@ def run_serve(args):
                 time.sleep(r["t"] - now)
             fr = pool[(r["width"], r["height"], r["seed"] % 2)]
             futs.append(srv.submit(FrameRequest(r["width"], r["height"], r["rank"], fr, dtype=r["dtype"],
-                                                bg=(0.2, 0.2, 0.2), tag=i)))
+                                                bg=(0.2, 0.2, 0.2), tag=i, out=outs[i])))
         results = [fu.result(timeout=600) for fu in futs]
         srv.close()
         stats = srv.stats.summary()
@@ -674,7 +683,7 @@ def run_serve(args):
                 alone_ws[key] = wt.Workspace(spec, most, device=dev)
             alone = wt.render(spec, fr, (0.2, 0.2, 0.2), alone_ws[key])
             worst = max(worst, float((alone - results[i].out).abs().max()))
-        del alone_ws, results, ex
+        del alone_ws, results, ex, outs
         torch.cuda.empty_cache()
         sweep.append({"load": load, "rate_hz": rate, "requests": len(trace), "fragments_per_s": stats["fragments_per_s"],
                       "p50_ms": stats["p50_ms"], "p99_ms": stats["p99_ms"], "mean_ms": stats["mean_ms"],
@@ -689,7 +698,7 @@ def run_serve(args):
     line = {"metric": "served frames: p50/p99 latency (arrival to completion) and fragments/s", "mode": "serve",
             "value": head["fragments_per_s"], "unit": "fragments/s", "n_gpus": 1, "load": head["load"],
             "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"], "mean_solo_ms": mean_service * 1e3,
-            "slots": args.slots, "budget_gb": args.budget_gb, "sweep": sweep,
+            "slots": args.slots, "budget_gb": args.budget_gb, "policy": args.policy, "sweep": sweep,
             "solo_vs_mix_max_abs": max(x["solo_vs_mix_max_abs"] for x in sweep),
             "data": "synthetic", "dtype": "f32/f16 storage mix",
             "config": {"workload": "Poisson arrivals; 640x360..3840x2160, rank 3/4, f32/f16 storage, "

@@ -39,6 +39,7 @@ class FrameRequest:
     want_coeffs: bool = False
     tag: object = None
     timeout: float = None         # admission deadline in seconds from submit (None: wait as long as it takes)
+    out: object = None            # optional [P, 3] float32 device tensor the composite is written to (else allocated)
 
     @property
     def pixels(self) -> int:
@@ -119,15 +120,20 @@ class ServerStats:
 
 
 class Server:
-    """Admission by HBM footprint and free slots; FIFO with bounded back-filling (a request that does not fit
-    may be passed by later, smaller ones at most ``max_bypass`` times, after which admission waits for it).
+    """Admission by HBM footprint and free slots. ``policy="fifo"``: first come, first admitted, with bounded
+    back-filling (a request that does not fit may be passed by later, smaller ones at most ``max_bypass`` times,
+    after which admission waits for it). ``policy="sjf"``: the queued request with the fewest fragments that fits
+    goes first, and a request passed over ``max_bypass`` times goes before any other (so none waits forever).
 
     The budget holds the footprints of the requests in flight plus the executor's resident per-slot buffers
     (``resident_bytes``), including what a slot's buffers must grow by to take the request (``growth``). When a
     request does not fit, the buffers of idle slots are released (``trim``) before it is left waiting."""
 
     def __init__(self, executor, slots: int = 3, budget_bytes: int = 96 << 30, max_bypass: int = 8,
-                 poll_interval: float = 0.0002, clock=time.perf_counter):
+                 poll_interval: float = 0.0002, clock=time.perf_counter, policy: str = "fifo"):
+        if policy not in ("fifo", "sjf"):
+            raise ValueError("policy must be 'fifo' or 'sjf'")
+        self.policy = policy
         self.ex = executor
         self.slots = int(slots)
         self.budget = int(budget_bytes)
@@ -232,39 +238,62 @@ class Server:
                 keep.append(p)
         self._queue = keep
 
+    def _start_locked(self, i, slot):
+        """Launch queue[i] on slot (or drop it if its client cancelled it meanwhile); on success every request
+        ahead of it in the queue has been passed over once more."""
+        p = self._queue[i]
+        del self._queue[i]
+        if not p.fut.set_running_or_notify_cancel():  # cancelled by the client meanwhile
+            self.stats.cancelled += 1
+            return
+        self._free_slots.remove(slot)
+        self._bytes += p.footprint
+        t = self.clock()
+        try:
+            handle = self.ex.launch(p.req, slot, p.token) if self._prep else self.ex.launch(p.req, slot)
+        except Exception as e:  # launch failure: report to the client, release resources
+            self._bytes -= p.footprint
+            self._free_slots.append(slot)
+            self.stats.failed += 1
+            p.fut.set_exception(e)
+            return
+        self._running.append(_Running(p, slot, handle, t))
+        self.stats.max_inflight = max(self.stats.max_inflight, len(self._running))
+        self.stats.max_bytes_inflight = max(self.stats.max_bytes_inflight, self._held())
+        for q in list(self._queue)[:i]:
+            q.bypassed += 1
+
     def _admit_locked(self):
         self._drop_expired_locked()
+        if self.policy == "sjf":
+            self._admit_sjf_locked()
+            return
         i = 0
         while i < len(self._queue) and self._free_slots:
             p = self._queue[i]
             slot = self._fit_slot(p)
             if slot is not None:
-                del self._queue[i]
-                if not p.fut.set_running_or_notify_cancel():  # cancelled by the client meanwhile
-                    self.stats.cancelled += 1
-                    continue
-                self._free_slots.remove(slot)
-                self._bytes += p.footprint
-                t = self.clock()
-                try:
-                    handle = self.ex.launch(p.req, slot, p.token) if self._prep else self.ex.launch(p.req, slot)
-                except Exception as e:  # launch failure: report to the client, release resources
-                    self._bytes -= p.footprint
-                    self._free_slots.append(slot)
-                    self.stats.failed += 1
-                    p.fut.set_exception(e)
-                    continue
-                self._running.append(_Running(p, slot, handle, t))
-                self.stats.max_inflight = max(self.stats.max_inflight, len(self._running))
-                self.stats.max_bytes_inflight = max(self.stats.max_bytes_inflight, self._held())
-                # requests ahead of this one were passed over once more
-                for q in list(self._queue)[:i]:
-                    q.bypassed += 1
+                self._start_locked(i, slot)
                 i = 0
                 continue
             if p.bypassed >= self.max_bypass:
                 break  # the oldest blocked request has waited long enough: no more back-filling
             i += 1
+
+    def _admit_sjf_locked(self):
+        while self._queue and self._free_slots:
+            q = self._queue
+            if q[0].bypassed >= self.max_bypass:
+                order = [0]  # passed over often enough: the oldest goes next, or nothing does
+            else:
+                order = sorted(range(len(q)), key=lambda j: (q[j].req.count, j))
+            for i in order:
+                slot = self._fit_slot(q[i])
+                if slot is not None:
+                    self._start_locked(i, slot)
+                    break
+            else:
+                return
 
     def _complete_locked(self):
         still = []
@@ -342,6 +371,8 @@ class GpuExecutor:
         import torch
         self.torch = torch
         self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device(self.device.type, torch.cuda.current_device())
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]
         self.ws = [None] * slots
         self.cf = [None] * slots
@@ -367,6 +398,22 @@ class GpuExecutor:
     def resident_bytes(self) -> int:
         return sum(b.numel() for b in self.ws + self.cf if b is not None)
 
+    def reserve(self, width: int, height: int, rank: int, count: int, channels: int = 1, dtype: str = "f32"):
+        """Grow every slot's resident buffers to hold a request of this description and fragment count now, so that
+        requests up to that size allocate nothing when they are launched (the buffers count against the server's
+        budget as resident bytes)."""
+        from . import wt as _wt
+        need_ws, need_cf = _slot_bytes(_wt.FrameSpec(width, height, rank, channels, dtype), count)
+        torch = self.torch
+        for k, s in enumerate(self.streams):
+            with torch.cuda.stream(s):
+                if self.ws[k] is None or self.ws[k].numel() < need_ws:
+                    self.ws[k] = None
+                    self.ws[k] = torch.empty(need_ws, dtype=torch.uint8, device=self.device)
+                if self.cf[k] is None or self.cf[k].numel() < need_cf:
+                    self.cf[k] = None
+                    self.cf[k] = torch.empty(need_cf, dtype=torch.uint8, device=self.device)
+
     def trim(self, slot: int):
         """Release an idle slot's buffers (its stream's earlier work is ordered before any reuse of the memory)."""
         self.ws[slot] = None
@@ -377,7 +424,13 @@ class GpuExecutor:
         spec = self._spec(req)
         from . import wt as _wt
         client = torch.cuda.current_stream(self.device)
-        out = torch.empty((spec.pixels, 3), dtype=torch.float32, device=self.device)
+        out = req.out
+        if out is None:
+            out = torch.empty((spec.pixels, 3), dtype=torch.float32, device=self.device)
+        elif (not isinstance(out, torch.Tensor) or out.dtype != torch.float32 or out.device != self.device or
+              tuple(out.shape) != (spec.pixels, 3) or not out.is_contiguous()):
+            raise ValueError("FrameRequest.out must be a contiguous [%d, 3] float32 tensor on %s" %
+                             (spec.pixels, self.device))
         kept = torch.empty(spec.coeff_shape(), dtype=_wt.TORCH_DTYPES[spec.dtype], device=self.device) \
             if req.want_coeffs else None
         ready = torch.cuda.Event()

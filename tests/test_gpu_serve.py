@@ -93,3 +93,48 @@ def test_fragments_produced_on_a_side_stream(orc):
     for r in results:
         d = float((r.out - solo).abs().max())
         assert d <= 1e-5, (r.tag, d)
+
+
+def test_reserved_slots_and_client_result_buffers():
+    """Slots reserved for the largest request allocate nothing when requests up to that size run (no growth), and a
+    request that brings its own composite buffer gets its result written there, equal to the frame rendered alone;
+    under the shortest-first policy as well. A wrongly shaped buffer is refused at submit."""
+    import torch
+    import paper_2201_00094_amd as wt
+    from paper_2201_00094_amd.serve import FrameRequest, GpuExecutor, Server
+
+    frames = []
+    for i, (w, h, rank) in enumerate([(300, 200, 4), (160, 90, 3), (64, 64, 3)]):
+        f = synth.frame_c4(seed=40 + i, width=w, height=h, rank=rank, mean=16.0)
+        fr = wt.Fragments.from_numpy(f.pixel, f.depth, f.alpha, f.rgb)
+        spec = wt.FrameSpec(w, h, rank)
+        frames.append((f, fr, spec, wt.render(spec, fr, f.bg, wt.Workspace(spec, f.count))))
+    say("case serving with reserved slots and client buffers")
+    ex = GpuExecutor(slots=2)
+    big = frames[0]
+    ex.reserve(big[0].width, big[0].height, 4, big[0].count)
+    held = ex.resident_bytes()
+    for f, fr, spec, _ in frames:
+        req = FrameRequest(f.width, f.height, spec.rank, fr, bg=f.bg)
+        assert ex.growth(0, req) == 0 and ex.growth(1, req) == 0
+    srv = Server(ex, slots=2, budget_bytes=4 << 30, policy="sjf")
+    outs, futs = [], []
+    for rep in range(3):
+        for f, fr, spec, _ in frames:
+            o = torch.full((spec.pixels, 3), float("nan"), device="cuda")
+            outs.append(o)
+            futs.append(srv.submit(FrameRequest(f.width, f.height, spec.rank, fr, bg=f.bg, out=o)))
+    res = [fu.result(timeout=60) for fu in futs]
+    srv.close()
+    torch.cuda.synchronize()
+    assert ex.resident_bytes() == held
+    for k, r in enumerate(res):
+        f, fr, spec, solo = frames[k % len(frames)]
+        assert r.out.data_ptr() == outs[k].data_ptr()
+        assert float((r.out - solo).abs().max()) <= 1e-5
+    srv2 = Server(GpuExecutor(slots=1), slots=1)
+    f, fr, spec, _ = frames[1]
+    bad = torch.empty((spec.pixels + 1, 3), device="cuda")
+    with pytest.raises(ValueError, match="FrameRequest.out"):
+        srv2.submit(FrameRequest(f.width, f.height, spec.rank, fr, bg=f.bg, out=bad))
+    srv2.close()

@@ -299,3 +299,85 @@ def test_idle_slot_buffers_are_released_when_a_request_needs_the_room(orc):
     r = srv.submit(_req(1, 8, 8, tag="x")).result(timeout=30)
     srv.close()
     assert r.slot == 0 and ex.trimmed == [1] and ex.peak <= 1000
+
+
+class GatedExecutor:
+    """Fake device whose requests finish only when the test releases them; records the order of launches."""
+
+    def __init__(self):
+        self.launched = []
+        self.gates = {}
+
+    def footprint(self, req):
+        return 1
+
+    def launch(self, req, slot):
+        ev = threading.Event()
+        self.gates[req.tag] = ev
+        self.launched.append(req.tag)
+        return ev
+
+    def done(self, h):
+        return h.is_set()
+
+    def finish(self, h):
+        return FrameResult(out=None)
+
+
+def _sized(tag, count):
+    """A request whose only property that matters here is its fragment count."""
+    class _F:
+        pass
+    f = _F()
+    f.count = count
+    return FrameRequest(8, 8, 3, f, tag=tag)
+
+
+def _wait_launched(ex, n, timeout=10.0):
+    t0 = time.perf_counter()
+    while len(ex.launched) < n:
+        assert time.perf_counter() - t0 < timeout, "launches: %r" % ex.launched
+        time.sleep(0.001)
+
+
+def test_shortest_first_admits_the_smallest_queued_request():
+    ex = GatedExecutor()
+    srv = Server(ex, slots=1, budget_bytes=10 ** 6, policy="sjf")
+    futs = [srv.submit(_sized("first", 100))]
+    _wait_launched(ex, 1)
+    for tag, n in (("big", 900), ("mid", 500), ("small", 10), ("mid2", 500)):
+        futs.append(srv.submit(_sized(tag, n)))
+    time.sleep(0.01)
+    for k, expect in enumerate(("small", "mid", "mid2", "big"), start=1):
+        ex.gates[ex.launched[k - 1]].set()
+        _wait_launched(ex, k + 1)
+        assert ex.launched[k] == expect, ex.launched
+    ex.gates[ex.launched[-1]].set()
+    for f in futs:
+        f.result(timeout=10)
+    srv.close()
+
+
+def test_shortest_first_does_not_starve_a_large_request():
+    """Every admission of a younger, smaller request passes the large one over once; after max_bypass of them it
+    goes next although smaller requests are still queued."""
+    ex = GatedExecutor()
+    srv = Server(ex, slots=1, budget_bytes=10 ** 6, policy="sjf", max_bypass=2)
+    futs = [srv.submit(_sized("first", 1))]
+    _wait_launched(ex, 1)
+    futs.append(srv.submit(_sized("large", 1000)))
+    futs += [srv.submit(_sized("s%d" % k, 10 + k)) for k in range(4)]
+    time.sleep(0.01)
+    for k in range(1, 6):
+        ex.gates[ex.launched[k - 1]].set()
+        _wait_launched(ex, k + 1)
+    assert ex.launched[:4] == ["first", "s0", "s1", "large"], ex.launched
+    ex.gates[ex.launched[-1]].set()
+    for f in futs:
+        f.result(timeout=10)
+    srv.close()
+
+
+def test_policy_must_be_known():
+    with pytest.raises(ValueError):
+        Server(GatedExecutor(), policy="lifo")
