@@ -16,6 +16,9 @@ documented at the C definitions:
 * :func:`abuffer`  -- the exact sorted A-buffer the method approximates (visibility function of 1.2).
 * :func:`backward` -- gradient of the resolve with respect to alpha and colour (chain rule through the steps).
 * :func:`coeffs_one`, :func:`cells_one`, :func:`reconstruct`, :func:`Psi`, :func:`psi` -- the per-pixel pieces.
+
+``ref_tiny`` is a scalar pure-Python twin for tiny frames that reaches the same quantities by another route
+(cell means of the absorbance step function, then the Haar analysis); the tests compare the two.
 """
 from __future__ import annotations
 
