@@ -323,40 +323,46 @@ def test_many_tiles(orc, width, height):
     assert_close_abs(g["out"], o["out"], 1e-4, sel=sel)
 
 
-def test_glass_4k_full(orc):
+@pytest.fixture(scope="module")
+def glass_4k():
+    """The glass + particles frame at full size, generated once for the module."""
+    import paper_2201_00094_amd as wt
+    f = synth.frame_c3(seed=0, rank=3)
+    return f, wt.Fragments.from_numpy(f.pixel, f.depth, f.alpha, f.rgb)
+
+
+@pytest.mark.parametrize("dtype,rel", [("f32", 1e-5), ("f16", 2 * 2.0 ** -11 + 1e-5), ("bf16", 2 * 2.0 ** -8 + 1e-5)])
+def test_glass_4k_full(orc, glass_4k, dtype, rel):
     """The glass + particles workload at full size (3840x2160, rank 3, 2-4 glass layers with per-channel alpha plus
     Poisson(24) particles per pixel, about 224 M fragments) in the benchmark's launch configuration (bin count,
     bin scatter, render over the binned stream; two-level binning), FP32, FP16 and BF16 storage: every coefficient
     and every composite pixel against the oracle (FP16 and BF16 against the oracle at the same storage precision)."""
     import torch
     import paper_2201_00094_amd as wt
-    f = synth.frame_c3(seed=0, rank=3)
-    say("case glass 4K F", f.count)
-    fr = wt.Fragments.from_numpy(f.pixel, f.depth, f.alpha, f.rgb)
+    f, fr = glass_4k
+    say("case glass 4K F", f.count, "storage", dtype)
     sel = None
-    for dtype, rel in (("f32", 1e-5), ("f16", 2 * 2.0 ** -11 + 1e-5), ("bf16", 2 * 2.0 ** -8 + 1e-5)):
-        say("  storage", dtype)
-        spec = wt.FrameSpec(f.width, f.height, 3, 3, dtype)
-        ws = wt.Workspace(spec, f.count)
-        coeffs = spec.new_coeffs()
-        out = torch.empty((spec.pixels, 3), dtype=torch.float32, device="cuda")
-        wt.bin_count(spec, fr, ws)
-        wt.bin_scatter(spec, fr, ws)
-        wt.render_binned(spec, ws, f.bg, out, coeffs)
-        torch.cuda.synchronize()
-        assert wt.dropped_count(ws) == 0
-        o = oracle_frame(orc, f, want=("coeffs", "accum", "out"), storage="exact" if dtype == "f32" else dtype)
-        assert_coeffs(coeffs.float().cpu().double().numpy(), o["coeffs"], rel=rel, sel=sel, what=dtype + " coeffs",
-                      atol=STORAGE_ATOL[dtype])
-        if dtype == "f32":
-            err = assert_close_abs(out.cpu().double().numpy(), o["out"], 1e-4, sel=sel, what=dtype + " out")
-        else:
-            tol = storage_out_bound(orc, 3, o["coeffs"], o["accum"], 3, rel, atol=STORAGE_ATOL[dtype])
-            err, ratio = assert_within(out.cpu().double().numpy(), o["out"], tol, sel=sel, what=dtype + " out")
-            say("  %s: largest error / derived bound %.2f" % (dtype, ratio))
-        say("  %s: max |out - oracle| over all %d pixels: %.2e" % (dtype, f.pixels, err))
-        del ws, coeffs, out, o
-        torch.cuda.empty_cache()
+    spec = wt.FrameSpec(f.width, f.height, 3, 3, dtype)
+    ws = wt.Workspace(spec, f.count)
+    coeffs = spec.new_coeffs()
+    out = torch.empty((spec.pixels, 3), dtype=torch.float32, device="cuda")
+    wt.bin_count(spec, fr, ws)
+    wt.bin_scatter(spec, fr, ws)
+    wt.render_binned(spec, ws, f.bg, out, coeffs)
+    torch.cuda.synchronize()
+    assert wt.dropped_count(ws) == 0
+    o = oracle_frame(orc, f, want=("coeffs", "accum", "out"), storage="exact" if dtype == "f32" else dtype)
+    assert_coeffs(coeffs.float().cpu().double().numpy(), o["coeffs"], rel=rel, sel=sel, what=dtype + " coeffs",
+                  atol=STORAGE_ATOL[dtype])
+    if dtype == "f32":
+        err = assert_close_abs(out.cpu().double().numpy(), o["out"], 1e-4, sel=sel, what=dtype + " out")
+    else:
+        tol = storage_out_bound(orc, 3, o["coeffs"], o["accum"], 3, rel, atol=STORAGE_ATOL[dtype])
+        err, ratio = assert_within(out.cpu().double().numpy(), o["out"], tol, sel=sel, what=dtype + " out")
+        say("  %s: largest error / derived bound %.2f" % (dtype, ratio))
+    say("  %s: max |out - oracle| over all %d pixels: %.2e" % (dtype, f.pixels, err))
+    del ws, coeffs, out, o
+    torch.cuda.empty_cache()
 
 
 def test_global_binning_fallback(orc):
