@@ -12,7 +12,9 @@ The paper measures on rendered scenes (the Bistro bar, smoke and particle system
 here; the workloads below are synthetic stand-ins with the shapes, counts and value ranges of those cases.
 """
 from .frames import (Frame, REQUEST_RESOLUTIONS, frame_c1, frame_c2, frame_c3, frame_c4, frame_c5, frame_uniform,
-                     make_frame, poisson_arrivals, smoke_density, target_image, torch_frame)
+                     make_frame, poisson_arrivals, scrambled_multiplier, scrambled_stream, smoke_density,
+                     target_image, torch_frame)
 
 __all__ = ["Frame", "REQUEST_RESOLUTIONS", "frame_c1", "frame_c2", "frame_c3", "frame_c4", "frame_c5", "frame_uniform",
-           "make_frame", "poisson_arrivals", "smoke_density", "target_image", "torch_frame"]
+           "make_frame", "poisson_arrivals", "scrambled_multiplier", "scrambled_stream", "smoke_density",
+           "target_image", "torch_frame"]

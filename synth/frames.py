@@ -216,3 +216,40 @@ def torch_frame(seed, width, height, mean=24.0, rank=3, device="cuda"):
     rgb = torch.rand((F, 3), generator=g, device=device).contiguous()
     return pixel, depth, alpha, rgb
 
+
+
+def scrambled_multiplier(P):
+    """The multiplier of :func:`scrambled_stream`: the first integer at or above 0.618 P that is coprime to P, so
+    that i -> (A i + B) mod P visits every pixel once per P consecutive fragments in a scattered order."""
+    import math
+    A = max(1, int(0.6180339887 * P))
+    while math.gcd(A, P) != 1:
+        A += 1
+    return A
+
+
+def scrambled_stream(seed, width, height, count, alpha=(0.0005, 0.003), device="cuda", chunk=1 << 28):
+    """Exactly ``count`` fragments spread evenly over the frame in a scrambled order, drawn on the device for streams
+    too large to generate on the host (past 2^31 fragments). Fragment i lands on pixel (A i + B) mod P
+    (A = :func:`scrambled_multiplier`, B from the seed), so pixel p holds the fragments i_p + k P, k = 0, 1, ...,
+    with i_p = A^-1 (p - B) mod P: any pixel's fragments are gathered without a search, and the pixels with
+    i_p < count mod P hold one fragment more. Depth U[0,1), alpha U[alpha], rgb U[0,1]^3 from torch's generator on
+    the device (small alphas keep the deep per-pixel lists visible). Returns (pixel int32, depth, alpha, rgb, A, B)
+    with the tensors on ``device``."""
+    import torch
+    P = width * height
+    A = scrambled_multiplier(P)
+    B = int(seed) * 7919 % P
+    pixel = torch.empty(count, dtype=torch.int32, device=device)
+    for s in range(0, count, chunk):
+        e = min(count, s + chunk)
+        i = torch.arange(s, e, dtype=torch.int64, device=device)
+        pixel[s:e] = ((i * A + B) % P).to(torch.int32)
+        del i
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    depth = torch.rand(count, generator=g, device=device)
+    lo, hi = alpha
+    al = torch.empty(count, device=device).uniform_(float(lo), float(hi), generator=g)
+    rgb = torch.rand((count, 3), generator=g, device=device)
+    return pixel, depth, al, rgb, A, B

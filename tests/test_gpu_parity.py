@@ -381,3 +381,49 @@ def test_global_binning_fallback(orc):
     o = oracle_frame(orc, f, mask=mask, want=("out",))
     err = assert_close_abs(g["out"], o["out"], 1e-4, sel=sel)
     say("  max |out - oracle| on %d sampled pixels: %.2e" % (sel.size, err))
+
+
+def test_stream_past_2_31_fragments(orc):
+    """Maximum sizes: 2^31 + 12,345 fragments (about 1,036 per pixel: 51.5 GB of input and a 60 GB workspace) over
+    the 1920x1080 rank-3 frame in the benchmark's launch configuration, so fragment indices, record slots and
+    segment offsets run past 2^31, with a partial last chunk. No drops; signs of every stored coefficient; and
+    about 48 pixels against the oracle: the pixels of the first and last fragment, both sides of the ragged edge
+    (the pixels before it hold one fragment more) and 43 random ones, each with its whole list of fragments."""
+    import torch
+    import paper_2201_00094_amd as wt
+    W, H, F = 1920, 1080, (1 << 31) + 12345
+    P = W * H
+    say("case stream past 2^31: F", F)
+    pixel, depth, alpha, rgb, A, B = synth.scrambled_stream(5, W, H, F)
+    spec = wt.FrameSpec(W, H, 3, 1, "f32")
+    fr = wt.Fragments(pixel, depth, alpha, rgb)
+    ws = wt.Workspace(spec, F)
+    coeffs = spec.new_coeffs()
+    bg = (0.2, 0.3, 0.4)
+    out = wt.render(spec, fr, bg, ws, coeffs=coeffs)
+    torch.cuda.synchronize()
+    assert wt.dropped_count(ws) == 0
+    c = coeffs[:, 0, :]
+    assert bool((c[:, 0] >= 0).all()) and bool((c[:, 1:] <= 0).all())
+    # the pixel of fragment i is (A i + B) mod P; pixel p holds the fragments i_p + k P
+    rag = F % P
+    rng = np.random.default_rng(5)
+    firsts = np.unique(np.concatenate([[0, P - 1, rag - 1, rag, (F - 1) % P], rng.choice(P, 43, replace=False)]))
+    sel = (A * firsts + B) % P
+    dev = pixel.device
+    parts = []
+    for j, ip in enumerate(firsts):
+        idx = torch.arange(int(ip), F, P, device=dev)
+        parts.append((np.full(idx.numel(), j, np.uint32), depth[idx].cpu().numpy(), alpha[idx].cpu().numpy(),
+                      rgb[idx].cpu().numpy()))
+    n = len(parts)
+    assert sum(p[0].size for p in parts) == sum(F // P + (ip < rag) for ip in firsts)
+    mp, md, ma, mc = (np.concatenate([p[k] for p in parts]) for k in range(4))
+    o = orc.resolve(n, 1, 3, mp, md, ma, mc, bg=bg, want=("coeffs", "out"))
+    sel_t = torch.from_numpy(sel).to(dev)
+    assert_coeffs(coeffs[sel_t].cpu().double().numpy(), o["coeffs"])
+    err = assert_close_abs(out[sel_t].cpu().double().numpy(), o["out"], 1e-4)
+    say("  %d pixels with %d-%d fragments each: max |out - oracle| %.2e" %
+        (n, min(p[0].size for p in parts), max(p[0].size for p in parts), err))
+    del pixel, depth, alpha, rgb, fr, ws, coeffs, out, c
+    torch.cuda.empty_cache()
