@@ -18,8 +18,8 @@
  *   - Every call is asynchronous on the given HIP stream (0 = the null stream) and returns once the work is
  *     enqueued. The return code reports host-side validation and launch failures only.
  *   - Errors: WT_ERR_INVALID (null pointer, bad enum, zero size), WT_ERR_RANGE (size limits: rank > 10,
- *     pixel count or fragment count >= 2^32, workspace too small), WT_ERR_HIP (a HIP runtime error; the HIP
- *     error string is in wt_last_error()). Nothing is enqueued when validation fails.
+ *     pixel count >= 2^32, fragment count > WT_MAX_FRAGMENTS, workspace too small), WT_ERR_HIP (a HIP runtime
+ *     error; the HIP error string is in wt_last_error()). Nothing is enqueued when validation fails.
  *   - Device-side bad fragments are dropped, not faulted: a pixel id >= width*height, a NaN depth or a NaN
  *     alpha. Their number is read back with wt_dropped_count(). Depth is clamped to [0, 1]; alpha to
  *     [0, 1 - 2^-24].
@@ -49,6 +49,11 @@
 #include <stdint.h>
 
 #include <hip/hip_runtime_api.h>
+
+/* Largest fragment count a call takes: 2^32 - 2^20. Binned records are addressed by 32-bit indices, and a kernel's
+ * loop over a tile's records may step up to 8,192 records past its last one before it stops, so counts stop well
+ * short of 2^32 (larger counts are refused with WT_ERR_RANGE, and wt_workspace_bytes returns 0 for them). */
+#define WT_MAX_FRAGMENTS 4293918720ull
 
 #ifdef __cplusplus
 extern "C" {
@@ -102,7 +107,7 @@ typedef struct {
 } wt_frame_desc;
 
 typedef struct {
-  uint64_t count;       /* F < 2^32 */
+  uint64_t count;       /* F <= WT_MAX_FRAGMENTS */
   const uint32_t* pixel;
   const float* depth;
   const float* alpha;

@@ -15,6 +15,7 @@ WT_TIGHT_DEPTH = 1
 WT_TEMPORAL = 2
 WT_DETERMINISTIC = 4
 WT_SCRATCH_BYTES = 256 << 20  # the static device array behind wt_render_noalloc
+WT_MAX_FRAGMENTS = (1 << 32) - (1 << 20)  # the largest fragment count a call takes
 
 
 class FrameDesc(C.Structure):

@@ -61,10 +61,13 @@ wt_status check_temporal(const wt_frame_desc* d, const void* prev, const uint32_
   return WT_OK;
 }
 
+static_assert(WT_MAX_FRAGMENTS == (1ull << 32) - (1ull << 20), "fragment limit");
+
 wt_status check_frags(const wt_fragments* f) {
   if (!f) return fail(WT_ERR_INVALID, "frags is NULL");
-  if (f->count >= (1ull << 32)) return fail(WT_ERR_RANGE, "fragment count %llu is 2^32 or more",
-                                            (unsigned long long)f->count);
+  if (f->count > WT_MAX_FRAGMENTS)
+    return fail(WT_ERR_RANGE, "fragment count %llu is above WT_MAX_FRAGMENTS (2^32 - 2^20)",
+                (unsigned long long)f->count);
   if (f->count && (!f->pixel || !f->depth || !f->alpha || !f->rgb))
     return fail(WT_ERR_INVALID, "a fragment array pointer is NULL");
   return WT_OK;
@@ -125,7 +128,7 @@ int wt_abi_version(void) { return 2; }
 const char* wt_last_error(void) { return g_last_error.c_str(); }
 
 size_t wt_workspace_bytes(const wt_frame_desc* desc, uint64_t max_fragments) {
-  if (check_desc(desc) != WT_OK || max_fragments >= (1ull << 32)) return 0;
+  if (check_desc(desc) != WT_OK || max_fragments > WT_MAX_FRAGMENTS) return 0;
   // the gradient uses smaller tiles (more tile-table entries), so size for whichever layout is larger
   const size_t fwd = wt::make_layout(wt::make_geom(*desc), max_fragments).total;
   const size_t bwd = wt::make_layout(wt::make_geom(*desc, true), max_fragments).total;

@@ -51,6 +51,9 @@ def test_workspace_bytes(lib):
     assert lib.wt_workspace_bytes(C.byref(_lib.desc(16, 16, 3, channels=2)), 10) == 0
     assert lib.wt_workspace_bytes(None, 10) == 0
     assert lib.wt_workspace_bytes(C.byref(_lib.desc(16, 16, 3)), 1 << 32) == 0
+    # the fragment limit: 2^32 - 2^20 fragments are sized, one more is not
+    assert lib.wt_workspace_bytes(C.byref(_lib.desc(16, 16, 3)), _lib.WT_MAX_FRAGMENTS) >= _lib.WT_MAX_FRAGMENTS * 28
+    assert lib.wt_workspace_bytes(C.byref(_lib.desc(16, 16, 3)), _lib.WT_MAX_FRAGMENTS + 1) == 0
 
 
 def _err(lib):
@@ -67,6 +70,12 @@ def test_validation_errors_before_any_launch(lib):
     assert "NULL" in _err(lib)
     big = _lib.Fragments(1 << 32, 1, 1, 1, 1)
     assert lib.wt_bin(C.byref(d), C.byref(big), ws, 1 << 20, None) == _lib.WT_ERR_RANGE
+    over = _lib.Fragments(_lib.WT_MAX_FRAGMENTS + 1, 1, 1, 1, 1)
+    assert lib.wt_bin(C.byref(d), C.byref(over), ws, 1 << 20, None) == _lib.WT_ERR_RANGE
+    assert "WT_MAX_FRAGMENTS" in _err(lib)
+    at_limit = _lib.Fragments(_lib.WT_MAX_FRAGMENTS, 1, 1, 1, 1)
+    assert lib.wt_bin(C.byref(d), C.byref(at_limit), ws, 1 << 20, None) == _lib.WT_ERR_RANGE
+    assert "workspace" in _err(lib)  # the count passes; the 1 MiB workspace does not
     ok = _lib.Fragments(10, 8, 8, 8, 8)
     assert lib.wt_bin(C.byref(d), C.byref(ok), ws, 16, None) == _lib.WT_ERR_RANGE
     assert "workspace" in _err(lib)
@@ -158,7 +167,7 @@ def test_every_description_sizes_and_validates(lib):
     holds the binned copy, and each binning or one-pass call with a 16-byte workspace stops at validation (range or
     unsupported, never a launch)."""
     sizes = [(1, 1), (7, 5), (1920, 1080), (3840, 2160), (65535, 65537)]
-    counts = [0, 1, 1_000_000, (1 << 32) - 1]
+    counts = [0, 1, 1_000_000, _lib.WT_MAX_FRAGMENTS]
     ok = _lib.Fragments(10, 8, 8, 8, 8)
     ws = C.c_void_p(0x1000)  # never dereferenced: validation fails first
     bg = _lib.bg3((0, 0, 0))
@@ -178,7 +187,7 @@ def test_every_description_sizes_and_validates(lib):
                             continue
                         n_valid += 1
                         assert got == sorted(got) and got[0] < got[2], (rank, ch, dt, fl, w, h, got)
-                        assert got[2] >= 1_000_000 * 28 and got[3] >= ((1 << 32) - 1) * 28
+                        assert got[2] >= 1_000_000 * 28 and got[3] >= _lib.WT_MAX_FRAGMENTS * 28
                         assert st in errs, (rank, ch, dt, fl, w, h, st, _err(lib))
                         if fl == _lib.WT_TEMPORAL:
                             st = lib.wt_render_temporal_binned(C.byref(d), ws, 16, bg, None, None, None, ws, None)
@@ -204,3 +213,20 @@ def test_noalloc_refuses_frames_beyond_its_array(lib):
     n3 = _lib.Fragments(_lib.WT_SCRATCH_BYTES // 72 + 1, 8, 8, 8, 8)
     assert lib.wt_render_noalloc(C.byref(d3), C.byref(n3), _lib.bg3((0, 0, 0)), None, ok_ptr,
                                  None) == _lib.WT_ERR_RANGE
+
+
+def test_binding_constants_match_the_header():
+    """The numeric #defines of wt.h (fragment limit, scratch size, flags) are the binding's constants."""
+    with open(os.path.join(ROOT, "include", "wt.h")) as fh:
+        text = fh.read()
+    defs = dict(re.findall(r"^#define (WT_[A-Z_0-9]+) (.+)$", text, flags=re.M))
+    val = {"WT_MAX_FRAGMENTS": int(defs["WT_MAX_FRAGMENTS"].rstrip("ul")),
+           "WT_SCRATCH_BYTES": (lambda m: int(m[0]) << int(m[1]))(
+               re.fullmatch(r"\(\(size_t\)(\d+) << (\d+)\)", defs["WT_SCRATCH_BYTES"]).groups()),
+           "WT_TIGHT_DEPTH": int(defs["WT_TIGHT_DEPTH"].rstrip("u")),
+           "WT_TEMPORAL": int(defs["WT_TEMPORAL"].rstrip("u")),
+           "WT_DETERMINISTIC": int(defs["WT_DETERMINISTIC"].rstrip("u"))}
+    for name, v in val.items():
+        assert getattr(_lib, name) == v, name
+    assert _lib.WT_MAX_FRAGMENTS == (1 << 32) - (1 << 20)
+
