@@ -1,0 +1,61 @@
+"""The largest stream a call takes: WT_MAX_FRAGMENTS = 2^32 - 2^20 fragments over the 1920x1080 rank-3 frame in
+the benchmark's launch configuration (about 2,071 fragments per pixel: 103 GB of input and a 120 GB workspace), so
+the 32-bit record indices and segment offsets reach the top of their range. Pixels are checked whole against the
+oracle."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import assert_close_abs, assert_coeffs, say
+
+pytestmark = pytest.mark.gpu
+
+
+def test_stream_at_the_fragment_limit(orc):
+    """No drops; signs of every stored coefficient; the pixels of the first and last fragment, both sides of the
+    ragged edge (the pixels before it hold one fragment more) and random ones, each with its whole list of about
+    2,071 fragments, against the oracle. Skipped where the device has no room for the 224 GB this takes."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2201_00094_amd as wt
+    from paper_2201_00094_amd import _lib
+    W, H, F = 1920, 1080, _lib.WT_MAX_FRAGMENTS
+    P = W * H
+    spec = wt.FrameSpec(W, H, 3, 1, "f32")
+    need = 24 * F + wt.workspace_bytes(spec, F) + (64 + 12) * P + (8 << 30)
+    torch.cuda.empty_cache()
+    free, total = torch.cuda.mem_get_info()
+    if free < need:
+        pytest.skip("needs %.0f GB of device memory, %.0f GB free" % (need / 1e9, free / 1e9))
+    say("case stream at the fragment limit: F", F)
+    pixel, depth, alpha, rgb, A, B = synth.scrambled_stream(7, W, H, F)
+    fr = wt.Fragments(pixel, depth, alpha, rgb)
+    ws = wt.Workspace(spec, F)
+    coeffs = spec.new_coeffs()
+    bg = (0.25, 0.2, 0.15)
+    out = wt.render(spec, fr, bg, ws, coeffs=coeffs)
+    torch.cuda.synchronize()
+    assert wt.dropped_count(ws) == 0
+    c = coeffs[:, 0, :]
+    assert bool((c[:, 0] >= 0).all()) and bool((c[:, 1:] <= 0).all())
+    # the pixel of fragment i is (A i + B) mod P; pixel p holds the fragments i_p + k P
+    rag = F % P
+    rng = np.random.default_rng(7)
+    firsts = np.unique(np.concatenate([[0, P - 1, rag - 1, rag, (F - 1) % P], rng.choice(P, 27, replace=False)]))
+    sel = (A * firsts + B) % P
+    parts = []
+    for j, ip in enumerate(firsts):
+        idx = torch.arange(int(ip), F, P, device=pixel.device)
+        parts.append((np.full(idx.numel(), j, np.uint32), depth[idx].cpu().numpy(), alpha[idx].cpu().numpy(),
+                      rgb[idx].cpu().numpy()))
+    assert sum(p[0].size for p in parts) == sum(F // P + (ip < rag) for ip in firsts)
+    mp, md, ma, mc = (np.concatenate([p[k] for p in parts]) for k in range(4))
+    o = orc.resolve(len(parts), 1, 3, mp, md, ma, mc, bg=bg, want=("coeffs", "out"))
+    sel_t = torch.from_numpy(sel).to(pixel.device)
+    assert_coeffs(coeffs[sel_t].cpu().double().numpy(), o["coeffs"])
+    err = assert_close_abs(out[sel_t].cpu().double().numpy(), o["out"], 1e-4)
+    say("  %d pixels with %d-%d fragments each: max |out - oracle| %.2e" %
+        (len(parts), min(p[0].size for p in parts), max(p[0].size for p in parts), err))
+    del pixel, depth, alpha, rgb, fr, ws, coeffs, out, c
+    torch.cuda.empty_cache()
