@@ -13,8 +13,8 @@ here; the workloads below are synthetic stand-ins with the shapes, counts and va
 """
 from .frames import (Frame, REQUEST_RESOLUTIONS, frame_c1, frame_c2, frame_c3, frame_c4, frame_c5, frame_uniform,
                      make_frame, poisson_arrivals, scrambled_multiplier, scrambled_stream, smoke_density,
-                     target_image, torch_frame)
+                     sparse_stream, target_image, torch_frame)
 
 __all__ = ["Frame", "REQUEST_RESOLUTIONS", "frame_c1", "frame_c2", "frame_c3", "frame_c4", "frame_c5", "frame_uniform",
            "make_frame", "poisson_arrivals", "scrambled_multiplier", "scrambled_stream", "smoke_density",
-           "target_image", "torch_frame"]
+           "sparse_stream", "target_image", "torch_frame"]

@@ -253,3 +253,21 @@ def scrambled_stream(seed, width, height, count, alpha=(0.0005, 0.003), device="
     al = torch.empty(count, device=device).uniform_(float(lo), float(hi), generator=g)
     rgb = torch.rand((count, 3), generator=g, device=device)
     return pixel, depth, al, rgb, A, B
+
+
+def sparse_stream(seed, width, height, pixels, mean=3.0):
+    """Fragments on the listed pixels only, 1 + Poisson(mean) each, in shuffled order, with the c1 distributions
+    (depth (0.05, 1], alpha U[0.05, 0.6], rgb U[0,1]^3): for frames too large to describe pixel by pixel (up to
+    2^32 - 1 pixels). Returns (pixel uint32, depth, alpha, rgb) NumPy arrays."""
+    rng = np.random.default_rng(seed)
+    pixels = np.asarray(pixels, dtype=np.int64).reshape(-1)
+    assert pixels.size == 0 or (pixels.min() >= 0 and pixels.max() < width * height)
+    counts = 1 + rng.poisson(mean, pixels.size)
+    pixel = np.repeat(pixels, counts)
+    F = pixel.size
+    perm = rng.permutation(F)
+    pixel = np.ascontiguousarray(pixel[perm].astype(np.uint32))
+    depth = _depth_c1(rng, F)
+    alpha = _u(rng, 0.05, 0.6, F)
+    rgb = _rgb_uniform(rng, F)
+    return pixel, depth, alpha, rgb

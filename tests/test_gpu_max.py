@@ -1,7 +1,7 @@
-"""The largest stream a call takes: WT_MAX_FRAGMENTS = 2^32 - 2^20 fragments over the 1920x1080 rank-3 frame in
+"""The largest inputs a call takes. WT_MAX_FRAGMENTS = 2^32 - 2^20 fragments over the 1920x1080 rank-3 frame in
 the benchmark's launch configuration (about 2,071 fragments per pixel: 103 GB of input and a 120 GB workspace), so
-the 32-bit record indices and segment offsets reach the top of their range. Pixels are checked whole against the
-oracle."""
+the 32-bit record indices and segment offsets reach the top of their range; and the largest frame, 65535 x 65537 =
+2^32 - 1 pixels. Pixels are checked whole against the oracle."""
 import numpy as np
 import pytest
 
@@ -59,3 +59,53 @@ def test_stream_at_the_fragment_limit(orc):
         (len(parts), min(p[0].size for p in parts), max(p[0].size for p in parts), err))
     del pixel, depth, alpha, rgb, fr, ws, coeffs, out, c
     torch.cuda.empty_cache()
+
+
+def test_frame_at_the_pixel_limit(orc):
+    """65535 x 65537 = 2^32 - 1 pixels at rank 0 (4.2 M tiles, binned with one global atomic per fragment) with
+    fragments on about 2,000 pixels, among them the first and the last pixel, the ends of the first and last rows
+    and both sides of 2^31: those pixels against the oracle, and every other pixel of the frame shows the
+    background over zero coefficients. Skipped where the device has no room for the 103 GB this takes."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2201_00094_amd as wt
+    W, H = 65535, 65537
+    P = W * H
+    spec = wt.FrameSpec(W, H, 0, 1, "f32")
+    torch.cuda.empty_cache()
+    free, total = torch.cuda.mem_get_info()
+    need = (8 + 12 + 3) * P + (4 << 30)
+    if free < need:
+        pytest.skip("needs %.0f GB of device memory, %.0f GB free" % (need / 1e9, free / 1e9))
+    rng = np.random.default_rng(11)
+    special = [0, 1, W - 1, W, (1 << 31) - 1, 1 << 31, (1 << 31) + 1, P - W, P - 2, P - 1]
+    pix = np.unique(np.concatenate([special, rng.integers(0, P, 2000)]))
+    pixel, depth, alpha, rgb = synth.sparse_stream(11, W, H, pix)
+    say("case frame at the pixel limit: P", P, "F", pixel.size)
+    fr = wt.Fragments.from_numpy(pixel, depth, alpha, rgb)
+    ws = wt.Workspace(spec, pixel.size)
+    coeffs = spec.new_coeffs()
+    bg = (0.3, 0.5, 0.7)
+    out = wt.render(spec, fr, bg, ws, coeffs=coeffs)
+    torch.cuda.synchronize()
+    assert wt.dropped_count(ws) == 0
+    sel_t = torch.from_numpy(pix.astype(np.int64)).cuda()
+    go = out[sel_t].cpu().double().numpy()
+    gc = coeffs[sel_t].cpu().double().numpy()
+    # the oracle over the same fragments with the listed pixels renumbered 0..n-1
+    o = orc.resolve(pix.size, 1, 0, np.searchsorted(pix, pixel).astype(np.uint32), depth, alpha, rgb, bg=bg,
+                    want=("coeffs", "out"))
+    assert_coeffs(gc, o["coeffs"])
+    err = assert_close_abs(go, o["out"], 1e-4)
+    # every other pixel: the background, over zero coefficients
+    bg_t = torch.tensor(bg, dtype=torch.float32, device="cuda")
+    out[sel_t] = bg_t
+    coeffs[sel_t] = 0
+    assert bool((out == bg_t).all()), "a pixel without fragments does not show the background"
+    assert bool((coeffs == 0).all()), "a pixel without fragments has a non-zero coefficient"
+    say("  %d pixels against the oracle: max |out - oracle| %.2e; the other %d show the background" %
+        (pix.size, err, P - pix.size))
+    del fr, ws, coeffs, out
+    torch.cuda.empty_cache()
+
