@@ -228,14 +228,14 @@ def scrambled_multiplier(P):
     return A
 
 
-def scrambled_stream(seed, width, height, count, alpha=(0.0005, 0.003), device="cuda", chunk=1 << 28):
+def scrambled_stream(seed, width, height, count, alpha=(0.0005, 0.003), device="cuda", chunk=1 << 28, channels=1):
     """Exactly ``count`` fragments spread evenly over the frame in a scrambled order, drawn on the device for streams
     too large to generate on the host (past 2^31 fragments). Fragment i lands on pixel (A i + B) mod P
     (A = :func:`scrambled_multiplier`, B from the seed), so pixel p holds the fragments i_p + k P, k = 0, 1, ...,
     with i_p = A^-1 (p - B) mod P: any pixel's fragments are gathered without a search, and the pixels with
-    i_p < count mod P hold one fragment more. Depth U[0,1), alpha U[alpha], rgb U[0,1]^3 from torch's generator on
-    the device (small alphas keep the deep per-pixel lists visible). Returns (pixel int32, depth, alpha, rgb, A, B)
-    with the tensors on ``device``."""
+    i_p < count mod P hold one fragment more. Depth U[0,1), alpha U[alpha] ([count] or, for three channels,
+    [count, 3]), rgb U[0,1]^3 from torch's generator on the device (small alphas keep the deep per-pixel lists
+    visible). Returns (pixel int32, depth, alpha, rgb, A, B) with the tensors on ``device``."""
     import torch
     P = width * height
     A = scrambled_multiplier(P)
@@ -250,7 +250,7 @@ def scrambled_stream(seed, width, height, count, alpha=(0.0005, 0.003), device="
     g.manual_seed(int(seed))
     depth = torch.rand(count, generator=g, device=device)
     lo, hi = alpha
-    al = torch.empty(count, device=device).uniform_(float(lo), float(hi), generator=g)
+    al = torch.empty((count, 3) if channels == 3 else count, device=device).uniform_(float(lo), float(hi), generator=g)
     rgb = torch.rand((count, 3), generator=g, device=device)
     return pixel, depth, al, rgb, A, B
 

@@ -31,3 +31,7 @@ def test_scrambled_stream_places_every_pixel_where_its_closed_form_says():
         # the same seed draws the same stream
         again = synth.scrambled_stream(3, w, h, count, device="cpu", chunk=1 << 18)
         assert torch.equal(again[0], pixel) and torch.equal(again[1], depth) and torch.equal(again[3], rgb)
+    three = synth.scrambled_stream(3, 48, 30, 5000, device="cpu", channels=3)
+    assert tuple(three[2].shape) == (5000, 3) and torch.equal(three[0], synth.scrambled_stream(3, 48, 30, 5000,
+                                                                                             device="cpu")[0])
+
