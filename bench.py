@@ -660,17 +660,21 @@ def run_serve(args):
         torch.cuda.synchronize()
         srv = Server(ex, slots=args.slots, budget_bytes=int(args.budget_gb * (1 << 30)), policy=args.policy)
         futs = []
+        late = np.zeros(len(trace))
         t0 = time.perf_counter()
         for i, r in enumerate(trace):
             now = time.perf_counter() - t0
             if r["t"] > now:
                 time.sleep(r["t"] - now)
+            late[i] = time.perf_counter() - t0 - r["t"]  # how far the submission fell behind the trace
             fr = pool[(r["width"], r["height"], r["seed"] % 2)]
             futs.append(srv.submit(FrameRequest(r["width"], r["height"], r["rank"], fr, dtype=r["dtype"],
                                                 bg=(0.2, 0.2, 0.2), tag=i, out=outs[i])))
         results = [fu.result(timeout=600) for fu in futs]
         srv.close()
         stats = srv.stats.summary()
+        # latency from the trace's arrival times (the server's own figures start at submit)
+        from_arrival = np.array([(res.t_done - t0 - r["t"]) * 1e3 for res, r in zip(results, trace)])
         # every request against the same frame rendered alone
         worst = 0.0
         alone_ws = {}
@@ -690,9 +694,15 @@ def run_serve(args):
                       "queued": stats["queued"], "wait_p50_ms": stats["wait_p50_ms"],
                       "wait_p99_ms": stats["wait_p99_ms"], "admitted": stats["completed"],
                       "rejected": stats["rejected"], "max_inflight": stats["max_inflight"],
-                      "max_gb_inflight": stats["max_bytes_inflight"] / (1 << 30), "solo_vs_mix_max_abs": worst})
-        print("serve: load %.2f p50 %.2f ms p99 %.2f ms %.3g fragments/s" % (load, stats["p50_ms"], stats["p99_ms"],
-                                                                          stats["fragments_per_s"]),
+                      "max_gb_inflight": stats["max_bytes_inflight"] / (1 << 30), "solo_vs_mix_max_abs": worst,
+                      "arrival_p50_ms": float(np.percentile(from_arrival, 50)),
+                      "arrival_p99_ms": float(np.percentile(from_arrival, 99)),
+                      "submit_late_p99_ms": float(np.percentile(late, 99) * 1e3),
+                      "submit_late_max_ms": float(late.max() * 1e3)})
+        print("serve: load %.2f p50 %.2f ms p99 %.2f ms %.3g fragments/s; from arrival p50 %.2f p99 %.2f ms, "
+              "submissions late by %.2f ms at p99" % (load, stats["p50_ms"], stats["p99_ms"], stats["fragments_per_s"],
+                                                      sweep[-1]["arrival_p50_ms"], sweep[-1]["arrival_p99_ms"],
+                                                      sweep[-1]["submit_late_p99_ms"]),
               file=sys.stderr, flush=True)
     head = sweep[min(1, len(sweep) - 1)]
     line = {"metric": "served frames: p50/p99 latency (arrival to completion) and fragments/s", "mode": "serve",

@@ -2,8 +2,9 @@
 
 Frames of different sizes, ranks and coefficient storage types arrive as requests. The scheduler admits a request
 as soon as an execution slot is free and its HBM footprint fits the remaining budget, launches it on that slot's
-HIP stream, and keeps polling the device: requests that arrive while others run are admitted as slots and memory
-free up, and their work overlaps on the GPU. Per-slot buffers (workspace and coefficient array) stay resident and
+HIP stream, and learns of completions by polling the executor (or, for an executor that can block on a
+request's completion, from one waiting thread per slot that wakes the scheduler): requests that arrive while others
+run are admitted as slots and memory free up, and their work overlaps on the GPU. Per-slot buffers (workspace and coefficient array) stay resident and
 are reused across requests; the budget counts them as well as the requests in flight. Latency is measured from
 arrival (submit) to the moment the completion event is observed.
 
@@ -12,13 +13,15 @@ A queued request can be cancelled (``Future.cancel()``, until it is admitted) or
 Work already launched on the GPU runs to completion.
 
 The scheduler is independent of the device: it drives an executor with ``footprint``, ``launch``, ``done`` and
-``finish``, and optionally ``prepare`` (called on the submitting thread; its token is passed to ``launch``) and
+``finish``, and optionally ``prepare`` (called on the submitting thread; its token is passed to ``launch``),
+``wait`` (blocks until a launched request's work is complete; without it the scheduler polls ``done``) and
 ``growth`` / ``resident_bytes`` / ``trim`` (resident per-slot buffers). :class:`GpuExecutor` runs the library;
 tests drive the scheduler with CPU executors.
 """
 from __future__ import annotations
 
 import collections
+import queue
 import threading
 import time
 from concurrent.futures import Future
@@ -148,6 +151,12 @@ class Server:
         self._prep = hasattr(executor, "prepare")
         self._cv = threading.Condition()
         self._stop = False
+        # an executor that can block on a request's completion gets one waiting thread per slot, which wakes the
+        # scheduler when the request it waits for is complete; otherwise the scheduler polls every poll_interval
+        self._blocking = callable(getattr(executor, "wait", None))
+        self._wq = [queue.SimpleQueue() for _ in range(self.slots)] if self._blocking else []
+        for k, q in enumerate(self._wq):
+            threading.Thread(target=self._wait_loop, args=(q,), name="wt-serve-wait-%d" % k, daemon=True).start()
         self._thread = threading.Thread(target=self._loop, name="wt-serve", daemon=True)
         self._thread.start()
 
@@ -258,6 +267,8 @@ class Server:
             p.fut.set_exception(e)
             return
         self._running.append(_Running(p, slot, handle, t))
+        if self._blocking:
+            self._wq[slot].put(handle)
         self.stats.max_inflight = max(self.stats.max_inflight, len(self._running))
         self.stats.max_bytes_inflight = max(self.stats.max_bytes_inflight, self._held())
         for q in list(self._queue)[:i]:
@@ -322,18 +333,49 @@ class Server:
             r.pend.fut.set_result(res)
         self._running = still
 
-    def _loop(self):
+    def _wait_loop(self, q):
         while True:
+            handle = q.get()
+            if handle is None:
+                return
+            try:
+                self.ex.wait(handle)
+            except Exception:  # finish() reports the failure on the scheduler thread
+                pass
             with self._cv:
-                if self._stop and not self._queue and not self._running:
-                    return
-                self._complete_locked()
-                self._admit_locked()
-                idle = not self._running and not self._queue
-                if idle and not self._stop:
-                    self._cv.wait(timeout=0.05)
-                    continue
-            time.sleep(self.poll_interval)
+                self._cv.notify_all()
+
+    def _wake_in(self) -> float:
+        """How long the scheduler may sleep when a waiting thread, a submission or close will wake it: until the
+        nearest admission deadline of a queued request, and briefly while requests are queued (to count client
+        cancellations)."""
+        t = 0.005 if self._queue else 0.05
+        now = self.clock()
+        for p in self._queue:
+            if p.req.timeout is not None:
+                t = min(t, max(0.0, p.t_submit + p.req.timeout - now) + 1e-4)
+        return t
+
+    def _loop(self):
+        try:
+            while True:
+                with self._cv:
+                    if self._stop and not self._queue and not self._running:
+                        return
+                    self._complete_locked()
+                    self._admit_locked()
+                    idle = not self._running and not self._queue
+                    if self._blocking:
+                        if not (idle and self._stop):
+                            self._cv.wait(timeout=self._wake_in())
+                        continue
+                    if idle and not self._stop:
+                        self._cv.wait(timeout=0.05)
+                        continue
+                time.sleep(self.poll_interval)
+        finally:
+            for q in self._wq:
+                q.put(None)
 
 
 def _slot_bytes(spec, count):
@@ -365,7 +407,12 @@ class GpuExecutor:
     current stream and records an event there; the slot stream waits for that event before reading the fragments,
     so inputs still being produced on the client's stream are complete. The fragment and result tensors are
     marked as used by the slot stream (``record_stream``), so the caching allocator does not hand their memory to
-    other work before the slot's kernels are done with it, whichever stream frees them."""
+    other work before the slot's kernels are done with it, whichever stream frees them.
+
+    Completion is polled (``done``); the executor has no ``wait``. Threads blocked in ``hipEventSynchronize`` on
+    the slots' completion events (through torch or through ctypes with the interpreter lock released) held up the
+    client's submissions, whose event records waited behind them: at 0.8 of the solo capacity submissions fell
+    up to 85 ms behind the arrival trace and the median latency from arrival rose from 7 to 23 ms."""
 
     def __init__(self, slots: int = 3, device="cuda"):
         import torch
@@ -475,6 +522,7 @@ class GpuExecutor:
 
     def done(self, handle) -> bool:
         return handle[0].query()
+
 
     def finish(self, handle) -> FrameResult:
         ev, out, kept = handle

@@ -1,5 +1,6 @@
 """Scheduler of the serving loop, driven on the CPU by an executor that runs the FP64 oracle on worker threads.
 The GPU path of the same scheduler is tested in test_gpu_serve.py."""
+import concurrent.futures
 import threading
 import time
 from concurrent.futures import ThreadPoolExecutor
@@ -381,3 +382,78 @@ def test_shortest_first_does_not_starve_a_large_request():
 def test_policy_must_be_known():
     with pytest.raises(ValueError):
         Server(GatedExecutor(), policy="lifo")
+
+
+# -- executors that can block on a completion: the scheduler is woken by its per-slot waiting threads ---------------
+NEVER_POLLS = 30.0  # a poll interval no test here could wait out: progress must come from the waiting threads
+
+
+class BlockingOracleExecutor(OracleExecutor):
+    def wait(self, h):
+        concurrent.futures.wait([h])
+
+
+class BlockingGatedExecutor(GatedExecutor):
+    def wait(self, h):
+        h.wait()
+
+
+def test_blocking_executor_completes_every_request_without_polling(orc):
+    ex = BlockingOracleExecutor(orc)
+    srv = Server(ex, slots=3, budget_bytes=10 ** 9, poll_interval=NEVER_POLLS)
+    reqs = [_req(s, 8 + s, 5 + (s % 3), tag=s) for s in range(12)]
+    t0 = time.perf_counter()
+    futs = [srv.submit(r) for r in reqs]
+    res = [f.result(timeout=20) for f in futs]
+    assert time.perf_counter() - t0 < 20
+    srv.close()
+    for r, q in zip(res, reqs):
+        assert r.tag == q.tag
+        alone = orc.resolve(q.width, q.height, q.rank, q.frags.pixel, q.frags.depth, q.frags.alpha, q.frags.rgb,
+                            bg=q.bg, want=("out",))["out"]
+        np.testing.assert_array_equal(r.out, alone)
+        assert r.t_submit <= r.t_admit <= r.t_done
+    s = srv.stats.summary()
+    assert s["completed"] == 12 and s["max_inflight"] <= 3 and ex.max_active <= 3
+
+
+def test_blocking_executor_admits_the_next_request_when_one_completes():
+    """One slot, shortest first: each release of the running request's gate wakes the scheduler, which launches the
+    next request at once (well within a second, against a poll interval of 30 s)."""
+    ex = BlockingGatedExecutor()
+    srv = Server(ex, slots=1, budget_bytes=10 ** 6, policy="sjf", poll_interval=NEVER_POLLS)
+    futs = [srv.submit(_sized("first", 100))]
+    _wait_launched(ex, 1, timeout=2.0)
+    for tag, n in (("big", 900), ("small", 10), ("mid", 500)):
+        futs.append(srv.submit(_sized(tag, n)))
+    time.sleep(0.01)
+    for k, expect in enumerate(("small", "mid", "big"), start=1):
+        t0 = time.perf_counter()
+        ex.gates[ex.launched[k - 1]].set()
+        _wait_launched(ex, k + 1, timeout=2.0)
+        assert ex.launched[k] == expect, ex.launched
+        assert time.perf_counter() - t0 < 1.0
+    ex.gates[ex.launched[-1]].set()
+    for f in futs:
+        f.result(timeout=5)
+    srv.close()
+    assert srv.stats.completed == 4
+
+
+def test_blocking_executor_keeps_admission_deadlines():
+    from paper_2201_00094_amd.serve import RequestTimeout
+    ex = BlockingGatedExecutor()
+    srv = Server(ex, slots=1, budget_bytes=10 ** 6, poll_interval=NEVER_POLLS)
+    f_run = srv.submit(_sized("running", 10))
+    _wait_launched(ex, 1, timeout=2.0)
+    late = _sized("late", 10)
+    late.timeout = 0.05
+    t0 = time.perf_counter()
+    f_late = srv.submit(late)
+    with pytest.raises(RequestTimeout):
+        f_late.result(timeout=5)
+    assert time.perf_counter() - t0 < 1.0
+    ex.gates["running"].set()
+    f_run.result(timeout=5)
+    srv.close()
+    assert srv.stats.timed_out == 1 and srv.stats.completed == 1 and ex.launched == ["running"]
