@@ -3,10 +3,11 @@
 Frames of different sizes, ranks and coefficient storage types arrive as requests. The scheduler admits a request
 as soon as an execution slot is free and its HBM footprint fits the remaining budget, launches it on that slot's
 HIP stream, and learns of completions by polling the executor (or, for an executor that can block on a
-request's completion, from one waiting thread per slot that wakes the scheduler): requests that arrive while others
-run are admitted as slots and memory free up, and their work overlaps on the GPU. Per-slot buffers (workspace and coefficient array) stay resident and
-are reused across requests; the budget counts them as well as the requests in flight. Latency is measured from
-arrival (submit) to the moment the completion event is observed.
+request's completion, from one waiting thread per slot that wakes the scheduler): requests that arrive while
+others run are admitted as slots and memory free up, and their work overlaps on the GPU. Per-slot buffers
+(workspace and coefficient array) stay resident and are reused across requests; the budget counts them as well
+as the requests in flight. Latency is measured from arrival (submit) to the moment the completion event is
+observed.
 
 A queued request can be cancelled (``Future.cancel()``, until it is admitted) or given an admission deadline
 (``FrameRequest.timeout``: seconds from submit; a request still queued then fails with :class:`RequestTimeout`).
@@ -522,7 +523,6 @@ class GpuExecutor:
 
     def done(self, handle) -> bool:
         return handle[0].query()
-
 
     def finish(self, handle) -> FrameResult:
         ev, out, kept = handle
